@@ -1,0 +1,234 @@
+"""Seeded synthetic workloads for the QCL trajectory ensemble.
+
+This module only *defines inputs*: model parameters of linear-vibronic
+harmonic (LVC) Hamiltonians, initial-state descriptors and run shapes.  It
+contains none of the method's arithmetic (no sampling, no eigen-solves, no
+propagation), and it is shared by the FP64 oracle, the HIP path, the tests
+and the benchmark, which all consume the *numbers* it produces.
+
+Model family (Sec. II.A, Eq. 1 symbols R, P, M; Sec. II.C models):
+
+    H = sum_j p_j^2/(2 m_j) + sum_j m_j w_j^2 q_j^2 / 2 + V(q),
+    V(q) = V0 + sum_j q_j K_j           (V0, K_j real symmetric N x N)
+
+Workloads (sizes from the headline configurations; parameters of the
+paper's 3-D spin-boson model live in its cited references and are replaced
+by an Ohmic discretisation here; the pyrazine-like model uses the
+vibronic parameters stated for the conical-intersection workload):
+
+* ``spin_boson_1mode``  1 mode, 2 states, reduced units.
+* ``spin_boson_ohmic``  3 modes discretising an Ohmic density, 2 states.
+* ``pyrazine_ci``       2-state 3-mode conical-intersection model (eV, fs).
+* ``random_lvc``        N-state harmonic models drawn from a seed (batched
+                        and served workloads).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+HBAR_EV_FS = 0.6582119569  # hbar in eV*fs (CODATA 2018)
+
+INIT_DIABATIC = 0
+INIT_ADIABATIC = 1
+
+
+@dataclasses.dataclass
+class LVCModel:
+    """Numbers of one LVC model.  Arrays are float64, C-contiguous."""
+
+    name: str
+    mass: np.ndarray   # [M]
+    omega: np.ndarray  # [M]
+    v0: np.ndarray     # [N, N] symmetric
+    k: np.ndarray      # [M, N, N] each symmetric
+    hbar: float = 1.0
+    time_unit_fs: Optional[float] = None  # fs per internal time unit (eV models)
+
+    def __post_init__(self):
+        self.mass = np.ascontiguousarray(self.mass, dtype=np.float64)
+        self.omega = np.ascontiguousarray(self.omega, dtype=np.float64)
+        self.v0 = np.ascontiguousarray(self.v0, dtype=np.float64)
+        self.k = np.ascontiguousarray(self.k, dtype=np.float64)
+
+    @property
+    def n_states(self) -> int:
+        return int(self.v0.shape[0])
+
+    @property
+    def n_modes(self) -> int:
+        return int(self.mass.shape[0])
+
+
+@dataclasses.dataclass
+class InitSpec:
+    """Initial state: thermal Wigner (q, p) centred on q0, electronic state
+    ``state`` in the diabatic (default) or adiabatic basis."""
+
+    kT: float
+    q0: np.ndarray
+    state: int = 0
+    basis: int = INIT_DIABATIC
+
+    def __post_init__(self):
+        self.q0 = np.ascontiguousarray(self.q0, dtype=np.float64)
+
+
+@dataclasses.dataclass
+class RunSpec:
+    n_traj: int
+    n_steps: int
+    dt: float
+    cadence: int
+    seed: int
+
+    @property
+    def n_out(self) -> int:
+        return self.n_steps // self.cadence + 1
+
+
+@dataclasses.dataclass
+class Workload:
+    model: LVCModel
+    init: InitSpec
+    run: RunSpec
+
+
+def _z_diag(n: int) -> np.ndarray:
+    """Per-state bath coupling pattern diag(z_k), z_k = 1 - 2k/(N-1):
+    (1,-1) for N=2, (1,0,-1) for N=3, (1,1/3,-1/3,-1) for N=4."""
+    return np.diag([1.0 - 2.0 * kk / (n - 1) for kk in range(n)])
+
+
+def ohmic_modes(n_modes: int, omega_c: float = 1.0, xi: float = 0.1):
+    """Discretised Ohmic density J(w) = (pi/2) xi w exp(-w/w_c):
+    w_j = -w_c ln(1 - j/(M+1)), c_j = w_j sqrt(xi w_c/(M+1)), j = 1..M."""
+    j = np.arange(1, n_modes + 1, dtype=np.float64)
+    w = -omega_c * np.log(1.0 - j / (n_modes + 1))
+    c = w * math.sqrt(xi * omega_c / (n_modes + 1))
+    return w, c
+
+
+def state1_minimum(model: LVCModel) -> np.ndarray:
+    """Minimum of the first diabatic surface: q0_j = -(K_j)_00/(m_j w_j^2)."""
+    return -model.k[:, 0, 0] / (model.mass * model.omega ** 2)
+
+
+# --------------------------------------------------------------------------
+# Named workloads
+# --------------------------------------------------------------------------
+
+def spin_boson_1mode(n_traj: int = 10_000, n_steps: int = 200, dt: float = 0.05,
+                     cadence: int = 10, seed: int = 0) -> Workload:
+    eps, delta, g = 0.5, 0.2, 0.5
+    model = LVCModel(
+        name="spin_boson_1mode",
+        mass=[1.0], omega=[1.0],
+        v0=[[eps, delta], [delta, -eps]],
+        k=[[[g, 0.0], [0.0, -g]]],
+    )
+    init = InitSpec(kT=0.5, q0=state1_minimum(model), state=0)
+    return Workload(model, init, RunSpec(n_traj, n_steps, dt, cadence, seed))
+
+
+def spin_boson_ohmic(kT: float = 0.2, n_traj: int = 1_000_000, n_steps: int = 2000,
+                     dt: float = 0.02, cadence: int = 10, seed: Optional[int] = None,
+                     n_modes: int = 3) -> Workload:
+    w, c = ohmic_modes(n_modes, 1.0, 0.1)
+    eps, delta = 0.0, 0.5
+    k = np.stack([cj * _z_diag(2) for cj in c])
+    model = LVCModel(
+        name=f"spin_boson_ohmic_m{n_modes}",
+        mass=np.ones(n_modes), omega=w,
+        v0=[[eps, delta], [delta, -eps]], k=k,
+    )
+    init = InitSpec(kT=kT, q0=state1_minimum(model), state=0)
+    if seed is None:
+        seed = 1 if kT <= 0.5 else 2
+    return Workload(model, init, RunSpec(n_traj, n_steps, dt, cadence, seed))
+
+
+def pyrazine_ci(n_traj: int = 10_000_000, n_steps: int = 1000, dt_fs: float = 0.5,
+                cadence: int = 10, seed: int = 3) -> Workload:
+    """Two-state three-mode S2/S1 conical-intersection model in dimensionless
+    normal coordinates (m_j = 1/w_j so that H_j = w_j (p^2 + q^2)/2), energies
+    in eV, hbar = 1 internally, one time unit = hbar/eV = 0.6582 fs."""
+    om = np.array([0.126, 0.074, 0.118])  # nu1, nu6a (tuning), nu10a (coupling)
+    k = np.zeros((3, 2, 2))
+    k[0] = np.diag([0.037, -0.254])
+    k[1] = np.diag([-0.105, 0.149])
+    k[2] = [[0.0, 0.262], [0.262, 0.0]]
+    model = LVCModel(
+        name="pyrazine_ci", mass=1.0 / om, omega=om,
+        v0=np.diag([-0.46, 0.46]), k=k, hbar=1.0, time_unit_fs=HBAR_EV_FS,
+    )
+    init = InitSpec(kT=0.0, q0=np.zeros(3), state=1)  # vertical excitation, upper diabatic state
+    return Workload(model, init, RunSpec(n_traj, n_steps, dt_fs / HBAR_EV_FS, cadence, seed))
+
+
+def zero_coupling(n_traj: int = 2000, n_steps: int = 200, dt: float = 0.05,
+                  cadence: int = 10, seed: int = 11) -> Workload:
+    """Diagonal V(q) with well-separated surfaces: no nonadiabatic coupling."""
+    model = LVCModel(
+        name="zero_coupling", mass=[1.0, 2.0], omega=[1.0, 0.7],
+        v0=np.diag([-1.0, 1.0]),
+        k=[np.diag([0.2, -0.1]), np.diag([-0.15, 0.05])],
+    )
+    init = InitSpec(kT=0.3, q0=np.zeros(2), state=0)
+    return Workload(model, init, RunSpec(n_traj, n_steps, dt, cadence, seed))
+
+
+def uncoupled_harmonic(n_traj: int = 1000, n_steps: int = 300, dt: float = 0.05,
+                       cadence: int = 10, seed: int = 12) -> Workload:
+    """K_j = 0: every surface is the bare harmonic well."""
+    model = LVCModel(
+        name="uncoupled_harmonic", mass=[1.0, 0.5, 3.0], omega=[1.0, 1.7, 0.4],
+        v0=[[0.3, 0.1], [0.1, -0.3]], k=np.zeros((3, 2, 2)),
+    )
+    init = InitSpec(kT=0.8, q0=np.array([0.5, -0.2, 1.0]), state=0)
+    return Workload(model, init, RunSpec(n_traj, n_steps, dt, cadence, seed))
+
+
+def random_lvc(index: int, key: int = 4, n_modes: Optional[int] = None,
+               n_states: Optional[int] = None, n_traj: Optional[int] = None,
+               n_steps: Optional[int] = None, max_modes: int = 64,
+               traj_range=(1e4, 1e6), steps_range=(500, 4000),
+               dt: float = 0.05, cadence: int = 50) -> Workload:
+    """One N-state harmonic model drawn from (key, index): modes U{1..max},
+    states U{2..4}, diabatic biases and couplings U[0, 0.5], kT log-U[0.1, 2],
+    trajectories log-U over ``traj_range``, steps U over ``steps_range``.
+    K_j = c_j diag(z_k) with the Ohmic c_j (xi = 0.1, w_c = 1)."""
+    rng = np.random.Generator(np.random.Philox(key=[key, index]))
+    M = int(rng.integers(1, max_modes + 1)) if n_modes is None else int(n_modes)
+    N = int(rng.integers(2, 5)) if n_states is None else int(n_states)
+    bias = rng.uniform(0.0, 0.5, size=N)
+    coup = rng.uniform(0.0, 0.5, size=(N, N))
+    kT = float(math.exp(rng.uniform(math.log(0.1), math.log(2.0))))
+    T = int(round(math.exp(rng.uniform(math.log(traj_range[0]), math.log(traj_range[1]))))) \
+        if n_traj is None else int(n_traj)
+    S = int(rng.integers(steps_range[0], steps_range[1] + 1)) if n_steps is None else int(n_steps)
+    S = max(cadence, (S // cadence) * cadence)
+    v0 = np.triu(coup, 1)
+    v0 = v0 + v0.T + np.diag(bias - bias.mean())
+    w, c = ohmic_modes(M, 1.0, 0.1)
+    k = np.stack([cj * _z_diag(N) for cj in c])
+    model = LVCModel(name=f"random_lvc_{key}_{index}", mass=np.ones(M), omega=w, v0=v0, k=k)
+    init = InitSpec(kT=kT, q0=state1_minimum(model), state=0)
+    seed = (key << 32) | (index & 0xFFFFFFFF)
+    return Workload(model, init, RunSpec(T, S, dt, cadence, seed))
+
+
+def batched_instances(n_instances: int = 256, key: int = 4, **kw) -> List[Workload]:
+    return [random_lvc(i, key=key, **kw) for i in range(n_instances)]
+
+
+NAMED = {
+    "spin_boson_1mode": spin_boson_1mode,
+    "spin_boson_ohmic": spin_boson_ohmic,
+    "pyrazine_ci": pyrazine_ci,
+    "zero_coupling": zero_coupling,
+    "uncoupled_harmonic": uncoupled_harmonic,
+}
