@@ -1,0 +1,181 @@
+"""Throughput of the QCL walker-ensemble hot path on one MI355X.
+
+One benchmark step = one pass of the whole path over one ensemble:
+qcl_sample_initial + qcl_propagate (all time steps) + qcl_reduce_observables
+for the two-state three-mode conical-intersection model (pyrazine-like
+S2/S1, 1e7 walkers, 1000 steps of 0.5 fs, bins every 10 steps).  Inputs are
+synthetic and seeded; the ensemble lives in HBM before timing starts.
+
+value = walkers * time steps / wall time of the step, in trajectory-steps/s,
+for the headline precision (binary32 propagation with binary64 phase,
+weights and sums).  The plain binary64 path is timed the same way and
+reported beside it, with the largest population difference between the
+two.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--prec fp32|fp64] [--n-traj T]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X published dense vector peaks
+
+
+def flops_per_traj_step(n_modes: int) -> int:
+    """Algorithmic floating-point work of one two-state walker step (FMA = 2):
+    velocity and coupling contractions 5M, two mean forces 14M, two kicks 4M,
+    drift 3M, coupling coordinates 4M (30M per step), plus 43 for the
+    nonadiabatic coupling, the transition weights, the closed-form eigen-solve,
+    the frame alignment and the phase."""
+    return 30 * n_modes + 43
+
+
+def time_path(P, torch, model, wl, prec, n_traj, steps, warmup):
+    r = wl.run
+    ens = P.Ensemble(model, n_traj, prec)
+    part = P.Partials(model, n_traj, r.n_out)
+    out = torch.empty((r.n_out, 2, 2, 2, 4), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+
+    def one(i=None):
+        P.qcl_sample_initial(model, wl.init, r.seed, ens, part, stream)
+        if i is not None:
+            ev[i][0].record(stream)
+        P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part, 0, stream)
+        if i is not None:
+            ev[i][1].record(stream)
+        P.qcl_reduce_observables(model, part, n_traj, out, stream)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        one(i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    ms_prop = sum(a.elapsed_time(b) for a, b in ev) / steps
+    res = out.cpu().numpy()
+    del ens, part
+    return ms_step, ms_prop, res
+
+
+def cpu_baseline(wl, target_s: float):
+    """The FP64 oracle on the host cores, on a bounded slice of the same
+    workload (same model, same 1000 steps, fewer walkers)."""
+    import numpy as np
+    import oracle.core as oc
+    r = wl.run
+    m = oc.Model(wl.model)
+
+    def run(n):
+        t = time.perf_counter()
+        st, s0 = oc.sample(m, wl.init, r.seed, n)
+        sums = np.zeros((r.n_out, 2, 2, 2, 4))
+        sums[0] = s0
+        oc.propagate(m, st, r.dt, r.n_steps, r.cadence, r.seed, r.n_out, sums)
+        oc.finalize(sums, n)
+        return time.perf_counter() - t
+
+    cal_n = 4096
+    dt_cal = run(cal_n)
+    n = int(max(cal_n, min(5_000_000, cal_n * target_s / max(dt_cal, 1e-6))))
+    n = (n // 1024) * 1024
+    dt = run(n)
+    return {"value": n * r.n_steps / dt, "unit": "trajectory-steps/s", "cores": oc.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} walkers x {r.n_steps} steps of the same model (sample+propagate+reduce), "
+                      f"{dt:.1f} s, FP64 C oracle, OpenMP over walkers"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--n-traj", type=int, default=None)
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the walker ensemble would shard by trajectory id; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2608_14544_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = W.pyrazine_ci()
+    n_traj = args.n_traj or wl.run.n_traj
+    r = wl.run
+    model = P.Model(wl.model)
+    print(f"[bench] {wl.model.name}: {n_traj} walkers x {r.n_steps} steps, prec {args.prec}", file=sys.stderr,
+          flush=True)
+
+    ms_step, ms_prop, res = time_path(P, torch, model, wl, args.prec, n_traj, args.steps, args.warmup)
+    tsteps = n_traj * r.n_steps
+    value = tsteps / (ms_step / 1e3)
+    fl = flops_per_traj_step(wl.model.n_modes)
+    achieved = fl * tsteps / (ms_prop / 1e3) / 1e12
+    peak = PEAK_TFLOPS[args.prec]
+    line = {
+        "metric": "trajectory-steps/s (3-mode CI model, 1e7 walkers)",
+        "value": value,
+        "unit": "trajectory-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64acc" if args.prec == "fp32" else "f64",
+        "data": "synthetic (seeded Wigner sampling of the model; no dataset)",
+        "config": {"workload": "pyrazine_ci: 2-state 3-mode LVC conical intersection, "
+                               f"{n_traj} walkers, {r.n_steps} steps of 0.5 fs, bins every {r.cadence} steps",
+                   "n_traj": n_traj, "n_steps": r.n_steps, "cadence": r.cadence, "precision": args.prec},
+        "propagate_ms": ms_prop,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "propagate_n2_kernel", "flops_per_traj_step": fl},
+    }
+    print(f"[bench] {args.prec}: {ms_step:.2f} ms/step, propagate {ms_prop:.2f} ms", file=sys.stderr, flush=True)
+
+    if not args.no_compare:
+        other = "fp64" if args.prec == "fp32" else "fp32"
+        ms2, mp2, res2 = time_path(P, torch, model, wl, other, n_traj, args.steps, args.warmup)
+        pops = (0, 1)
+        diff = max(float(np.max(np.abs(res[:, 0, i, i, 0] - res2[:, 0, i, i, 0]))) for i in pops)
+        se = float(np.max(np.hypot(res[:, 0, :, :, 2], res2[:, 0, :, :, 2])))
+        line[other] = {"value": tsteps / (ms2 / 1e3), "ms_per_step": ms2, "propagate_ms": mp2,
+                       "roofline_frac": fl * tsteps / (mp2 / 1e3) / 1e12 / PEAK_TFLOPS[other]}
+        line["fp32_vs_fp64_max_abs_population_diff"] = diff
+        line["population_max_se"] = se
+        print(f"[bench] {other}: {ms2:.2f} ms/step, propagate {mp2:.2f} ms; max |dP| {diff:.2e}",
+              file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

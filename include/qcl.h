@@ -1,0 +1,228 @@
+/*
+ * qcl.h -- C ABI of the MI355X (gfx950) propagator for the
+ * momentum-jump-free quantum-classical Liouville (QCL) trajectory ensemble
+ * (K. Ando, "GPU implementation of mixed quantum-classical Liouville
+ * molecular dynamics without momentum jump").
+ *
+ * The method (Sec. II.A, Eq. 1) propagates the partially Wigner-transformed
+ * density matrix rho_ab:W(R,P) with a fixed number of independent walkers
+ * (Sec. II.B: no trajectory spawning).  A walker carries one element (a,b)
+ * of the adiabatic basis, classical coordinates q and momenta p, a real
+ * weight w and a phase Phi; its contribution to rho_ab is w exp(-i Phi).
+ * Per step it makes a Monte Carlo move between elements with a weight
+ * update (the -(P/M) sum_g (d rho - rho d) term; p is never changed),
+ * moves (q,p) by velocity Verlet on the mean force (F_a + F_b)/2 (last two
+ * terms of Eq. 1) and accumulates Phi from w_ab = (E_a - E_b)/hbar (first
+ * term of Eq. 1).  Ensemble averages are reduced in a fixed order
+ * (Sec. II.B: deterministic reduction rather than atomics).
+ *
+ * Model family: linear-vibronic harmonic Hamiltonians (Sec. II.C models)
+ *     H = sum_j p_j^2/(2 m_j) + sum_j m_j w_j^2 q_j^2/2 + V0 + sum_j q_j K_j
+ * with real symmetric N x N matrices V0 and K_j.
+ *
+ * General conventions
+ *   - Every call returns a qcl_status; nothing throws across the ABI.  On
+ *     failure qcl_last_error() returns a thread-local message.
+ *   - Arguments are validated on the host before any launch; an invalid
+ *     call launches nothing and changes nothing.
+ *   - "device" pointers are HIP device allocations owned by the caller;
+ *     "host" pointers are read during the call only.
+ *   - Device work is enqueued on the given stream (a hipStream_t passed as
+ *     void*, NULL = the default stream) and is asynchronous: results are
+ *     valid once the stream has reached the point of the call.
+ *   - Nothing in qcl_sample_initial, qcl_propagate or
+ *     qcl_reduce_observables allocates memory.
+ */
+#ifndef QCL_H
+#define QCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QCL_MAX_STATES 4
+#define QCL_MAX_MODES 128
+/* Walkers per reduction tile: the partial sums are kept per tile of this
+ * many consecutive walkers. */
+#define QCL_TILE 256
+
+typedef enum {
+    QCL_OK = 0,
+    QCL_ERR_INVALID_ARG = 1,   /* bad size, pointer, value or layout */
+    QCL_ERR_UNSUPPORTED = 2,   /* valid request this build cannot run */
+    QCL_ERR_OUT_OF_MEMORY = 3, /* qcl_create_model could not allocate */
+    QCL_ERR_DEVICE = 4         /* a HIP call or kernel launch failed */
+} qcl_status;
+
+typedef enum {
+    QCL_FP64 = 0,        /* everything in binary64 */
+    QCL_FP32_ACC64 = 1   /* q, p, frame and per-step arithmetic in binary32;
+                            weight, phase integral, near-degenerate
+                            eigen-solves and all sums in binary64 */
+} qcl_precision;
+
+typedef enum {
+    QCL_INIT_DIABATIC = 0, /* |k><k| in the diabatic basis */
+    QCL_INIT_ADIABATIC = 1 /* |k><k| in the adiabatic basis */
+} qcl_init_basis;
+
+typedef enum {
+    /* stay with probability 1/(1+S), move to candidate k with probability
+     * |f_k|/(1+S); w <- w (1+S) sgn(f_k) (sgn = 1 when staying) */
+    QCL_TRANS_NORMALIZED = 0,
+    /* when S < 1: move to k with probability |f_k| (w <- w sgn f_k), else
+     * stay with w <- w/(1-S); steps with S >= 1 use the normalized rule
+     * and set QCL_FLAG_FALLBACK */
+    QCL_TRANS_LINEAR = 1
+} qcl_transition;
+
+/* per-walker diagnostic bits (qcl_ensemble.flags) */
+#define QCL_FLAG_NONFINITE 1u   /* w or Phi not finite: walker excluded from sums */
+#define QCL_FLAG_DEGENERATE 2u  /* an adiabatic gap below DBL_MIN was met */
+#define QCL_FLAG_RESOLVED64 4u  /* binary32 path re-solved a small gap in binary64 */
+#define QCL_FLAG_FALLBACK 8u    /* linear rule fell back to the normalized one */
+
+typedef struct qcl_model_s *qcl_model; /* opaque, library-owned, immutable */
+
+/* Model description (host pointers, read during qcl_create_model only). */
+typedef struct {
+    int32_t n_states;     /* N, 2 .. QCL_MAX_STATES */
+    int32_t n_modes;      /* M, 1 .. QCL_MAX_MODES */
+    const double *mass;   /* [M], > 0 */
+    const double *omega;  /* [M], > 0 */
+    const double *v0;     /* [N*N] row-major, symmetric to 1e-12 relative */
+    const double *k;      /* [M*N*N] row-major per mode, each symmetric */
+    double hbar;          /* > 0 (1 in reduced units or eV-based units) */
+} qcl_model_desc;
+
+/* Initial state (Sec. II.A: partial Wigner transform of the nuclei).
+ * Each mode j is drawn from the thermal Wigner distribution of its
+ * harmonic well, centred on (q0_j, 0):
+ *   var q = hbar/(2 m w tanh(hbar w/2kT)),  var p = hbar m w/(2 tanh(.)),
+ * (kT = 0: ground state).  DIABATIC k: element (a,b) drawn with
+ * probability |U_ka U_kb|/Z, Z = (sum_a |U_ka|)^2, w = sgn(U_ka U_kb) Z;
+ * ADIABATIC k: (a,b) = (k,k), w = 1.  Phi = 0. */
+typedef struct {
+    double kT;            /* >= 0, finite */
+    const double *q0;     /* [M] host */
+    int32_t state;        /* k in 0 .. N-1 */
+    int32_t basis;        /* qcl_init_basis */
+} qcl_init_desc;
+
+/* Walker ensemble: structure-of-arrays in device memory, owned by the
+ * caller.  Every per-walker array has leading dimension ld (>= n_traj,
+ * a multiple of 64); walker t of mode j lives at q[j*ld + t].  "real" is
+ * double for QCL_FP64 and float for QCL_FP32_ACC64. */
+typedef struct {
+    int64_t n_traj;       /* walkers, >= 0 */
+    int64_t ld;           /* leading dimension */
+    int64_t traj_offset;  /* global id of walker 0 (random streams are keyed
+                             by global id, so a slice reproduces the whole) */
+    int64_t step;         /* global step counter; qcl_propagate advances it */
+    int32_t prec;         /* qcl_precision */
+    int32_t reserved;
+    void *q;              /* device real [M][ld]  coordinates */
+    void *p;              /* device real [M][ld]  momenta */
+    void *u;              /* device real [N*N][ld] adiabatic frame:
+                             u[(i*N + k)*ld + t] = U_ik, column k is the
+                             eigenvector of the k-th lowest energy */
+    double *w;            /* device [ld] weight */
+    double *phase;        /* device [ld] Phi */
+    uint8_t *a;           /* device [ld] element row */
+    uint8_t *b;           /* device [ld] element column */
+    uint32_t *flags;      /* device [ld] QCL_FLAG_* bits, or NULL */
+} qcl_ensemble;
+
+/* Propagation request. */
+typedef struct {
+    double dt;            /* > 0 */
+    int32_t n_steps;      /* >= 0 */
+    int32_t cadence;      /* >= 1: bin o receives global step o*cadence */
+    int32_t n_out;        /* bins held by the partials buffer; every bin
+                             reached by this call must be < n_out */
+    int32_t scheme;       /* qcl_transition */
+    uint64_t seed;        /* Philox key */
+    int32_t block;        /* reserved, 0 */
+    int32_t reserved;
+} qcl_prop_desc;
+
+/* Builds a model: validates the description, derives the per-mode
+ * constants and uploads them to the current device (a few KB, owned by
+ * the model).  Errors: INVALID_ARG (sizes, non-finite values, mass/omega
+ * <= 0, asymmetry), OUT_OF_MEMORY, DEVICE. */
+qcl_status qcl_create_model(const qcl_model_desc *desc, qcl_model *out);
+
+/* Frees a model (NULL is accepted).  Work that uses it must be complete. */
+qcl_status qcl_destroy_model(qcl_model model);
+
+int32_t qcl_model_states(qcl_model model);
+int32_t qcl_model_modes(qcl_model model);
+
+/* Layout of one ensemble in a single caller allocation: *ld is the
+ * leading dimension and *bytes the size of a buffer that
+ * qcl_ensemble_bind() carves into the arrays above (256-byte aligned
+ * sub-buffers; flags included). */
+qcl_status qcl_ensemble_bytes(qcl_model model, int64_t n_traj, int32_t prec,
+                              int64_t *ld, size_t *bytes);
+
+/* Fills *ens with pointers into base (device, >= qcl_ensemble_bytes,
+ * 256-byte aligned); sets step = 0, traj_offset as given. */
+qcl_status qcl_ensemble_bind(qcl_model model, void *base, int64_t n_traj, int32_t prec,
+                             int64_t traj_offset, qcl_ensemble *ens);
+
+/* Bytes of the partial-sum buffer for n_traj walkers and n_out bins:
+ * n_tiles = ceil(n_traj/QCL_TILE) rows of n_out x 2 x N x N x 4 doubles,
+ * plus scratch rows used by qcl_reduce_observables. */
+qcl_status qcl_partials_bytes(qcl_model model, int64_t n_traj, int32_t n_out, size_t *bytes);
+
+/* Samples the initial ensemble (Sec. II.A, partial Wigner transform) and
+ * writes bin 0 of the partials.  Random numbers: Philox4x32-10 keyed by
+ * seed, counter (gid lo, gid hi, j, 1) for mode j and (gid lo, gid hi, 0,
+ * 2) for the element draw, gid = traj_offset + walker index.  Sampling is
+ * done in binary64 and stored in the ensemble's precision.
+ * partials: device, qcl_partials_bytes(model, n_traj, n_out).  Sets
+ * ens->step = 0.  Errors: INVALID_ARG, DEVICE. */
+qcl_status qcl_sample_initial(qcl_model model, const qcl_init_desc *init, uint64_t seed,
+                              qcl_ensemble *ens, double *partials, int32_t n_out, void *stream);
+
+/* Advances every walker prop->n_steps steps from global step ens->step
+ * (Eq. 1; Sec. II.B: one fixed ensemble, no spawning).  Step n:
+ *   1. Monte Carlo move at (q_n, p_n): candidates (c,b), c != a, with
+ *      f = dt v.d_ac, then (a,c), c != b, with f = dt v.d_bc, where
+ *      v.d_ab = [U^T (sum_j p_j/m_j K_j) U]_ab / (E_b - E_a);
+ *      u = Philox(seed; gid lo, gid hi, n>>2, 0) word n&3 as
+ *      (2 floor(x/2^9) + 1) 2^-24; p is not changed;
+ *   2. velocity Verlet with the mean force of the new element,
+ *      F_j = -m_j w_j^2 q_j - [(U^T K_j U)_aa + (U^T K_j U)_bb]/2;
+ *      eigen-solve at q_{n+1} (energies ascending, each eigenvector's sign
+ *      kept continuous with the previous frame);
+ *   3. Phi += dt [w_ab(q_n) + w_ab(q_{n+1})]/2;
+ *   4. if (n+1) % cadence == 0: bin (n+1)/cadence of the partials.
+ * Then ens->step += n_steps.  The result does not depend on how the steps
+ * are split over calls.  Errors: INVALID_ARG (including a bin >= n_out),
+ * UNSUPPORTED, DEVICE. */
+qcl_status qcl_propagate(qcl_model model, qcl_ensemble *ens, const qcl_prop_desc *prop,
+                         double *partials, void *stream);
+
+/* Ensemble averages (Sec. II.B: deterministic-order reduction).  Sums the
+ * tile partials over tiles in a fixed pairwise tree and writes, to device
+ * memory out [n_out][2][N][N][4]:
+ *   [o][0][a][b] adiabatic rho_ab, [o][1][i][j] diabatic rho_ij, each as
+ *   (mean Re, mean Im, standard error Re, standard error Im) over n_traj
+ *   walkers (normalised by n_traj; SE = sqrt((S2 - S1^2/T)/(T(T-1)))).
+ * The partials are read, not modified (scratch rows are).  n_traj >= 1.
+ * Errors: INVALID_ARG, DEVICE. */
+qcl_status qcl_reduce_observables(qcl_model model, double *partials, int64_t n_traj,
+                                  int32_t n_out, double *out, void *stream);
+
+/* Thread-local description of the last failure on this thread. */
+const char *qcl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCL_H */

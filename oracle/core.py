@@ -84,6 +84,8 @@ def lib():
                                        C.c_int32, _dp, _up, C.POINTER(C.c_int64)]
             L.or_propagate.restype = C.c_int
             L.or_finalize.argtypes = [C.c_int, C.c_int64, C.c_int32, _dp, _dp]
+            L.or_num_threads.argtypes = []
+            L.or_num_threads.restype = C.c_int
             _lib = L
     return _lib
 
@@ -264,6 +266,10 @@ def propagate(m, st: State, dt: float, n_steps: int, cadence: int, seed: int, n_
         raise ValueError("oracle propagate: invalid arguments")
     st.step += int(n_steps)
     return sums, int(nfb.value)
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
 
 
 def finalize(sums: np.ndarray, n_traj: int) -> np.ndarray:

@@ -36,6 +36,9 @@
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -565,6 +568,16 @@ int or_propagate(const or_model *m, int64_t n_traj, int64_t traj_offset, int64_t
     free(part);
     free(fb);
     return 0;
+}
+
+/* Threads the OpenMP loops over walkers use. */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Ensemble averages from bin sums: out [n_out][2][N][N][4] =

@@ -1,0 +1,473 @@
+// Two-state kernels for gfx950: initial sampling and multi-step propagation
+// of the QCL walker ensemble (Eq. 1), one walker per lane, whole state in
+// registers for the entire step loop.
+//
+// For N = 2 the adiabatic problem is solved in closed form (no iteration):
+// with V(q) = Vbar I + [[dl, cc], [cc, -dl]] the energies are Vbar -+ r,
+// r = sqrt(dl^2 + cc^2) (computed without cancellation, also near a
+// conical intersection), the upper eigenvector is (r + dl, cc) for dl >= 0
+// and (cc, r - dl) otherwise, normalised by 1/sqrt(2 r (r + |dl|)), and the
+// lower one is its 90-degree rotation.  The Hellmann-Feynman forces are
+// the gradients of Vbar -+ r, so the mean force of element (a,b) needs no
+// eigenvector at all:
+//     (F_a + F_b)_j / 2 = -m w^2 q_j - kbar_j - (a+b-1)(dl dlt_j + cc cpl_j)/r.
+// The nonadiabatic coupling uses the tracked frame U:
+//     v.d_01 = [dl_v (U00 U01 - U10 U11) + c_v (U00 U11 + U10 U01)] / (2 r),
+// with dl_v = sum_j v_j dlt_j, c_v = sum_j v_j cpl_j.
+#include "block_reduce.hpp"
+#include "philox.hpp"
+#include "qcl_internal.hpp"
+
+namespace qcl {
+namespace {
+
+__device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+__device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
+
+template <typename R>
+struct Frame2 {
+    R dl, cc, r, rinv;
+    R u00, u10, u01, u11;  // U_ik: column 0 = lower state, column 1 = upper
+};
+
+// Closed-form eigen-solve at (dl, cc); eigenvector signs unset.
+template <typename R>
+__device__ __forceinline__ void solve2(R dl, R cc, Frame2<R> &e)
+{
+    const R r2 = dl * dl + cc * cc;
+    const R rinv = rsq(r2);
+    const R r = r2 * rinv;
+    const bool pos = dl >= R(0);
+    const R x0 = pos ? r + dl : cc;
+    const R x1 = pos ? cc : r - dl;
+    const R nrm = rsq(R(2) * r * (r + (pos ? dl : -dl)));
+    e.dl = dl;
+    e.cc = cc;
+    e.r = r;
+    e.rinv = rinv;
+    e.u01 = x0 * nrm;  // upper eigenvector (column 1)
+    e.u11 = x1 * nrm;
+    e.u00 = -e.u11;    // lower eigenvector (column 0)
+    e.u10 = e.u01;
+}
+
+// Sign of each column: continuity with the previous frame (flip when the
+// overlap is negative, keep at exactly zero).
+template <typename R>
+__device__ __forceinline__ void align2(Frame2<R> &e, R p00, R p10, R p01, R p11)
+{
+    const R d0 = e.u00 * p00 + e.u10 * p10;
+    const R d1 = e.u01 * p01 + e.u11 * p11;
+    if (d0 < R(0)) { e.u00 = -e.u00; e.u10 = -e.u10; }
+    if (d1 < R(0)) { e.u01 = -e.u01; e.u11 = -e.u11; }
+}
+
+// Sign of each column without a previous frame: U_kk > 0, or the first
+// nonzero entry positive when U_kk == 0.
+template <typename R>
+__device__ __forceinline__ void gauge0_2(Frame2<R> &e)
+{
+    const R l0 = e.u00 != R(0) ? e.u00 : e.u10;
+    const R l1 = e.u11 != R(0) ? e.u11 : e.u01;
+    if (l0 < R(0)) { e.u00 = -e.u00; e.u10 = -e.u10; }
+    if (l1 < R(0)) { e.u01 = -e.u01; e.u11 = -e.u11; }
+}
+
+template <int M, typename R>
+__device__ __forceinline__ void coupling_coords(const N2Const<M, R> &C, const R (&q)[M], R &dl, R &cc)
+{
+    dl = C.dlt0;
+    cc = C.c0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        dl += C.dlt[j] * q[j];
+        cc += C.cpl[j] * q[j];
+    }
+}
+
+// binary64 re-solve of a near-degenerate point for the binary32 path
+template <int M>
+__device__ __noinline__ void resolve64(const N2Const<M, float> &C, const float (&q)[M], Frame2<float> &e)
+{
+    double dl = C.dlt0_64, cc = C.c0_64;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        dl += C.dlt64[j] * (double)q[j];
+        cc += C.cpl64[j] * (double)q[j];
+    }
+    Frame2<double> d;
+    solve2<double>(dl, cc, d);
+    e.dl = (float)d.dl; e.cc = (float)d.cc; e.r = (float)d.r; e.rinv = (float)d.rinv;
+    e.u00 = (float)d.u00; e.u10 = (float)d.u10; e.u01 = (float)d.u01; e.u11 = (float)d.u11;
+}
+
+template <int M, typename R>
+__device__ __forceinline__ void frame_at(const N2Const<M, R> &C, const R (&q)[M], Frame2<R> &e, uint32_t &flag)
+{
+    R dl, cc;
+    coupling_coords<M, R>(C, q, dl, cc);
+    solve2<R>(dl, cc, e);
+    if constexpr (sizeof(R) == 4) {
+        if (!(R(2) * e.r >= C.gap_thr)) {
+            resolve64<M>(C, q, e);
+            flag |= kFlagResolved;
+        }
+    }
+    if (!(R(2) * e.r > R(2.2250738585072014e-308)))
+        flag |= kFlagDegenerate;
+}
+
+// Per-walker contributions of one output bin, [slot][stat] with slots
+// 0..3 adiabatic (a*2+b) and 4..7 diabatic (i*2+j), stats Re, Im, Re^2, Im^2.
+template <typename R>
+__device__ __forceinline__ void bin_values(double (&v)[32], bool live, int a, int b, double w, double phase,
+                                           const Frame2<R> &e)
+{
+    double sn, cs;
+    sincos(phase, &sn, &cs);
+    double re = w * cs, im = -w * sn;
+    const bool ok = live && isfinite(w) && isfinite(phase);
+    re = ok ? re : 0.0;
+    im = ok ? im : 0.0;
+    const int s = a * 2 + b;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const bool on = (t == s);
+        v[4 * t + 0] = on ? re : 0.0;
+        v[4 * t + 1] = on ? im : 0.0;
+        v[4 * t + 2] = on ? re * re : 0.0;
+        v[4 * t + 3] = on ? im * im : 0.0;
+    }
+    const double ua0 = (double)(a ? e.u01 : e.u00);  // U_0a
+    const double ua1 = (double)(a ? e.u11 : e.u10);  // U_1a
+    const double ub0 = (double)(b ? e.u01 : e.u00);  // U_0b
+    const double ub1 = (double)(b ? e.u11 : e.u10);  // U_1b
+    const double c[4] = {ua0 * ub0, ua0 * ub1, ua1 * ub0, ua1 * ub1};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double r = re * c[t], m = im * c[t];
+        v[16 + 4 * t + 0] = r;
+        v[16 + 4 * t + 1] = m;
+        v[16 + 4 * t + 2] = r * r;
+        v[16 + 4 * t + 3] = m * m;
+    }
+}
+
+// ---------------------------------------------------------------- sampling
+
+template <int M, typename R>
+__global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C, SampleArgs S, EnsDev<R> E,
+                                                           double *__restrict__ partials, int32_t n_out)
+{
+    __shared__ double lds[4 * 32];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool live = i < E.n_traj;
+    const uint64_t gid = (uint64_t)(E.traj_offset + (live ? i : 0));
+    const double two_pi = 6.283185307179586476925286766559;
+
+    double q[M], p[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const U4 x = philox10(U4{(uint32_t)gid, (uint32_t)(gid >> 32), (uint32_t)j, 1u}, S.key0, S.key1);
+        const double u1 = u52(x.x, x.y);
+        const double u2 = u52(x.z, x.w);
+        const double rr = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincos(two_pi * u2, &sn, &cs);
+        q[j] = S.q0[j] + S.sq[j] * (rr * cs);
+        p[j] = S.sp[j] * (rr * sn);
+    }
+    Frame2<double> e;
+    uint32_t flag = 0;
+    frame_at<M, double>(C, q, e, flag);
+    gauge0_2<double>(e);
+
+    int a, b;
+    double w;
+    if (S.basis == QCL_INIT_ADIABATIC) {
+        a = b = S.state;
+        w = 1.0;
+    } else {
+        // diabatic |k><k| in the adiabatic basis: rho_ab = U_ka U_kb
+        const int k = S.state;
+        const double uk0 = k ? e.u10 : e.u00;  // U_k0
+        const double uk1 = k ? e.u11 : e.u01;  // U_k1
+        const double rs = fabs(uk0) + fabs(uk1);
+        const double Z = rs * rs;
+        const U4 x = philox10(U4{(uint32_t)gid, (uint32_t)(gid >> 32), 0u, 2u}, S.key0, S.key1);
+        const double t = u52(x.x, x.y) * Z;
+        const double w00 = fabs(uk0 * uk0), w01 = fabs(uk0 * uk1), w11 = fabs(uk1 * uk1);
+        double Cm = w00;
+        int pa = -1, pb = -1;
+        if (t < Cm) { pa = 0; pb = 0; }
+        Cm += w01;
+        if (pa < 0 && t < Cm) { pa = 0; pb = 1; }
+        Cm += w01;
+        if (pa < 0 && t < Cm) { pa = 1; pb = 0; }
+        Cm += w11;
+        if (pa < 0 && t < Cm) { pa = 1; pb = 1; }
+        if (pa < 0) {  // rounding: last element with nonzero weight
+            if (w11 > 0.0) { pa = 1; pb = 1; }
+            else if (w01 > 0.0) { pa = 1; pb = 0; }
+            else { pa = 0; pb = 0; }
+        }
+        a = pa;
+        b = pb;
+        const double prod = (pa ? uk1 : uk0) * (pb ? uk1 : uk0);
+        w = (prod > 0.0 ? 1.0 : -1.0) * Z;
+    }
+
+    double v[32];
+    bin_values<double>(v, live, a, b, w, 0.0, e);
+    block_reduce_store<32>(v, partials + ((int64_t)blockIdx.x * n_out + 0) * 32, lds);
+
+    if (live) {
+        const int64_t ld = E.ld;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            E.q[j * ld + i] = (R)q[j];
+            E.p[j * ld + i] = (R)p[j];
+        }
+        E.u[0 * ld + i] = (R)e.u00;
+        E.u[1 * ld + i] = (R)e.u01;
+        E.u[2 * ld + i] = (R)e.u10;
+        E.u[3 * ld + i] = (R)e.u11;
+        E.w[i] = w;
+        E.phase[i] = 0.0;
+        E.a[i] = (uint8_t)a;
+        E.b[i] = (uint8_t)b;
+        if (E.flags)
+            E.flags[i] = flag;
+    }
+}
+
+// ---------------------------------------------------------------- propagation
+
+template <int M, typename R>
+__device__ __forceinline__ void mean_force_kick(const N2Const<M, R> &C, const Frame2<R> &e, int a, int b,
+                                                const R (&q)[M], R (&p)[M])
+{
+    const R g = R(a + b - 1) * e.rinv;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const R F = -(C.kq[j] * q[j]) - C.kbar[j] - g * (e.dl * C.dlt[j] + e.cc * C.cpl[j]);
+        p[j] += C.half_dt * F;
+    }
+}
+
+template <int M, typename R>
+__global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, PropArgs P, EnsDev<R> E,
+                                                              double *__restrict__ partials)
+{
+    __shared__ double lds[4 * 32];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool live = i < E.n_traj;
+    const int64_t li = live ? i : E.n_traj - 1;  // idle lanes shadow a valid walker
+    const int64_t ld = E.ld;
+    const uint64_t gid = (uint64_t)(E.traj_offset + li);
+
+    R q[M], p[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        q[j] = E.q[j * ld + li];
+        p[j] = E.p[j * ld + li];
+    }
+    const R p00 = E.u[0 * ld + li], p01 = E.u[1 * ld + li], p10 = E.u[2 * ld + li], p11 = E.u[3 * ld + li];
+    double w = E.w[li];
+    double phase = E.phase[li];
+    int a = E.a[li];
+    int b = E.b[li];
+    uint32_t flag = 0;
+
+    Frame2<R> e;
+    frame_at<M, R>(C, q, e, flag);
+    align2<R>(e, p00, p10, p01, p11);
+
+    U4 rnd{0, 0, 0, 0};
+    for (int it = 0; it < P.n_steps; ++it) {
+        const int64_t step = P.step0 + it;
+        if (it == 0 || (step & 3) == 0)
+            rnd = philox10(U4{(uint32_t)gid, (uint32_t)(gid >> 32), (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
+        const uint32_t word = pick_word(rnd, (uint32_t)(step & 3));
+
+        // 1. Monte Carlo move between elements at (q_n, p_n)
+        R dlv = R(0), cv = R(0);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const R vj = p[j] * C.minv[j];
+            dlv += vj * C.dlt[j];
+            cv += vj * C.cpl[j];
+        }
+        const R D01 = dlv * (e.u00 * e.u01 - e.u10 * e.u11) + cv * (e.u00 * e.u11 + e.u10 * e.u01);
+        const R x = C.dt * (D01 * (R(0.5) * e.rinv));  // dt v.d_01
+        const R f0 = a == 0 ? x : -x;                  // to (1-a, b): dt v.d_{a,1-a}
+        const R f1 = b == 0 ? x : -x;                  // to (a, 1-b): dt v.d_{b,1-b}
+        const R af0 = f0 < R(0) ? -f0 : f0;
+        const R af1 = f1 < R(0) ? -f1 : f1;
+        const R S = af0 + af1;
+        int pick = -1;
+        if (P.scheme == QCL_TRANS_LINEAR && S < R(1)) {
+            R u;
+            if constexpr (sizeof(R) == 4) u = u24f(word); else u = u24d(word);
+            if (u < af0) pick = 0;
+            else if (u < S) pick = 1;
+            if (pick < 0) w = w / (double)(R(1) - S);
+            else w = w * ((pick == 0 ? f0 : f1) > R(0) ? 1.0 : -1.0);
+        } else {
+            if (P.scheme == QCL_TRANS_LINEAR)
+                flag |= kFlagFallback;
+            R u;
+            if constexpr (sizeof(R) == 4) u = u24f(word); else u = u24d(word);
+            const R t = u * (R(1) + S);
+            if (!(t < R(1))) {
+                if (t < R(1) + af0) pick = 0;
+                else if (t < R(1) + S) pick = 1;
+                else pick = af1 > R(0) ? 1 : (af0 > R(0) ? 0 : -1);
+            }
+            const double sg = pick < 0 ? 1.0 : ((pick == 0 ? f0 : f1) > R(0) ? 1.0 : -1.0);
+            w = w * (double)(R(1) + S) * sg;
+        }
+        if (pick == 0) a = 1 - a;
+        if (pick == 1) b = 1 - b;
+
+        // 2. velocity Verlet on the mean force of the current element
+        const R r_old = e.r;
+        mean_force_kick<M, R>(C, e, a, b, q, p);
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            q[j] += C.dt * (p[j] * C.minv[j]);
+        const R o00 = e.u00, o10 = e.u10, o01 = e.u01, o11 = e.u11;
+        frame_at<M, R>(C, q, e, flag);
+        align2<R>(e, o00, o10, o01, o11);
+        mean_force_kick<M, R>(C, e, a, b, q, p);
+
+        // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar = 2 (a - b) r / hbar
+        phase += (double)(a - b) * (C.dt_hbar * ((double)r_old + (double)e.r));
+
+        // 4. output bin
+        const int64_t s1 = step + 1;
+        if (s1 % P.cadence == 0) {
+            const int64_t o = s1 / P.cadence;
+            if (o < P.n_out) {
+                double v[32];
+                bin_values<R>(v, live, a, b, w, phase, e);
+                block_reduce_store<32>(v, partials + ((int64_t)blockIdx.x * P.n_out + o) * 32, lds);
+            }
+        }
+    }
+    if (!(isfinite(w) && isfinite(phase)))
+        flag |= kFlagNonfinite;
+
+    if (live) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            E.q[j * ld + i] = q[j];
+            E.p[j * ld + i] = p[j];
+        }
+        E.u[0 * ld + i] = e.u00;
+        E.u[1 * ld + i] = e.u01;
+        E.u[2 * ld + i] = e.u10;
+        E.u[3 * ld + i] = e.u11;
+        E.w[i] = w;
+        E.phase[i] = phase;
+        E.a[i] = (uint8_t)a;
+        E.b[i] = (uint8_t)b;
+        if (E.flags)
+            E.flags[i] |= flag;
+    }
+}
+
+template <int M, typename R>
+N2Const<M, R> make_const(const qcl_model_s &m, double dt)
+{
+    N2Const<M, R> C{};
+    for (int j = 0; j < M; ++j) {
+        const bool real = j < m.m;  // padded modes are inert
+        C.kq[j] = (R)(real ? m.kq[j] : 0.0);
+        C.minv[j] = (R)(real ? m.minv[j] : 0.0);
+        C.kbar[j] = (R)(real ? m.kbar[j] : 0.0);
+        C.dlt[j] = (R)(real ? m.dlt[j] : 0.0);
+        C.cpl[j] = (R)(real ? m.cpl[j] : 0.0);
+        C.dlt64[j] = real ? m.dlt[j] : 0.0;
+        C.cpl64[j] = real ? m.cpl[j] : 0.0;
+    }
+    C.dlt0 = (R)m.dlt0;
+    C.c0 = (R)m.c0;
+    C.dlt0_64 = m.dlt0;
+    C.c0_64 = m.c0;
+    C.dt = (R)dt;
+    C.half_dt = (R)(0.5 * dt);
+    C.gap_thr = (R)(1e-4 * m.energy_scale);
+    C.dt_hbar = dt / m.hbar;
+    return C;
+}
+
+template <typename R>
+EnsDev<R> ens_dev(const qcl_ensemble &e)
+{
+    return EnsDev<R>{(R *)e.q, (R *)e.p, (R *)e.u, e.w, e.phase, e.a, e.b, e.flags, e.ld, e.n_traj, e.traj_offset};
+}
+
+template <int M>
+hipError_t sample_m(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens, double *partials,
+                    int32_t n_out, hipStream_t s)
+{
+    const dim3 grid((unsigned)n_tiles(ens.n_traj)), block(kBlock);
+    const N2Const<M, double> C = make_const<M, double>(m, 1.0);
+    if (ens.prec == QCL_FP64)
+        hipLaunchKernelGGL((sample_n2_kernel<M, double>), grid, block, 0, s, C, sa, ens_dev<double>(ens), partials, n_out);
+    else
+        hipLaunchKernelGGL((sample_n2_kernel<M, float>), grid, block, 0, s, C, sa, ens_dev<float>(ens), partials, n_out);
+    return hipGetLastError();
+}
+
+template <int M>
+hipError_t propagate_m(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
+                       hipStream_t s)
+{
+    const dim3 grid((unsigned)n_tiles(ens.n_traj)), block(kBlock);
+    PropArgs P{ens.step, pd.n_steps, pd.cadence, pd.n_out, pd.scheme, (uint32_t)pd.seed, (uint32_t)(pd.seed >> 32)};
+    if (ens.prec == QCL_FP64)
+        hipLaunchKernelGGL((propagate_n2_kernel<M, double>), grid, block, 0, s, make_const<M, double>(m, pd.dt), P,
+                           ens_dev<double>(ens), partials);
+    else
+        hipLaunchKernelGGL((propagate_n2_kernel<M, float>), grid, block, 0, s, make_const<M, float>(m, pd.dt), P,
+                           ens_dev<float>(ens), partials);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sample_n2(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens, double *partials,
+                            int32_t n_out, hipStream_t s)
+{
+    switch (m.m) {
+    case 1: return sample_m<1>(m, sa, ens, partials, n_out, s);
+    case 2: return sample_m<2>(m, sa, ens, partials, n_out, s);
+    case 3: return sample_m<3>(m, sa, ens, partials, n_out, s);
+    case 4: return sample_m<4>(m, sa, ens, partials, n_out, s);
+    case 5: return sample_m<5>(m, sa, ens, partials, n_out, s);
+    case 6: return sample_m<6>(m, sa, ens, partials, n_out, s);
+    case 7: return sample_m<7>(m, sa, ens, partials, n_out, s);
+    case 8: return sample_m<8>(m, sa, ens, partials, n_out, s);
+    default: return hipErrorNotSupported;
+    }
+}
+
+hipError_t launch_propagate_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
+                               double *partials, hipStream_t s)
+{
+    switch (m.m) {
+    case 1: return propagate_m<1>(m, ens, pd, partials, s);
+    case 2: return propagate_m<2>(m, ens, pd, partials, s);
+    case 3: return propagate_m<3>(m, ens, pd, partials, s);
+    case 4: return propagate_m<4>(m, ens, pd, partials, s);
+    case 5: return propagate_m<5>(m, ens, pd, partials, s);
+    case 6: return propagate_m<6>(m, ens, pd, partials, s);
+    case 7: return propagate_m<7>(m, ens, pd, partials, s);
+    case 8: return propagate_m<8>(m, ens, pd, partials, s);
+    default: return hipErrorNotSupported;
+    }
+}
+
+}  // namespace qcl

@@ -1,0 +1,369 @@
+// Host side of the C ABI declared in qcl.h: validation, model set-up,
+// ensemble layout and kernel dispatch.  No device memory is allocated
+// outside qcl_create_model.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "qcl_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qcl_status fail(qcl_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+qcl_status device_fail(hipError_t e, const char *what)
+{
+    return fail(QCL_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_all(const double *x, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(x[i]))
+            return false;
+    return true;
+}
+
+bool symmetric(const double *a, int n)
+{
+    double scale = 0.0;
+    for (int i = 0; i < n * n; ++i)
+        scale = std::max(scale, std::fabs(a[i]));
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            if (std::fabs(a[i * n + j] - a[j * n + i]) > 1e-12 * std::max(scale, 1e-300))
+                return false;
+    return true;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t real_size(int32_t prec) { return prec == QCL_FP64 ? sizeof(double) : sizeof(float); }
+
+int64_t leading_dim(int64_t n_traj) { return std::max<int64_t>(64, (n_traj + 63) / 64 * 64); }
+
+qcl_status check_model(qcl_model m)
+{
+    if (!m)
+        return fail(QCL_ERR_INVALID_ARG, "model is NULL");
+    return QCL_OK;
+}
+
+qcl_status check_ensemble(const qcl_model_s &m, const qcl_ensemble *e)
+{
+    if (!e)
+        return fail(QCL_ERR_INVALID_ARG, "ensemble is NULL");
+    if (e->prec != QCL_FP64 && e->prec != QCL_FP32_ACC64)
+        return fail(QCL_ERR_INVALID_ARG, "unknown precision %d", e->prec);
+    if (e->n_traj < 0)
+        return fail(QCL_ERR_INVALID_ARG, "n_traj < 0");
+    if (e->n_traj > ((int64_t)1 << 40))
+        return fail(QCL_ERR_INVALID_ARG, "n_traj too large");
+    if (e->ld < e->n_traj || e->ld % 64 != 0)
+        return fail(QCL_ERR_INVALID_ARG, "ld must be >= n_traj and a multiple of 64");
+    if (e->traj_offset < 0 || e->step < 0)
+        return fail(QCL_ERR_INVALID_ARG, "traj_offset and step must be >= 0");
+    if (e->n_traj > 0) {
+        if (!e->q || !e->p || !e->u || !e->w || !e->phase || !e->a || !e->b)
+            return fail(QCL_ERR_INVALID_ARG, "ensemble array pointer is NULL");
+        const size_t rs = real_size(e->prec);
+        if (((uintptr_t)e->q % rs) || ((uintptr_t)e->p % rs) || ((uintptr_t)e->u % rs) ||
+            ((uintptr_t)e->w % 8) || ((uintptr_t)e->phase % 8) || ((uintptr_t)e->flags % 4))
+            return fail(QCL_ERR_INVALID_ARG, "misaligned ensemble array");
+    }
+    (void)m;
+    return QCL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qcl_last_error(void) { return g_last_error.c_str(); }
+
+qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out)
+{
+    if (!d || !out)
+        return fail(QCL_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    const int n = d->n_states, M = d->n_modes;
+    if (n < 2 || n > QCL_MAX_STATES)
+        return fail(QCL_ERR_INVALID_ARG, "n_states %d outside [2, %d]", n, QCL_MAX_STATES);
+    if (M < 1 || M > QCL_MAX_MODES)
+        return fail(QCL_ERR_INVALID_ARG, "n_modes %d outside [1, %d]", M, QCL_MAX_MODES);
+    if (!d->mass || !d->omega || !d->v0 || !d->k)
+        return fail(QCL_ERR_INVALID_ARG, "model array is NULL");
+    if (!(d->hbar > 0.0) || !std::isfinite(d->hbar))
+        return fail(QCL_ERR_INVALID_ARG, "hbar must be finite and > 0");
+    if (!finite_all(d->mass, M) || !finite_all(d->omega, M) || !finite_all(d->v0, n * n) ||
+        !finite_all(d->k, (int64_t)M * n * n))
+        return fail(QCL_ERR_INVALID_ARG, "non-finite model parameter");
+    for (int j = 0; j < M; ++j)
+        if (!(d->mass[j] > 0.0) || !(d->omega[j] > 0.0))
+            return fail(QCL_ERR_INVALID_ARG, "mass and omega must be > 0 (mode %d)", j);
+    if (!symmetric(d->v0, n))
+        return fail(QCL_ERR_INVALID_ARG, "V0 is not symmetric");
+    for (int j = 0; j < M; ++j)
+        if (!symmetric(d->k + (size_t)j * n * n, n))
+            return fail(QCL_ERR_INVALID_ARG, "K_%d is not symmetric", j);
+    if (n != 2)
+        return fail(QCL_ERR_UNSUPPORTED, "n_states %d: only two-state models are built in this library", n);
+    if (M > qcl::kMaxFastModes)
+        return fail(QCL_ERR_UNSUPPORTED, "n_modes %d: two-state kernels cover up to %d modes", M,
+                    qcl::kMaxFastModes);
+
+    qcl_model_s *m = new (std::nothrow) qcl_model_s();
+    if (!m)
+        return fail(QCL_ERR_OUT_OF_MEMORY, "host allocation failed");
+    m->n = n;
+    m->m = M;
+    m->hbar = d->hbar;
+    m->mass.assign(d->mass, d->mass + M);
+    m->omega.assign(d->omega, d->omega + M);
+    m->v0.assign(d->v0, d->v0 + n * n);
+    m->k.assign(d->k, d->k + (size_t)M * n * n);
+    // two-state constants
+    m->kq.resize(M);
+    m->minv.resize(M);
+    m->kbar.resize(M);
+    m->dlt.resize(M);
+    m->cpl.resize(M);
+    double scale = std::fabs(m->v0[0]) + std::fabs(m->v0[1]) + std::fabs(m->v0[3]);
+    for (int j = 0; j < M; ++j) {
+        const double *K = &m->k[(size_t)j * 4];
+        m->kq[j] = m->mass[j] * m->omega[j] * m->omega[j];
+        m->minv[j] = 1.0 / m->mass[j];
+        m->kbar[j] = 0.5 * (K[0] + K[3]);
+        m->dlt[j] = 0.5 * (K[0] - K[3]);
+        m->cpl[j] = K[1];
+        scale += (std::fabs(K[0]) + std::fabs(K[1]) + std::fabs(K[3])) / std::sqrt(m->kq[j]);
+    }
+    m->dlt0 = 0.5 * (m->v0[0] - m->v0[3]);
+    m->c0 = m->v0[1];
+    m->energy_scale = scale > 0.0 ? scale : 1.0;
+
+    hipError_t e = hipGetDevice(&m->device);
+    if (e != hipSuccess) {
+        delete m;
+        return device_fail(e, "hipGetDevice");
+    }
+    const size_t bytes = sizeof(double) * (m->v0.size() + m->k.size());
+    e = hipMalloc((void **)&m->d_model, bytes);
+    if (e != hipSuccess) {
+        delete m;
+        return e == hipErrorOutOfMemory ? fail(QCL_ERR_OUT_OF_MEMORY, "hipMalloc of %zu bytes", bytes)
+                                        : device_fail(e, "hipMalloc");
+    }
+    std::vector<double> packed(m->v0);
+    packed.insert(packed.end(), m->k.begin(), m->k.end());
+    e = hipMemcpy(m->d_model, packed.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(m->d_model);
+        delete m;
+        return device_fail(e, "hipMemcpy");
+    }
+    *out = m;
+    return QCL_OK;
+}
+
+qcl_status qcl_destroy_model(qcl_model m)
+{
+    if (!m)
+        return QCL_OK;
+    if (m->d_model)
+        (void)hipFree(m->d_model);
+    delete m;
+    return QCL_OK;
+}
+
+int32_t qcl_model_states(qcl_model m) { return m ? m->n : 0; }
+int32_t qcl_model_modes(qcl_model m) { return m ? m->m : 0; }
+
+qcl_status qcl_ensemble_bytes(qcl_model m, int64_t n_traj, int32_t prec, int64_t *ld, size_t *bytes)
+{
+    if (qcl_status st = check_model(m))
+        return st;
+    if (!ld || !bytes)
+        return fail(QCL_ERR_INVALID_ARG, "NULL output");
+    if (n_traj < 0 || n_traj > ((int64_t)1 << 40))
+        return fail(QCL_ERR_INVALID_ARG, "n_traj out of range");
+    if (prec != QCL_FP64 && prec != QCL_FP32_ACC64)
+        return fail(QCL_ERR_INVALID_ARG, "unknown precision %d", prec);
+    const int64_t L = leading_dim(n_traj);
+    const size_t rs = real_size(prec);
+    size_t b = 0;
+    b += align256((size_t)m->m * L * rs);          // q
+    b += align256((size_t)m->m * L * rs);          // p
+    b += align256((size_t)m->n * m->n * L * rs);   // u
+    b += align256((size_t)L * 8);                  // w
+    b += align256((size_t)L * 8);                  // phase
+    b += align256((size_t)L);                      // a
+    b += align256((size_t)L);                      // b
+    b += align256((size_t)L * 4);                  // flags
+    *ld = L;
+    *bytes = b;
+    return QCL_OK;
+}
+
+qcl_status qcl_ensemble_bind(qcl_model m, void *base, int64_t n_traj, int32_t prec, int64_t traj_offset,
+                             qcl_ensemble *e)
+{
+    int64_t L;
+    size_t total;
+    if (qcl_status st = qcl_ensemble_bytes(m, n_traj, prec, &L, &total))
+        return st;
+    if (!e || !base)
+        return fail(QCL_ERR_INVALID_ARG, "NULL argument");
+    if ((uintptr_t)base % 256)
+        return fail(QCL_ERR_INVALID_ARG, "base must be 256-byte aligned");
+    if (traj_offset < 0)
+        return fail(QCL_ERR_INVALID_ARG, "traj_offset < 0");
+    const size_t rs = real_size(prec);
+    char *c = (char *)base;
+    std::memset(e, 0, sizeof(*e));
+    e->n_traj = n_traj;
+    e->ld = L;
+    e->traj_offset = traj_offset;
+    e->step = 0;
+    e->prec = prec;
+    e->q = c; c += align256((size_t)m->m * L * rs);
+    e->p = c; c += align256((size_t)m->m * L * rs);
+    e->u = c; c += align256((size_t)m->n * m->n * L * rs);
+    e->w = (double *)c; c += align256((size_t)L * 8);
+    e->phase = (double *)c; c += align256((size_t)L * 8);
+    e->a = (uint8_t *)c; c += align256((size_t)L);
+    e->b = (uint8_t *)c; c += align256((size_t)L);
+    e->flags = (uint32_t *)c;
+    return QCL_OK;
+}
+
+qcl_status qcl_partials_bytes(qcl_model m, int64_t n_traj, int32_t n_out, size_t *bytes)
+{
+    if (qcl_status st = check_model(m))
+        return st;
+    if (!bytes)
+        return fail(QCL_ERR_INVALID_ARG, "NULL output");
+    if (n_traj < 0 || n_out < 1)
+        return fail(QCL_ERR_INVALID_ARG, "n_traj >= 0 and n_out >= 1 required");
+    const int64_t t = qcl::n_tiles(n_traj);
+    const int64_t rows = t + (t + 7) / 8 + (t + 63) / 64;
+    *bytes = (size_t)rows * n_out * qcl::tile_values(m->n) * sizeof(double);
+    return QCL_OK;
+}
+
+qcl_status qcl_sample_initial(qcl_model m, const qcl_init_desc *init, uint64_t seed, qcl_ensemble *ens,
+                              double *partials, int32_t n_out, void *stream)
+{
+    if (qcl_status st = check_model(m))
+        return st;
+    if (qcl_status st = check_ensemble(*m, ens))
+        return st;
+    if (!init || !init->q0)
+        return fail(QCL_ERR_INVALID_ARG, "init or init->q0 is NULL");
+    if (!(init->kT >= 0.0) || !std::isfinite(init->kT))
+        return fail(QCL_ERR_INVALID_ARG, "kT must be finite and >= 0");
+    if (init->state < 0 || init->state >= m->n)
+        return fail(QCL_ERR_INVALID_ARG, "initial state %d outside [0, %d)", init->state, m->n);
+    if (init->basis != QCL_INIT_DIABATIC && init->basis != QCL_INIT_ADIABATIC)
+        return fail(QCL_ERR_INVALID_ARG, "unknown basis %d", init->basis);
+    if (!finite_all(init->q0, m->m))
+        return fail(QCL_ERR_INVALID_ARG, "non-finite q0");
+    if (n_out < 1)
+        return fail(QCL_ERR_INVALID_ARG, "n_out must be >= 1");
+    if (ens->n_traj > 0 && (!partials || ((uintptr_t)partials % 8)))
+        return fail(QCL_ERR_INVALID_ARG, "partials is NULL or misaligned");
+    qcl::SampleArgs sa{};
+    for (int j = 0; j < m->m; ++j) {
+        const double w = m->omega[j], ms = m->mass[j], hb = m->hbar;
+        const double th = init->kT > 0.0 ? std::tanh(hb * w / (2.0 * init->kT)) : 1.0;
+        sa.q0[j] = init->q0[j];
+        sa.sq[j] = std::sqrt(hb / (2.0 * ms * w * th));
+        sa.sp[j] = std::sqrt(hb * ms * w / (2.0 * th));
+    }
+    sa.state = init->state;
+    sa.basis = init->basis;
+    sa.key0 = (uint32_t)seed;
+    sa.key1 = (uint32_t)(seed >> 32);
+    ens->step = 0;
+    if (ens->n_traj == 0)
+        return QCL_OK;
+    hipError_t e = qcl::launch_sample_n2(*m, sa, *ens, partials, n_out, (hipStream_t)stream);
+    if (e == hipErrorNotSupported)
+        return fail(QCL_ERR_UNSUPPORTED, "no sampling kernel for this model");
+    if (e != hipSuccess)
+        return device_fail(e, "sample kernel launch");
+    return QCL_OK;
+}
+
+qcl_status qcl_propagate(qcl_model m, qcl_ensemble *ens, const qcl_prop_desc *pd, double *partials, void *stream)
+{
+    if (qcl_status st = check_model(m))
+        return st;
+    if (qcl_status st = check_ensemble(*m, ens))
+        return st;
+    if (!pd)
+        return fail(QCL_ERR_INVALID_ARG, "prop is NULL");
+    if (!(pd->dt > 0.0) || !std::isfinite(pd->dt))
+        return fail(QCL_ERR_INVALID_ARG, "dt must be finite and > 0");
+    if (pd->n_steps < 0 || pd->cadence < 1 || pd->n_out < 1)
+        return fail(QCL_ERR_INVALID_ARG, "n_steps >= 0, cadence >= 1 and n_out >= 1 required");
+    if (pd->scheme != QCL_TRANS_NORMALIZED && pd->scheme != QCL_TRANS_LINEAR)
+        return fail(QCL_ERR_INVALID_ARG, "unknown transition scheme %d", pd->scheme);
+    if (pd->block != 0)
+        return fail(QCL_ERR_INVALID_ARG, "block must be 0");
+    const int64_t last_bin = (ens->step + pd->n_steps) / pd->cadence;
+    if (last_bin >= pd->n_out)
+        return fail(QCL_ERR_INVALID_ARG, "bin %lld would be written but n_out is %d", (long long)last_bin,
+                    pd->n_out);
+    if (ens->step + (int64_t)pd->n_steps > ((int64_t)1 << 33))
+        return fail(QCL_ERR_INVALID_ARG, "global step counter out of range");
+    if (ens->n_traj > 0 && (!partials || ((uintptr_t)partials % 8)))
+        return fail(QCL_ERR_INVALID_ARG, "partials is NULL or misaligned");
+    if (ens->n_traj == 0 || pd->n_steps == 0) {
+        ens->step += pd->n_steps;
+        return QCL_OK;
+    }
+    hipError_t e = qcl::launch_propagate_n2(*m, *ens, *pd, partials, (hipStream_t)stream);
+    if (e == hipErrorNotSupported)
+        return fail(QCL_ERR_UNSUPPORTED, "no propagation kernel for this model");
+    if (e != hipSuccess)
+        return device_fail(e, "propagate kernel launch");
+    ens->step += pd->n_steps;
+    return QCL_OK;
+}
+
+qcl_status qcl_reduce_observables(qcl_model m, double *partials, int64_t n_traj, int32_t n_out, double *out,
+                                  void *stream)
+{
+    if (qcl_status st = check_model(m))
+        return st;
+    if (n_traj < 1)
+        return fail(QCL_ERR_INVALID_ARG, "n_traj must be >= 1 to average");
+    if (n_out < 1)
+        return fail(QCL_ERR_INVALID_ARG, "n_out must be >= 1");
+    if (!partials || !out || ((uintptr_t)partials % 8) || ((uintptr_t)out % 8))
+        return fail(QCL_ERR_INVALID_ARG, "partials/out NULL or misaligned");
+    hipError_t e = qcl::launch_reduce(m->n, partials, n_traj, n_out, out, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return device_fail(e, "reduce kernel launch");
+    return QCL_OK;
+}
+
+}  // extern "C"

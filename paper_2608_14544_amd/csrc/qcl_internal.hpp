@@ -1,0 +1,107 @@
+// Internal declarations shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "qcl.h"
+
+namespace qcl {
+
+constexpr int kBlock = QCL_TILE;           // walkers per workgroup == reduction tile
+constexpr int kWave = 64;                  // CDNA wavefront
+constexpr int kMaxFastModes = 8;           // N = 2 kernels specialised on M = 1..8
+
+// Per-walker flag bits (mirrors the public QCL_FLAG_* values).
+constexpr uint32_t kFlagNonfinite = QCL_FLAG_NONFINITE;
+constexpr uint32_t kFlagDegenerate = QCL_FLAG_DEGENERATE;
+constexpr uint32_t kFlagResolved = QCL_FLAG_RESOLVED64;
+constexpr uint32_t kFlagFallback = QCL_FLAG_FALLBACK;
+
+// Two-state model in the form the analytic kernels use: with
+// V(q) = Vbar(q) I + [[dl, cc], [cc, -dl]],
+//   dl(q) = dlt0 + sum_j dlt_j q_j,  cc(q) = c0 + sum_j cpl_j q_j,
+// the adiabatic energies are Vbar -+ r, r = sqrt(dl^2 + cc^2), and
+// dE_{0,1}/dq_j = kbar_j -+ (dl dlt_j + cc cpl_j)/r.
+template <int M, typename R>
+struct N2Const {
+    R kq[M];    // m_j w_j^2
+    R minv[M];  // 1/m_j
+    R kbar[M];  // (K_00 + K_11)/2
+    R dlt[M];   // (K_00 - K_11)/2
+    R cpl[M];   // K_01
+    R dlt0;     // (V0_00 - V0_11)/2
+    R c0;       // V0_01
+    R dt;
+    R half_dt;
+    R gap_thr;  // binary32 path: gaps 2r below this are re-solved in binary64
+    double dt_hbar;
+    // binary64 copies for the re-solve of near-degenerate points
+    double dlt64[M];
+    double cpl64[M];
+    double dlt0_64, c0_64;
+};
+
+template <typename R>
+struct EnsDev {
+    R *q;
+    R *p;
+    R *u;
+    double *w;
+    double *phase;
+    uint8_t *a;
+    uint8_t *b;
+    uint32_t *flags;
+    int64_t ld;
+    int64_t n_traj;
+    int64_t traj_offset;
+};
+
+struct SampleArgs {
+    double q0[QCL_MAX_MODES];
+    double sq[QCL_MAX_MODES];
+    double sp[QCL_MAX_MODES];
+    int32_t state;
+    int32_t basis;
+    uint32_t key0, key1;
+};
+
+struct PropArgs {
+    int64_t step0;
+    int32_t n_steps;
+    int32_t cadence;
+    int32_t n_out;
+    int32_t scheme;
+    uint32_t key0, key1;
+};
+
+}  // namespace qcl
+
+struct qcl_model_s {
+    int32_t n;
+    int32_t m;
+    double hbar;
+    std::vector<double> mass, omega, v0, k;
+    // two-state derived constants (binary64)
+    std::vector<double> kq, minv, kbar, dlt, cpl;
+    double dlt0 = 0.0, c0 = 0.0;
+    double energy_scale = 1.0;
+    int device = 0;
+    double *d_model = nullptr;  // device copy of V0 and K (general-N kernels)
+};
+
+namespace qcl {
+
+hipError_t launch_sample_n2(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,
+                            double *partials, int32_t n_out, hipStream_t stream);
+hipError_t launch_propagate_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
+                               double *partials, hipStream_t stream);
+hipError_t launch_reduce(int n_states, double *partials, int64_t n_traj, int32_t n_out, double *out,
+                         hipStream_t stream);
+
+inline int64_t n_tiles(int64_t n_traj) { return (n_traj + kBlock - 1) / kBlock; }
+inline int64_t tile_values(int n_states) { return 8LL * n_states * n_states; }
+
+}  // namespace qcl

@@ -1,0 +1,80 @@
+// Ensemble averages from tile partials (Sec. II.B: fixed summation order).
+//
+// The partials hold, per tile of QCL_TILE walkers, the sums of every bin
+// value.  They are combined by a perfect pairwise tree over the tile index
+// (zero-padded): each pass adds groups of 8 consecutive rows as
+// ((x0+x1)+(x2+x3))+((x4+x5)+(x6+x7)), i.e. three levels of the binary tree,
+// until one row remains.  The final kernel turns the sums into means and
+// standard errors.  The work is HBM-bound and tiny next to propagation.
+#include <algorithm>
+
+#include "qcl_internal.hpp"
+
+namespace qcl {
+namespace {
+
+__global__ __launch_bounds__(256) void pairwise8_kernel(const double *__restrict__ in, int64_t rows_in, int64_t cols,
+                                                        double *__restrict__ out)
+{
+    const int64_t rows_out = (rows_in + 7) / 8;
+    const int64_t n = rows_out * cols;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = idx / cols, c = idx - r * cols;
+        double x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t rr = 8 * r + k;
+            x[k] = rr < rows_in ? in[rr * cols + c] : 0.0;
+        }
+        out[idx] = ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7]));
+    }
+}
+
+// sums [n_out][2][N][N][4] (Re, Im, Re^2, Im^2) -> (mean Re, mean Im, SE Re, SE Im)
+__global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict__ sums, int64_t n_groups, double T,
+                                                       double *__restrict__ out)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups)
+        return;
+    const double s0 = sums[4 * g + 0], s1 = sums[4 * g + 1], s2 = sums[4 * g + 2], s3 = sums[4 * g + 3];
+    const double vr = (s2 - s0 * s0 / T) / (T * (T - 1.0));
+    const double vi = (s3 - s1 * s1 / T) / (T * (T - 1.0));
+    out[4 * g + 0] = s0 / T;
+    out[4 * g + 1] = s1 / T;
+    out[4 * g + 2] = (T > 1.0 && vr > 0.0) ? sqrt(vr) : 0.0;
+    out[4 * g + 3] = (T > 1.0 && vi > 0.0) ? sqrt(vi) : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_reduce(int n_states, double *partials, int64_t n_traj, int32_t n_out, double *out, hipStream_t s)
+{
+    const int64_t tiles = n_tiles(n_traj);
+    const int64_t cols = (int64_t)n_out * tile_values(n_states);
+    double *scratch_a = partials + tiles * cols;
+    double *scratch_b = scratch_a + ((tiles + 7) / 8) * cols;
+    const double *src = partials;
+    int64_t rows = tiles;
+    bool to_a = true;
+    while (rows > 1) {
+        double *dst = to_a ? scratch_a : scratch_b;
+        const int64_t rows_out = (rows + 7) / 8;
+        const int64_t work = rows_out * cols;
+        const int64_t blocks = std::min<int64_t>((work + 255) / 256, 8192);
+        hipLaunchKernelGGL(pairwise8_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, rows, cols, dst);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess)
+            return err;
+        src = dst;
+        rows = rows_out;
+        to_a = !to_a;
+    }
+    const int64_t groups = cols / 4;
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, src, groups,
+                       (double)n_traj, out);
+    return hipGetLastError();
+}
+
+}  // namespace qcl

@@ -1,0 +1,301 @@
+"""Python binding of libqcl (the C ABI in include/qcl.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of libqcl.so.  PyTorch provides device memory and streams.  The
+library must have been built (``python -m paper_2608_14544_amd.build``);
+there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libqcl.so")
+
+QCL_OK = 0
+QCL_ERR_INVALID_ARG = 1
+QCL_ERR_UNSUPPORTED = 2
+QCL_ERR_OUT_OF_MEMORY = 3
+QCL_ERR_DEVICE = 4
+
+QCL_FP64 = 0
+QCL_FP32_ACC64 = 1
+QCL_INIT_DIABATIC = 0
+QCL_INIT_ADIABATIC = 1
+QCL_TRANS_NORMALIZED = 0
+QCL_TRANS_LINEAR = 1
+QCL_TILE = 256
+
+FLAG_NONFINITE = 1
+FLAG_DEGENERATE = 2
+FLAG_RESOLVED64 = 4
+FLAG_FALLBACK = 8
+
+PRECISIONS = {"fp64": QCL_FP64, "fp32": QCL_FP32_ACC64, "f64": QCL_FP64, "f32": QCL_FP32_ACC64}
+
+
+class QCLError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"qcl status {status}: {msg}")
+        self.status = status
+
+
+class qcl_model_desc(C.Structure):
+    _fields_ = [("n_states", C.c_int32), ("n_modes", C.c_int32),
+                ("mass", C.POINTER(C.c_double)), ("omega", C.POINTER(C.c_double)),
+                ("v0", C.POINTER(C.c_double)), ("k", C.POINTER(C.c_double)),
+                ("hbar", C.c_double)]
+
+
+class qcl_init_desc(C.Structure):
+    _fields_ = [("kT", C.c_double), ("q0", C.POINTER(C.c_double)),
+                ("state", C.c_int32), ("basis", C.c_int32)]
+
+
+class qcl_ensemble(C.Structure):
+    _fields_ = [("n_traj", C.c_int64), ("ld", C.c_int64), ("traj_offset", C.c_int64),
+                ("step", C.c_int64), ("prec", C.c_int32), ("reserved", C.c_int32),
+                ("q", C.c_void_p), ("p", C.c_void_p), ("u", C.c_void_p),
+                ("w", C.c_void_p), ("phase", C.c_void_p), ("a", C.c_void_p),
+                ("b", C.c_void_p), ("flags", C.c_void_p)]
+
+
+class qcl_prop_desc(C.Structure):
+    _fields_ = [("dt", C.c_double), ("n_steps", C.c_int32), ("cadence", C.c_int32),
+                ("n_out", C.c_int32), ("scheme", C.c_int32), ("seed", C.c_uint64),
+                ("block", C.c_int32), ("reserved", C.c_int32)]
+
+
+EXPORTS = ("qcl_create_model", "qcl_destroy_model", "qcl_model_states", "qcl_model_modes",
+           "qcl_ensemble_bytes", "qcl_ensemble_bind", "qcl_partials_bytes",
+           "qcl_sample_initial", "qcl_propagate", "qcl_reduce_observables", "qcl_last_error")
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libqcl.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2608_14544_amd.build`")
+        L = C.CDLL(path)
+        vp, i32, i64, u64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
+        L.qcl_create_model.argtypes = [C.POINTER(qcl_model_desc), C.POINTER(vp)]
+        L.qcl_destroy_model.argtypes = [vp]
+        L.qcl_model_states.argtypes = [vp]
+        L.qcl_model_states.restype = i32
+        L.qcl_model_modes.argtypes = [vp]
+        L.qcl_model_modes.restype = i32
+        L.qcl_ensemble_bytes.argtypes = [vp, i64, i32, C.POINTER(i64), C.POINTER(sz)]
+        L.qcl_ensemble_bind.argtypes = [vp, vp, i64, i32, i64, C.POINTER(qcl_ensemble)]
+        L.qcl_partials_bytes.argtypes = [vp, i64, i32, C.POINTER(sz)]
+        L.qcl_sample_initial.argtypes = [vp, C.POINTER(qcl_init_desc), u64, C.POINTER(qcl_ensemble),
+                                         vp, i32, vp]
+        L.qcl_propagate.argtypes = [vp, C.POINTER(qcl_ensemble), C.POINTER(qcl_prop_desc), vp, vp]
+        L.qcl_reduce_observables.argtypes = [vp, vp, i64, i32, vp, vp]
+        L.qcl_last_error.argtypes = []
+        L.qcl_last_error.restype = C.c_char_p
+        for name in EXPORTS[:-1]:
+            if getattr(L, name).restype is C.c_int:
+                getattr(L, name).restype = C.c_int
+        _lib = L
+        return _lib
+
+
+def _check(status: int):
+    if status != QCL_OK:
+        msg = load_library().qcl_last_error()
+        raise QCLError(status, msg.decode() if msg else "")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> Optional[int]:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# --------------------------------------------------------------------- model
+
+class Model:
+    """Library-owned model handle built from a ``workloads.LVCModel``."""
+
+    def __init__(self, lvc):
+        L = load_library()
+        self.lvc = lvc
+        self._arrays = [np.ascontiguousarray(x, np.float64) for x in (lvc.mass, lvc.omega, lvc.v0, lvc.k)]
+        mass, omega, v0, k = self._arrays
+        desc = qcl_model_desc(int(v0.shape[0]), int(mass.shape[0]), _dptr(mass), _dptr(omega),
+                              _dptr(v0), _dptr(k), float(lvc.hbar))
+        h = C.c_void_p()
+        _check(L.qcl_create_model(C.byref(desc), C.byref(h)))
+        self.handle = h
+        self.n_states = int(L.qcl_model_states(h))
+        self.n_modes = int(L.qcl_model_modes(h))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().qcl_destroy_model(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def partials_bytes(self, n_traj: int, n_out: int) -> int:
+        b = C.c_size_t()
+        _check(load_library().qcl_partials_bytes(self.handle, int(n_traj), int(n_out), C.byref(b)))
+        return int(b.value)
+
+
+# ------------------------------------------------------------------ ensemble
+
+class Ensemble:
+    """Device-resident walker ensemble in one torch allocation."""
+
+    def __init__(self, model: Model, n_traj: int, prec="fp64", traj_offset: int = 0, device="cuda"):
+        torch = _torch()
+        L = load_library()
+        self.model = model
+        self.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        ld = C.c_int64()
+        nbytes = C.c_size_t()
+        _check(L.qcl_ensemble_bytes(model.handle, int(n_traj), self.prec, C.byref(ld), C.byref(nbytes)))
+        self.buffer = torch.zeros(int(nbytes.value), dtype=torch.uint8, device=device)
+        self.c = qcl_ensemble()
+        _check(L.qcl_ensemble_bind(model.handle, C.c_void_p(self.buffer.data_ptr()), int(n_traj), self.prec,
+                                   int(traj_offset), C.byref(self.c)))
+        self.n_traj = int(n_traj)
+        self.ld = int(ld.value)
+
+    @property
+    def step(self) -> int:
+        return int(self.c.step)
+
+    def _view(self, ptr, dtype, shape):
+        torch = _torch()
+        base = self.buffer.data_ptr()
+        off = int(ptr) - base
+        itemsize = torch.tensor([], dtype=dtype).element_size()
+        n = int(np.prod(shape))
+        return self.buffer[off:off + n * itemsize].view(dtype).view(*shape)
+
+    def tensors(self):
+        """Torch views of the arrays: q, p [M, ld], u [N*N, ld], w, phase, a, b, flags [ld]."""
+        torch = _torch()
+        rt = torch.float64 if self.prec == QCL_FP64 else torch.float32
+        M, N, ld = self.model.n_modes, self.model.n_states, self.ld
+        c = self.c
+        return {
+            "q": self._view(c.q, rt, (M, ld)), "p": self._view(c.p, rt, (M, ld)),
+            "u": self._view(c.u, rt, (N * N, ld)),
+            "w": self._view(c.w, torch.float64, (ld,)), "phase": self._view(c.phase, torch.float64, (ld,)),
+            "a": self._view(c.a, torch.uint8, (ld,)), "b": self._view(c.b, torch.uint8, (ld,)),
+            "flags": self._view(c.flags, torch.int32, (ld,)),
+        }
+
+    def to_numpy(self):
+        """Per-walker arrays in walker-major layout: q, p [T, M], U [T, N, N]."""
+        T, N = self.n_traj, self.model.n_states
+        t = {k: v.cpu().numpy() for k, v in self.tensors().items()}
+        return {
+            "q": t["q"][:, :T].T.astype(np.float64), "p": t["p"][:, :T].T.astype(np.float64),
+            "U": t["u"][:, :T].T.reshape(T, N, N).astype(np.float64),
+            "w": t["w"][:T].copy(), "phase": t["phase"][:T].copy(),
+            "a": t["a"][:T].astype(np.int32), "b": t["b"][:T].astype(np.int32),
+            "flags": t["flags"][:T].view(np.uint32).copy(),
+        }
+
+    def load_numpy(self, state):
+        """Writes walker-major arrays (oracle layout) into the device ensemble."""
+        torch = _torch()
+        T, N = self.n_traj, self.model.n_states
+        t = self.tensors()
+        dev = self.buffer.device
+        rt = t["q"].dtype
+        t["q"][:, :T] = torch.as_tensor(np.ascontiguousarray(state["q"].T), device=dev).to(rt)
+        t["p"][:, :T] = torch.as_tensor(np.ascontiguousarray(state["p"].T), device=dev).to(rt)
+        t["u"][:, :T] = torch.as_tensor(np.ascontiguousarray(state["U"].reshape(T, N * N).T), device=dev).to(rt)
+        t["w"][:T] = torch.as_tensor(state["w"], device=dev)
+        t["phase"][:T] = torch.as_tensor(state["phase"], device=dev)
+        t["a"][:T] = torch.as_tensor(state["a"].astype(np.uint8), device=dev)
+        t["b"][:T] = torch.as_tensor(state["b"].astype(np.uint8), device=dev)
+        t["flags"][:T] = 0
+        self.c.step = int(state.get("step", 0))
+
+
+class Partials:
+    def __init__(self, model: Model, n_traj: int, n_out: int, device="cuda"):
+        torch = _torch()
+        nb = model.partials_bytes(n_traj, n_out)
+        self.tensor = torch.zeros(max(nb // 8, 1), dtype=torch.float64, device=device)
+        self.n_out = int(n_out)
+        self.n_traj = int(n_traj)
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.tensor.data_ptr())
+
+
+# ------------------------------------------------------------- entry points
+
+def qcl_sample_initial(model: Model, init, seed: int, ens: Ensemble, partials: Partials, stream=None):
+    q0 = np.ascontiguousarray(init.q0, np.float64)
+    d = qcl_init_desc(float(init.kT), _dptr(q0), int(init.state), int(init.basis))
+    _check(load_library().qcl_sample_initial(model.handle, C.byref(d), C.c_uint64(int(seed)), C.byref(ens.c),
+                                             partials.ptr, partials.n_out, C.c_void_p(_stream_handle(stream))))
+
+
+def qcl_propagate(model: Model, ens: Ensemble, dt: float, n_steps: int, cadence: int, seed: int,
+                  partials: Partials, scheme: int = QCL_TRANS_NORMALIZED, stream=None):
+    pd = qcl_prop_desc(float(dt), int(n_steps), int(cadence), partials.n_out, int(scheme), int(seed), 0, 0)
+    _check(load_library().qcl_propagate(model.handle, C.byref(ens.c), C.byref(pd), partials.ptr,
+                                        C.c_void_p(_stream_handle(stream))))
+
+
+def qcl_reduce_observables(model: Model, partials: Partials, n_traj: int, out=None, stream=None):
+    """Returns a device tensor [n_out, 2, N, N, 4]: mean Re, mean Im, SE Re, SE Im."""
+    torch = _torch()
+    N = model.n_states
+    if out is None:
+        out = torch.empty((partials.n_out, 2, N, N, 4), dtype=torch.float64, device=partials.tensor.device)
+    _check(load_library().qcl_reduce_observables(model.handle, partials.ptr, int(n_traj), partials.n_out,
+                                                 C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(stream))))
+    return out
+
+
+def run(workload, prec="fp64", n_traj: Optional[int] = None, n_steps: Optional[int] = None,
+        scheme: int = QCL_TRANS_NORMALIZED, traj_offset: int = 0, model: Optional[Model] = None):
+    """Sample, propagate and reduce one workload; returns (out numpy, Ensemble)."""
+    torch = _torch()
+    r = workload.run
+    T = r.n_traj if n_traj is None else int(n_traj)
+    S = r.n_steps if n_steps is None else int(n_steps)
+    n_out = S // r.cadence + 1
+    model = model or Model(workload.model)
+    ens = Ensemble(model, T, prec, traj_offset)
+    part = Partials(model, T, n_out)
+    qcl_sample_initial(model, workload.init, r.seed, ens, part)
+    qcl_propagate(model, ens, r.dt, S, r.cadence, r.seed, part, scheme)
+    out = qcl_reduce_observables(model, part, T)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ens

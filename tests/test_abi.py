@@ -1,0 +1,93 @@
+"""The C-ABI library: it loads, exports every symbol include/qcl.h declares,
+and rejects invalid model descriptions on the host before touching a
+device (no compute call is made here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2608_14544_amd import qcl
+    if not os.path.exists(qcl.LIB_PATH):
+        from paper_2608_14544_amd import build
+        build.build()
+    return qcl, qcl.load_library()
+
+
+def _declared():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"\b(qcl_[a-z0-9_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol():
+    qcl, L = _lib()
+    decl = _declared()
+    assert "qcl_propagate" in decl and "qcl_sample_initial" in decl
+    for name in decl:
+        assert hasattr(L, name), name
+    assert set(decl) == set(qcl.EXPORTS)
+
+
+def _desc(qcl, lvc, **over):
+    mass = np.ascontiguousarray(over.get("mass", lvc.mass), np.float64)
+    omega = np.ascontiguousarray(over.get("omega", lvc.omega), np.float64)
+    v0 = np.ascontiguousarray(over.get("v0", lvc.v0), np.float64)
+    k = np.ascontiguousarray(over.get("k", lvc.k), np.float64)
+    keep = (mass, omega, v0, k)
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    d = qcl.qcl_model_desc(over.get("n_states", v0.shape[0]), over.get("n_modes", mass.shape[0]),
+                           dp(mass), dp(omega), dp(v0), dp(k), over.get("hbar", lvc.hbar))
+    return d, keep
+
+
+@pytest.mark.parametrize("case", [
+    dict(n_states=1), dict(n_states=5), dict(n_modes=0), dict(n_modes=129), dict(hbar=0.0),
+    dict(hbar=float("nan")), dict(mass=[-1.0, 1.0, 1.0]), dict(omega=[1.0, 0.0, 1.0]),
+    dict(v0=[[0.0, 0.1], [0.2, 0.0]]), dict(k=np.array([[[0, 1], [0, 0]]] * 3, float)),
+    dict(v0=[[np.inf, 0.0], [0.0, 0.0]]),
+])
+def test_create_model_rejects_invalid(case):
+    qcl, L = _lib()
+    lvc = W.pyrazine_ci().model
+    d, keep = _desc(qcl, lvc, **case)
+    h = C.c_void_p()
+    st = L.qcl_create_model(C.byref(d), C.byref(h))
+    assert st == qcl.QCL_ERR_INVALID_ARG, (case, st, L.qcl_last_error())
+    assert not h.value
+    assert L.qcl_last_error()
+
+
+def test_null_arguments_rejected():
+    qcl, L = _lib()
+    assert L.qcl_create_model(None, None) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_destroy_model(None) == qcl.QCL_OK
+    ld = C.c_int64()
+    b = C.c_size_t()
+    assert L.qcl_ensemble_bytes(None, 10, 0, C.byref(ld), C.byref(b)) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_partials_bytes(None, 10, 1, C.byref(b)) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_propagate(None, None, None, None, None) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_sample_initial(None, None, 0, None, None, 1, None) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_reduce_observables(None, None, 1, 1, None, None) == qcl.QCL_ERR_INVALID_ARG
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_2608_14544_amd import qcl
+    with pytest.raises(RuntimeError):
+        old = qcl._lib
+        qcl._lib = None
+        try:
+            qcl.load_library(str(tmp_path / "missing.so"))
+        finally:
+            qcl._lib = old

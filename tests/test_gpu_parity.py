@@ -1,0 +1,278 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (the headline configurations fix them):
+  * FP64 path, per walker: q, p, U, Phi within 1e-10 relative to
+    max(|value|, ensemble rms of that quantity), w within 1e-10 relative;
+    walkers whose transition decisions differ ("flips": a different final
+    element or |w| off by > 1e-6) are counted, reported and excluded.
+  * FP64 path, ensemble averages: within 1e-9 absolute.
+  * FP32 path (binary32 propagation, binary64 phase/weights/sums):
+    ensemble averages within 1e-3 absolute or 3 standard errors.
+Integer state (element indices) must match exactly for non-flipped walkers.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle.core as oc
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2608_14544_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def _oracle_state(st):
+    return {"q": st.q, "p": st.p, "U": st.U, "w": st.w, "phase": st.phase, "a": st.a, "b": st.b}
+
+
+def compare_walkers(g, o, rtol=1e-10, max_flip_frac=0.0, label=""):
+    flip = (g["a"] != o["a"]) | (g["b"] != o["b"])
+    flip |= ~(np.abs(np.abs(g["w"]) - np.abs(o["w"])) <= 1e-6 * np.abs(o["w"]))
+    ok = ~flip
+    worst = {}
+    for key in ("q", "p", "U", "phase"):
+        gv, ov = g[key][ok], o[key][ok]
+        scale = np.sqrt(np.mean(o[key] ** 2)) if o[key].size else 1.0
+        err = np.abs(gv - ov) / np.maximum(np.abs(ov), scale)
+        worst[key] = float(err.max()) if err.size else 0.0
+    errw = np.abs(g["w"][ok] - o["w"][ok]) / np.abs(o["w"][ok])
+    worst["w"] = float(errw.max()) if errw.size else 0.0
+    print(f"[{label}] walkers={len(ok)} flips={int(flip.sum())} worst-rel={worst}", flush=True)
+    assert flip.sum() <= max_flip_frac * len(ok), (label, int(flip.sum()))
+    for key, v in worst.items():
+        assert v <= rtol, (label, key, v)
+    return int(flip.sum())
+
+
+def gpu_run(P, wl, prec="fp64", n_traj=None, n_steps=None, scheme=0, split=None):
+    import torch
+    r = wl.run
+    T = r.n_traj if n_traj is None else n_traj
+    S = r.n_steps if n_steps is None else n_steps
+    n_out = S // r.cadence + 1
+    model = P.Model(wl.model)
+    ens = P.Ensemble(model, T, prec)
+    part = P.Partials(model, T, n_out)
+    P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
+    sample_state = ens.to_numpy()
+    chunks = [S] if split is None else split
+    assert sum(chunks) == S
+    for c in chunks:
+        P.qcl_propagate(model, ens, r.dt, c, r.cadence, r.seed, part, scheme)
+    out = P.qcl_reduce_observables(model, part, T) if T > 0 else None
+    torch.cuda.synchronize()
+    return (out.cpu().numpy() if out is not None else None), ens.to_numpy(), sample_state, ens
+
+
+def oracle_run(wl, n_traj=None, n_steps=None, scheme=0):
+    r = wl.run
+    T = r.n_traj if n_traj is None else n_traj
+    S = r.n_steps if n_steps is None else n_steps
+    n_out = S // r.cadence + 1
+    m = oc.Model(wl.model)
+    st, s0 = oc.sample(m, wl.init, r.seed, T)
+    samp = _oracle_state(st.copy())
+    sums = np.zeros((n_out, 2, m.n, m.n, 4))
+    sums[0] = s0
+    oc.propagate(m, st, r.dt, S, r.cadence, r.seed, n_out, sums, scheme)
+    return oc.finalize(sums, T), _oracle_state(st), samp, st.flags
+
+
+# ------------------------------------------------------------------ FP64
+
+def test_spin_boson_1mode_fp64_full(P):
+    wl = W.spin_boson_1mode()
+    out_g, st_g, s0_g, _ = gpu_run(P, wl)
+    out_o, st_o, s0_o, _ = oracle_run(wl)
+    compare_walkers(s0_g, s0_o, rtol=1e-12, label="sample")
+    compare_walkers(st_g, st_o, label="cfg0 end")
+    err = np.abs(out_g[..., :2] - out_o[..., :2]).max()
+    print("ensemble max abs err", err, flush=True)
+    assert err <= 1e-9
+    np.testing.assert_allclose(out_g[..., 2:], out_o[..., 2:], rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("name,T,S", [("ohmic", 3000, 400), ("pyrazine", 3000, 200),
+                                      ("zero", 700, 100), ("harmonic", 513, 90)])
+def test_fp64_parity_models(P, name, T, S):
+    wl = {"ohmic": W.spin_boson_ohmic(kT=1.0, cadence=20), "pyrazine": W.pyrazine_ci(),
+          "zero": W.zero_coupling(), "harmonic": W.uncoupled_harmonic()}[name]
+    S = (S // wl.run.cadence) * wl.run.cadence
+    out_g, st_g, s0_g, _ = gpu_run(P, wl, n_traj=T, n_steps=S)
+    out_o, st_o, s0_o, _ = oracle_run(wl, n_traj=T, n_steps=S)
+    compare_walkers(s0_g, s0_o, rtol=1e-12, label=name + " sample")
+    nflip = compare_walkers(st_g, st_o, max_flip_frac=0.002, label=name)
+    if nflip == 0:
+        assert np.abs(out_g[..., :2] - out_o[..., :2]).max() <= 1e-9
+
+
+@pytest.mark.parametrize("T", [1, 63, 255, 256, 257, 1000])
+def test_ragged_sizes(P, T):
+    wl = W.spin_boson_1mode(n_steps=40, cadence=7)
+    S = 40
+    out_g, st_g, _, _ = gpu_run(P, wl, n_traj=T, n_steps=S)
+    out_o, st_o, _, _ = oracle_run(wl, n_traj=T, n_steps=S)
+    compare_walkers(st_g, st_o, label=f"T={T}")
+    assert np.abs(out_g[..., :2] - out_o[..., :2]).max() <= 1e-9
+
+
+def test_linear_scheme_parity(P):
+    wl = W.spin_boson_1mode(n_traj=4000, n_steps=100)
+    out_g, st_g, _, _ = gpu_run(P, wl, scheme=1)
+    out_o, st_o, _, _ = oracle_run(wl, scheme=1)
+    compare_walkers(st_g, st_o, label="linear")
+    assert np.abs(out_g[..., :2] - out_o[..., :2]).max() <= 1e-9
+
+
+def test_empty_ensemble(P):
+    import torch
+    wl = W.spin_boson_1mode()
+    model = P.Model(wl.model)
+    ens = P.Ensemble(model, 0, "fp64")
+    part = P.Partials(model, 0, 3)
+    P.qcl_sample_initial(model, wl.init, 0, ens, part)
+    P.qcl_propagate(model, ens, 0.05, 20, 10, 0, part)
+    assert ens.step == 20
+    with pytest.raises(P.QCLError):
+        P.qcl_reduce_observables(model, part, 0)
+    torch.cuda.synchronize()
+
+
+def test_invalid_calls_launch_nothing(P):
+    wl = W.spin_boson_1mode()
+    model = P.Model(wl.model)
+    ens = P.Ensemble(model, 100, "fp64")
+    part = P.Partials(model, 100, 3)
+    P.qcl_sample_initial(model, wl.init, 0, ens, part)
+    before = ens.to_numpy()
+    for kw in (dict(dt=0.0), dict(dt=float("nan")), dict(cadence=0), dict(n_steps=-1), dict(n_steps=40)):
+        args = dict(dt=0.05, n_steps=20, cadence=10)
+        args.update(kw)
+        with pytest.raises(P.QCLError) as ei:
+            P.qcl_propagate(model, ens, args["dt"], args["n_steps"], args["cadence"], 0, part)
+        assert ei.value.status == 1
+    after = ens.to_numpy()
+    assert ens.step == 0
+    for k in before:
+        assert np.array_equal(before[k], after[k])
+
+
+# ------------------------------------------------------------ determinism
+
+def test_bitwise_repeat_and_slicing(P):
+    wl = W.pyrazine_ci(n_traj=5000, n_steps=120)
+    for prec in ("fp64", "fp32"):
+        out1, st1, _, _ = gpu_run(P, wl, prec=prec)
+        out2, st2, _, _ = gpu_run(P, wl, prec=prec)
+        out3, st3, _, _ = gpu_run(P, wl, prec=prec, split=[37, 3, 50, 30])
+        for k in st1:
+            assert np.array_equal(st1[k], st2[k]), (prec, k)
+            assert np.array_equal(st1[k], st3[k]), (prec, k)
+        assert np.array_equal(out1, out2) and np.array_equal(out1, out3), prec
+
+
+def test_traj_offset_reproduces_slice(P):
+    import torch
+    wl = W.pyrazine_ci(n_traj=3000, n_steps=60)
+    _, full, _, _ = gpu_run(P, wl)
+    model = P.Model(wl.model)
+    ens = P.Ensemble(model, 1000, "fp64", traj_offset=2000)
+    part = P.Partials(model, 1000, wl.run.n_out)
+    P.qcl_sample_initial(model, wl.init, wl.run.seed, ens, part)
+    P.qcl_propagate(model, ens, wl.run.dt, 60, wl.run.cadence, wl.run.seed, part)
+    torch.cuda.synchronize()
+    sl = ens.to_numpy()
+    for k in sl:
+        assert np.array_equal(sl[k], full[k][2000:]), k
+
+
+# ------------------------------------------------------------- FP32 path
+
+@pytest.mark.parametrize("name", ["spin_boson_1mode", "ohmic", "pyrazine"])
+def test_fp32_ensemble_vs_oracle(P, name):
+    wl = {"spin_boson_1mode": W.spin_boson_1mode(n_traj=100_000, n_steps=100),
+          "ohmic": W.spin_boson_ohmic(kT=0.2, n_traj=50_000, n_steps=400, cadence=40),
+          "pyrazine": W.pyrazine_ci(n_traj=100_000, n_steps=100)}[name]
+    out_g, st_g, _, _ = gpu_run(P, wl, prec="fp32")
+    out_o, _, _, _ = oracle_run(wl)
+    d = np.abs(out_g[..., :2] - out_o[..., :2])
+    se = np.maximum(out_o[..., 2:], 1e-300)
+    bad = (d > 1e-3) & (d > 3 * se)
+    print(name, "fp32 max abs err", d.max(), "max err/SE", (d / se).max(), flush=True)
+    assert not bad.any()
+
+
+# --------------------------------------------------------- whole estimator
+
+def test_gpu_matches_grid_solution(P):
+    with open(os.path.join(GOLDEN, "grid_spin_boson_1mode.json")) as f:
+        d = json.load(f)
+    rho = np.array(d["rho_re"]) + 1j * np.array(d["rho_im"])
+    dt = 0.0125
+    wl = W.spin_boson_1mode(n_traj=1_000_000, n_steps=int(round(3.0 / dt)), dt=dt,
+                            cadence=int(round(0.5 / dt)), seed=77)
+    for prec in ("fp64", "fp32"):
+        out, _, _, _ = gpu_run(P, wl, prec=prec)
+        n = out.shape[0]
+        g = rho[:n]
+        zr = np.abs(out[..., 0] - g.real) - 4.5 * out[..., 2]
+        zi = np.abs(out[..., 1] - g.imag) - 4.5 * out[..., 3]
+        print(prec, "grid excess", zr.max(), zi.max(), flush=True)
+        assert zr.max() <= 0.4 * dt and zi.max() <= 0.4 * dt
+
+
+# ------------------------------------------ headline size, sampled walkers
+
+def test_pyrazine_full_size_sampled_walkers(P):
+    """The conical-intersection workload at its full size (1e7 walkers,
+    1000 steps) in the benchmark's launch configuration: sampled walkers
+    are recomputed one by one by the oracle, and ensemble invariants are
+    checked on the full reduction."""
+    import torch
+    wl = W.pyrazine_ci()
+    r = wl.run
+    model = P.Model(wl.model)
+    ens = P.Ensemble(model, r.n_traj, "fp64")
+    part = P.Partials(model, r.n_traj, r.n_out)
+    P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
+    P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part)
+    out = P.qcl_reduce_observables(model, part, r.n_traj).cpu().numpy()
+    torch.cuda.synchronize()
+    t = ens.tensors()
+    rng = np.random.default_rng(0)
+    ids = np.unique(np.concatenate([[0, 1, 255, 256, r.n_traj - 1], rng.integers(0, r.n_traj, 59)]))
+    g = {"q": t["q"][:, ids].cpu().numpy().T, "p": t["p"][:, ids].cpu().numpy().T,
+         "U": t["u"][:, ids].cpu().numpy().T.reshape(-1, 2, 2), "w": t["w"][ids].cpu().numpy(),
+         "phase": t["phase"][ids].cpu().numpy(), "a": t["a"][ids].cpu().numpy().astype(np.int32),
+         "b": t["b"][ids].cpu().numpy().astype(np.int32)}
+    m = oc.Model(wl.model)
+    o = {k: [] for k in g}
+    for i in ids:
+        st, _ = oc.sample(m, wl.init, r.seed, 1, traj_offset=int(i))
+        oc.propagate(m, st, r.dt, r.n_steps, r.cadence, r.seed, r.n_out)
+        for k, v in _oracle_state(st).items():
+            o[k].append(v[0])
+    o = {k: np.array(v) for k, v in o.items()}
+    # 1000 steps through a conical intersection amplify rounding; a few
+    # walkers may take a different branch
+    compare_walkers(g, o, rtol=1e-8, max_flip_frac=0.05, label="pyrazine 1e7 sampled")
+    # ensemble invariants at early times (trace 1, Hermiticity) within 5 SE
+    for o_ in range(0, 11):
+        tr = out[o_, 0, 0, 0, 0] + out[o_, 0, 1, 1, 0]
+        se = math.hypot(out[o_, 0, 0, 0, 2], out[o_, 0, 1, 1, 2])
+        assert abs(tr - 1) <= 5 * se + 1e-12, (o_, tr, se)
+        h = out[o_, 0, 0, 1, 0] - out[o_, 0, 1, 0, 0]
+        assert abs(h) <= 5 * math.hypot(out[o_, 0, 0, 1, 2], out[o_, 0, 1, 0, 2]) + 1e-12
+    assert out[0, 1, 1, 1, 0] == pytest.approx(1.0, abs=5 * out[0, 1, 1, 1, 2])
