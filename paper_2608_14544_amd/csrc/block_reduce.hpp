@@ -3,10 +3,10 @@
 // A workgroup of kBlock walkers (4 wavefronts) sums V values per walker.
 // Inside a wavefront the sums follow the pairwise tree over lanes
 // ((0+1)+(2+3))+...: a reduce-scatter butterfly in which, at the stage
-// with lane distance d, each lane keeps half of its remaining values and
-// adds the partner's copy of that half.  Every value therefore meets the
-// same pairs as in the plain pairwise tree, but the wavefront moves only
-// V - 1 values instead of 6 V.  Across the 4 wavefronts the tree continues
+// with lane distance d, each lane keeps half of its remaining values,
+// summed with the partner lane's copy.  Every value therefore meets the
+// same pairs as in the plain pairwise tree, while each stage halves the
+// number of values a lane carries.  Across the 4 wavefronts the tree continues
 // in LDS as (w0 + w1) + (w2 + w3).  Together with the pairwise tree over
 // tiles this makes every sum a perfect binary tree over the walker index,
 // independent of launch geometry.
@@ -31,10 +31,12 @@ __device__ __forceinline__ void wave_reduce_scatter(double (&v)[V], int lane)
             const bool upper = (lane & off) != 0;
 #pragma unroll
             for (int i = 0; i < half; ++i) {
-                const double send = upper ? v[i] : v[i + half];
-                const double keep = upper ? v[i + half] : v[i];
-                const double recv = __shfl_xor(send, off, 64);
-                v[i] = keep + recv;
+                // both halves cross the lane pair; each lane keeps the sum of
+                // the half it owns (selecting sums, not array elements, keeps
+                // the array in registers)
+                const double lo = v[i] + __shfl_xor(v[i], off, 64);
+                const double hi = v[i + half] + __shfl_xor(v[i + half], off, 64);
+                v[i] = upper ? hi : lo;
             }
         } else {
             v[0] = v[0] + __shfl_xor(v[0], off, 64);

@@ -15,6 +15,7 @@
 //     v.d_01 = [dl_v (U00 U01 - U10 U11) + c_v (U00 U11 + U10 U01)] / (2 r),
 // with dl_v = sum_j v_j dlt_j, c_v = sum_j v_j cpl_j.
 #include "block_reduce.hpp"
+#include "phase_math.hpp"
 #include "philox.hpp"
 #include "qcl_internal.hpp"
 
@@ -87,7 +88,7 @@ __device__ __forceinline__ void coupling_coords(const N2Const<M, R> &C, const R 
 
 // binary64 re-solve of a near-degenerate point for the binary32 path
 template <int M>
-__device__ __noinline__ void resolve64(const N2Const<M, float> &C, const float (&q)[M], Frame2<float> &e)
+__device__ __forceinline__ void resolve64(const N2Const<M, float> &C, const float (&q)[M], Frame2<float> &e)
 {
     double dl = C.dlt0_64, cc = C.c0_64;
 #pragma unroll
@@ -124,7 +125,7 @@ __device__ __forceinline__ void bin_values(double (&v)[32], bool live, int a, in
                                            const Frame2<R> &e)
 {
     double sn, cs;
-    sincos(phase, &sn, &cs);
+    sincos_phase(phase, sn, cs);
     double re = w * cs, im = -w * sn;
     const bool ok = live && isfinite(w) && isfinite(phase);
     re = ok ? re : 0.0;
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
         const double u2 = u52(x.z, x.w);
         const double rr = sqrt(-2.0 * log(u1));
         double sn, cs;
-        sincos(two_pi * u2, &sn, &cs);
+        sincos_phase(two_pi * u2, sn, cs);
         q[j] = S.q0[j] + S.sq[j] * (rr * cs);
         p[j] = S.sp[j] * (rr * sn);
     }
@@ -243,16 +244,16 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
 
 // ---------------------------------------------------------------- propagation
 
+// p += (dt/2) * mean force of element (a,b):
+// (dt/2)(F_a + F_b)/2 = -hk q - hb - (dt/2)(a+b-1)(dl dlt + cc cpl)/r
 template <int M, typename R>
-__device__ __forceinline__ void mean_force_kick(const N2Const<M, R> &C, const Frame2<R> &e, int a, int b,
+__device__ __forceinline__ void mean_force_kick(const N2Const<M, R> &C, const Frame2<R> &e, R lam,
                                                 const R (&q)[M], R (&p)[M])
 {
-    const R g = R(a + b - 1) * e.rinv;
+    const R g = lam * (C.hdt * e.rinv);
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        const R F = -(C.kq[j] * q[j]) - C.kbar[j] - g * (e.dl * C.dlt[j] + e.cc * C.cpl[j]);
-        p[j] += C.half_dt * F;
-    }
+    for (int j = 0; j < M; ++j)
+        p[j] = p[j] - C.hk[j] * q[j] - C.hb[j] - g * (e.dl * C.dlt[j] + e.cc * C.cpl[j]);
 }
 
 template <int M, typename R>
@@ -265,6 +266,7 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
     const int64_t li = live ? i : E.n_traj - 1;  // idle lanes shadow a valid walker
     const int64_t ld = E.ld;
     const uint64_t gid = (uint64_t)(E.traj_offset + li);
+    const uint32_t g_lo = (uint32_t)gid, g_hi = (uint32_t)(gid >> 32);
 
     R q[M], p[M];
 #pragma unroll
@@ -283,76 +285,77 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
     frame_at<M, R>(C, q, e, flag);
     align2<R>(e, p00, p10, p01, p11);
 
+    int64_t step = P.step0;
+    const int64_t end = P.step0 + P.n_steps;
     U4 rnd{0, 0, 0, 0};
-    for (int it = 0; it < P.n_steps; ++it) {
-        const int64_t step = P.step0 + it;
-        if (it == 0 || (step & 3) == 0)
-            rnd = philox10(U4{(uint32_t)gid, (uint32_t)(gid >> 32), (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
-        const uint32_t word = pick_word(rnd, (uint32_t)(step & 3));
+    if (step & 3)
+        rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
+    while (step < end) {
+        const int64_t next_bin = (step / P.cadence + 1) * P.cadence;
+        const int64_t stop = next_bin < end ? next_bin : end;
+        for (; step < stop; ++step) {
+            if ((step & 3) == 0)
+                rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
+            const uint32_t word = pick_word(rnd, (uint32_t)(step & 3));
 
-        // 1. Monte Carlo move between elements at (q_n, p_n)
-        R dlv = R(0), cv = R(0);
+            // 1. Monte Carlo move between elements at (q_n, p_n)
+            R dlv = R(0), cv = R(0);  // dt * sum_j v_j dlt_j, dt * sum_j v_j cpl_j
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const R vj = p[j] * C.minv[j];
-            dlv += vj * C.dlt[j];
-            cv += vj * C.cpl[j];
-        }
-        const R D01 = dlv * (e.u00 * e.u01 - e.u10 * e.u11) + cv * (e.u00 * e.u11 + e.u10 * e.u01);
-        const R x = C.dt * (D01 * (R(0.5) * e.rinv));  // dt v.d_01
-        const R f0 = a == 0 ? x : -x;                  // to (1-a, b): dt v.d_{a,1-a}
-        const R f1 = b == 0 ? x : -x;                  // to (a, 1-b): dt v.d_{b,1-b}
-        const R af0 = f0 < R(0) ? -f0 : f0;
-        const R af1 = f1 < R(0) ? -f1 : f1;
-        const R S = af0 + af1;
-        int pick = -1;
-        if (P.scheme == QCL_TRANS_LINEAR && S < R(1)) {
+            for (int j = 0; j < M; ++j) {
+                const R vj = p[j] * C.dtm[j];
+                dlv += vj * C.dlt[j];
+                cv += vj * C.cpl[j];
+            }
+            const R D01 = dlv * (e.u00 * e.u01 - e.u10 * e.u11) + cv * (e.u00 * e.u11 + e.u10 * e.u01);
+            const R x = D01 * (R(0.5) * e.rinv);  // dt v.d_01
+            const R f0 = a == 0 ? x : -x;         // to (1-a, b): dt v.d_{a,1-a}
+            const R f1 = b == 0 ? x : -x;         // to (a, 1-b): dt v.d_{b,1-b}
+            const R af0 = f0 < R(0) ? -f0 : f0;
+            const R af1 = f1 < R(0) ? -f1 : f1;
+            const R S = af0 + af1;
             R u;
             if constexpr (sizeof(R) == 4) u = u24f(word); else u = u24d(word);
-            if (u < af0) pick = 0;
-            else if (u < S) pick = 1;
-            if (pick < 0) w = w / (double)(R(1) - S);
-            else w = w * ((pick == 0 ? f0 : f1) > R(0) ? 1.0 : -1.0);
-        } else {
-            if (P.scheme == QCL_TRANS_LINEAR)
-                flag |= kFlagFallback;
-            R u;
-            if constexpr (sizeof(R) == 4) u = u24f(word); else u = u24d(word);
-            const R t = u * (R(1) + S);
-            if (!(t < R(1))) {
-                if (t < R(1) + af0) pick = 0;
-                else if (t < R(1) + S) pick = 1;
-                else pick = af1 > R(0) ? 1 : (af0 > R(0) ? 0 : -1);
+            int pick = -1;
+            if (P.scheme == QCL_TRANS_LINEAR && S < R(1)) {
+                if (u < af0) pick = 0;
+                else if (u < S) pick = 1;
+                if (pick < 0) w = w / (double)(R(1) - S);
+                else w = w * ((pick == 0 ? f0 : f1) > R(0) ? 1.0 : -1.0);
+            } else {
+                if (P.scheme == QCL_TRANS_LINEAR)
+                    flag |= kFlagFallback;
+                const R t = u * (R(1) + S);
+                if (!(t < R(1))) {
+                    if (t < R(1) + af0) pick = 0;
+                    else if (t < R(1) + S) pick = 1;
+                    else pick = af1 > R(0) ? 1 : (af0 > R(0) ? 0 : -1);
+                }
+                const double sg = pick < 0 ? 1.0 : ((pick == 0 ? f0 : f1) > R(0) ? 1.0 : -1.0);
+                w = w * (double)(R(1) + S) * sg;
             }
-            const double sg = pick < 0 ? 1.0 : ((pick == 0 ? f0 : f1) > R(0) ? 1.0 : -1.0);
-            w = w * (double)(R(1) + S) * sg;
-        }
-        if (pick == 0) a = 1 - a;
-        if (pick == 1) b = 1 - b;
+            if (pick == 0) a = 1 - a;
+            if (pick == 1) b = 1 - b;
 
-        // 2. velocity Verlet on the mean force of the current element
-        const R r_old = e.r;
-        mean_force_kick<M, R>(C, e, a, b, q, p);
+            // 2. velocity Verlet on the mean force of the current element
+            const R lam = R(a + b - 1);
+            const R r_old = e.r;
+            mean_force_kick<M, R>(C, e, lam, q, p);
 #pragma unroll
-        for (int j = 0; j < M; ++j)
-            q[j] += C.dt * (p[j] * C.minv[j]);
-        const R o00 = e.u00, o10 = e.u10, o01 = e.u01, o11 = e.u11;
-        frame_at<M, R>(C, q, e, flag);
-        align2<R>(e, o00, o10, o01, o11);
-        mean_force_kick<M, R>(C, e, a, b, q, p);
+            for (int j = 0; j < M; ++j)
+                q[j] += C.dtm[j] * p[j];
+            const R o00 = e.u00, o10 = e.u10, o01 = e.u01, o11 = e.u11;
+            frame_at<M, R>(C, q, e, flag);
+            align2<R>(e, o00, o10, o01, o11);
+            mean_force_kick<M, R>(C, e, lam, q, p);
 
-        // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar = 2 (a - b) r / hbar
-        phase += (double)(a - b) * (C.dt_hbar * ((double)r_old + (double)e.r));
-
-        // 4. output bin
-        const int64_t s1 = step + 1;
-        if (s1 % P.cadence == 0) {
-            const int64_t o = s1 / P.cadence;
-            if (o < P.n_out) {
-                double v[32];
-                bin_values<R>(v, live, a, b, w, phase, e);
-                block_reduce_store<32>(v, partials + ((int64_t)blockIdx.x * P.n_out + o) * 32, lds);
-            }
+            // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar = 2 (a - b) r / hbar
+            phase += (double)(a - b) * (C.dt_hbar * ((double)r_old + (double)e.r));
+        }
+        // 4. output bin at global step next_bin
+        if (step == next_bin && next_bin / P.cadence < P.n_out) {
+            double v[32];
+            bin_values<R>(v, live, a, b, w, phase, e);
+            block_reduce_store<32>(v, partials + ((int64_t)blockIdx.x * P.n_out + next_bin / P.cadence) * 32, lds);
         }
     }
     if (!(isfinite(w) && isfinite(phase)))
@@ -381,13 +384,14 @@ template <int M, typename R>
 N2Const<M, R> make_const(const qcl_model_s &m, double dt)
 {
     N2Const<M, R> C{};
+    const double hdt = 0.5 * dt;
     for (int j = 0; j < M; ++j) {
         const bool real = j < m.m;  // padded modes are inert
-        C.kq[j] = (R)(real ? m.kq[j] : 0.0);
-        C.minv[j] = (R)(real ? m.minv[j] : 0.0);
-        C.kbar[j] = (R)(real ? m.kbar[j] : 0.0);
         C.dlt[j] = (R)(real ? m.dlt[j] : 0.0);
         C.cpl[j] = (R)(real ? m.cpl[j] : 0.0);
+        C.hk[j] = (R)(real ? hdt * m.kq[j] : 0.0);
+        C.hb[j] = (R)(real ? hdt * m.kbar[j] : 0.0);
+        C.dtm[j] = (R)(real ? dt * m.minv[j] : 0.0);
         C.dlt64[j] = real ? m.dlt[j] : 0.0;
         C.cpl64[j] = real ? m.cpl[j] : 0.0;
     }
@@ -395,8 +399,7 @@ N2Const<M, R> make_const(const qcl_model_s &m, double dt)
     C.c0 = (R)m.c0;
     C.dlt0_64 = m.dlt0;
     C.c0_64 = m.c0;
-    C.dt = (R)dt;
-    C.half_dt = (R)(0.5 * dt);
+    C.hdt = (R)hdt;
     C.gap_thr = (R)(1e-4 * m.energy_scale);
     C.dt_hbar = dt / m.hbar;
     return C;

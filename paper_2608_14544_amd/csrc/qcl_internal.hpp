@@ -24,18 +24,18 @@ constexpr uint32_t kFlagFallback = QCL_FLAG_FALLBACK;
 // V(q) = Vbar(q) I + [[dl, cc], [cc, -dl]],
 //   dl(q) = dlt0 + sum_j dlt_j q_j,  cc(q) = c0 + sum_j cpl_j q_j,
 // the adiabatic energies are Vbar -+ r, r = sqrt(dl^2 + cc^2), and
-// dE_{0,1}/dq_j = kbar_j -+ (dl dlt_j + cc cpl_j)/r.
+// dE_{0,1}/dq_j = kbar_j -+ (dl dlt_j + cc cpl_j)/r.  Constants that only
+// ever appear multiplied by a step length are stored pre-multiplied.
 template <int M, typename R>
 struct N2Const {
-    R kq[M];    // m_j w_j^2
-    R minv[M];  // 1/m_j
-    R kbar[M];  // (K_00 + K_11)/2
     R dlt[M];   // (K_00 - K_11)/2
     R cpl[M];   // K_01
+    R hk[M];    // (dt/2) m_j w_j^2
+    R hb[M];    // (dt/2) (K_00 + K_11)/2
+    R dtm[M];   // dt/m_j
     R dlt0;     // (V0_00 - V0_11)/2
     R c0;       // V0_01
-    R dt;
-    R half_dt;
+    R hdt;      // dt/2
     R gap_thr;  // binary32 path: gaps 2r below this are re-solved in binary64
     double dt_hbar;
     // binary64 copies for the re-solve of near-degenerate points
@@ -85,7 +85,7 @@ struct qcl_model_s {
     double hbar;
     std::vector<double> mass, omega, v0, k;
     // two-state derived constants (binary64)
-    std::vector<double> kq, minv, kbar, dlt, cpl;
+    std::vector<double> kq, minv, kbar, dlt, cpl;  // m w^2, 1/m, (K00+K11)/2, (K00-K11)/2, K01
     double dlt0 = 0.0, c0 = 0.0;
     double energy_scale = 1.0;
     int device = 0;

@@ -44,7 +44,7 @@ def compare_walkers(g, o, rtol=1e-10, max_flip_frac=0.0, label=""):
     worst = {}
     for key in ("q", "p", "U", "phase"):
         gv, ov = g[key][ok], o[key][ok]
-        scale = np.sqrt(np.mean(o[key] ** 2)) if o[key].size else 1.0
+        scale = max(float(np.sqrt(np.mean(o[key] ** 2))) if o[key].size else 1.0, 1e-300)
         err = np.abs(gv - ov) / np.maximum(np.abs(ov), scale)
         worst[key] = float(err.max()) if err.size else 0.0
     errw = np.abs(g["w"][ok] - o["w"][ok]) / np.abs(o["w"][ok])
