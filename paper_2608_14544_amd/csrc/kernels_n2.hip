@@ -5,15 +5,23 @@
 // For N = 2 the adiabatic problem is solved in closed form (no iteration):
 // with V(q) = Vbar I + [[dl, cc], [cc, -dl]] the energies are Vbar -+ r,
 // r = sqrt(dl^2 + cc^2) (computed without cancellation, also near a
-// conical intersection), the upper eigenvector is (r + dl, cc) for dl >= 0
-// and (cc, r - dl) otherwise, normalised by 1/sqrt(2 r (r + |dl|)), and the
-// lower one is its 90-degree rotation.  The Hellmann-Feynman forces are
-// the gradients of Vbar -+ r, so the mean force of element (a,b) needs no
-// eigenvector at all:
-//     (F_a + F_b)_j / 2 = -m w^2 q_j - kbar_j - (a+b-1)(dl dlt_j + cc cpl_j)/r.
-// The nonadiabatic coupling uses the tracked frame U:
-//     v.d_01 = [dl_v (U00 U01 - U10 U11) + c_v (U00 U11 + U10 U01)] / (2 r),
-// with dl_v = sum_j v_j dlt_j, c_v = sum_j v_j cpl_j.
+// conical intersection).  The upper eigenvector is parallel to
+//     x = (r + dl, cc) for dl >= 0,   x = (cc, r - dl) otherwise,
+// (both forms are the same direction up to sign; each is free of
+// cancellation on its side), and the lower one to (-x1, x0).  The tracked
+// frame is U = [s0 (-x1, x0), s1 (x0, x1)] / |x| with column signs s0, s1.
+//
+// The step needs no eigenvector:
+//   * the mean force of element (a,b) is a gradient of Vbar -+ r,
+//       (F_a + F_b)_j / 2 = -m w^2 q_j - kbar_j - (a+b-1)(dl dlt_j + cc cpl_j)/r;
+//   * the velocity-projected coupling is
+//       v.d_01 = s0 s1 (dl c_v - cc dl_v) / (2 r^2),
+//     dl_v = sum_j v_j dlt_j, c_v = sum_j v_j cpl_j;
+//   * keeping each column continuous (flip when its overlap with the
+//     previous column is negative) flips s0 and s1 together, exactly when
+//     x_old . x_new < 0, so s0 s1 is constant along a walker.
+// Normalised eigenvectors are formed only for output bins and for the
+// frame stored at the end of a call.
 #include "block_reduce.hpp"
 #include "phase_math.hpp"
 #include "philox.hpp"
@@ -25,53 +33,35 @@ namespace {
 __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
 __device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
 
+// Geometry of the 2x2 problem at one point: dl, cc, r = sqrt(dl^2+cc^2),
+// 1/r and the unnormalised canonical upper eigenvector x.
 template <typename R>
-struct Frame2 {
-    R dl, cc, r, rinv;
-    R u00, u10, u01, u11;  // U_ik: column 0 = lower state, column 1 = upper
+struct Geo2 {
+    R dl, cc, r, rinv, x0, x1;
 };
 
-// Closed-form eigen-solve at (dl, cc); eigenvector signs unset.
 template <typename R>
-__device__ __forceinline__ void solve2(R dl, R cc, Frame2<R> &e)
+__device__ __forceinline__ void geo2(R dl, R cc, Geo2<R> &g)
 {
     const R r2 = dl * dl + cc * cc;
     const R rinv = rsq(r2);
     const R r = r2 * rinv;
     const bool pos = dl >= R(0);
-    const R x0 = pos ? r + dl : cc;
-    const R x1 = pos ? cc : r - dl;
-    const R nrm = rsq(R(2) * r * (r + (pos ? dl : -dl)));
-    e.dl = dl;
-    e.cc = cc;
-    e.r = r;
-    e.rinv = rinv;
-    e.u01 = x0 * nrm;  // upper eigenvector (column 1)
-    e.u11 = x1 * nrm;
-    e.u00 = -e.u11;    // lower eigenvector (column 0)
-    e.u10 = e.u01;
+    g.dl = dl;
+    g.cc = cc;
+    g.r = r;
+    g.rinv = rinv;
+    g.x0 = pos ? r + dl : cc;
+    g.x1 = pos ? cc : r - dl;
 }
 
-// Sign of each column: continuity with the previous frame (flip when the
-// overlap is negative, keep at exactly zero).
+// normalised canonical upper eigenvector (c0, c1); the lower one is (-c1, c0)
 template <typename R>
-__device__ __forceinline__ void align2(Frame2<R> &e, R p00, R p10, R p01, R p11)
+__device__ __forceinline__ void canon2(const Geo2<R> &g, R &c0, R &c1)
 {
-    const R d0 = e.u00 * p00 + e.u10 * p10;
-    const R d1 = e.u01 * p01 + e.u11 * p11;
-    if (d0 < R(0)) { e.u00 = -e.u00; e.u10 = -e.u10; }
-    if (d1 < R(0)) { e.u01 = -e.u01; e.u11 = -e.u11; }
-}
-
-// Sign of each column without a previous frame: U_kk > 0, or the first
-// nonzero entry positive when U_kk == 0.
-template <typename R>
-__device__ __forceinline__ void gauge0_2(Frame2<R> &e)
-{
-    const R l0 = e.u00 != R(0) ? e.u00 : e.u10;
-    const R l1 = e.u11 != R(0) ? e.u11 : e.u01;
-    if (l0 < R(0)) { e.u00 = -e.u00; e.u10 = -e.u10; }
-    if (l1 < R(0)) { e.u01 = -e.u01; e.u11 = -e.u11; }
+    const R n = rsq(g.x0 * g.x0 + g.x1 * g.x1);
+    c0 = g.x0 * n;
+    c1 = g.x1 * n;
 }
 
 template <int M, typename R>
@@ -88,7 +78,7 @@ __device__ __forceinline__ void coupling_coords(const N2Const<M, R> &C, const R 
 
 // binary64 re-solve of a near-degenerate point for the binary32 path
 template <int M>
-__device__ __forceinline__ void resolve64(const N2Const<M, float> &C, const float (&q)[M], Frame2<float> &e)
+__device__ __forceinline__ void resolve64(const N2Const<M, float> &C, const float (&q)[M], Geo2<float> &g)
 {
     double dl = C.dlt0_64, cc = C.c0_64;
 #pragma unroll
@@ -96,33 +86,34 @@ __device__ __forceinline__ void resolve64(const N2Const<M, float> &C, const floa
         dl += C.dlt64[j] * (double)q[j];
         cc += C.cpl64[j] * (double)q[j];
     }
-    Frame2<double> d;
-    solve2<double>(dl, cc, d);
-    e.dl = (float)d.dl; e.cc = (float)d.cc; e.r = (float)d.r; e.rinv = (float)d.rinv;
-    e.u00 = (float)d.u00; e.u10 = (float)d.u10; e.u01 = (float)d.u01; e.u11 = (float)d.u11;
+    Geo2<double> d;
+    geo2<double>(dl, cc, d);
+    g.dl = (float)d.dl; g.cc = (float)d.cc; g.r = (float)d.r; g.rinv = (float)d.rinv;
+    g.x0 = (float)d.x0; g.x1 = (float)d.x1;
 }
 
 template <int M, typename R>
-__device__ __forceinline__ void frame_at(const N2Const<M, R> &C, const R (&q)[M], Frame2<R> &e, uint32_t &flag)
+__device__ __forceinline__ void geo_at(const N2Const<M, R> &C, const R (&q)[M], Geo2<R> &g, uint32_t &flag)
 {
     R dl, cc;
     coupling_coords<M, R>(C, q, dl, cc);
-    solve2<R>(dl, cc, e);
+    geo2<R>(dl, cc, g);
     if constexpr (sizeof(R) == 4) {
-        if (!(R(2) * e.r >= C.gap_thr)) {
-            resolve64<M>(C, q, e);
+        if (!(R(2) * g.r >= C.gap_thr)) {
+            resolve64<M>(C, q, g);
             flag |= kFlagResolved;
         }
     }
-    if (!(R(2) * e.r > R(2.2250738585072014e-308)))
+    if (!(R(2) * g.r > R(2.2250738585072014e-308)))
         flag |= kFlagDegenerate;
 }
 
 // Per-walker contributions of one output bin, [slot][stat] with slots
 // 0..3 adiabatic (a*2+b) and 4..7 diabatic (i*2+j), stats Re, Im, Re^2, Im^2.
+// U_ia U_jb = (a == b ? 1 : s0 s1) C_ia C_jb with the canonical frame C.
 template <typename R>
 __device__ __forceinline__ void bin_values(double (&v)[32], bool live, int a, int b, double w, double phase,
-                                           const Frame2<R> &e)
+                                           R c0, R c1, R sig)
 {
     double sn, cs;
     sincos_phase(phase, sn, cs);
@@ -139,11 +130,13 @@ __device__ __forceinline__ void bin_values(double (&v)[32], bool live, int a, in
         v[4 * t + 2] = on ? re * re : 0.0;
         v[4 * t + 3] = on ? im * im : 0.0;
     }
-    const double ua0 = (double)(a ? e.u01 : e.u00);  // U_0a
-    const double ua1 = (double)(a ? e.u11 : e.u10);  // U_1a
-    const double ub0 = (double)(b ? e.u01 : e.u00);  // U_0b
-    const double ub1 = (double)(b ? e.u11 : e.u10);  // U_1b
-    const double c[4] = {ua0 * ub0, ua0 * ub1, ua1 * ub0, ua1 * ub1};
+    const double d0 = (double)c0, d1 = (double)c1;
+    const double ua0 = a ? d0 : -d1;  // C_0a
+    const double ua1 = a ? d1 : d0;   // C_1a
+    const double ub0 = b ? d0 : -d1;  // C_0b
+    const double ub1 = b ? d1 : d0;   // C_1b
+    const double sg = (a == b) ? 1.0 : (double)sig;
+    const double c[4] = {sg * (ua0 * ub0), sg * (ua0 * ub1), sg * (ua1 * ub0), sg * (ua1 * ub1)};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const double r = re * c[t], m = im * c[t];
@@ -178,10 +171,19 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
         q[j] = S.q0[j] + S.sq[j] * (rr * cs);
         p[j] = S.sp[j] * (rr * sn);
     }
-    Frame2<double> e;
+    Geo2<double> g;
     uint32_t flag = 0;
-    frame_at<M, double>(C, q, e, flag);
-    gauge0_2<double>(e);
+    geo_at<M, double>(C, q, g, flag);
+    double c0, c1;
+    canon2<double>(g, c0, c1);
+    // column signs without a previous frame: U_kk > 0, else the first
+    // nonzero entry of the column positive.  Column 0 = s0 (-c1, c0),
+    // column 1 = s1 (c0, c1).
+    const double l0 = (-c1 != 0.0) ? -c1 : c0;
+    const double l1 = (c1 != 0.0) ? c1 : c0;
+    const double s0 = l0 < 0.0 ? -1.0 : 1.0;
+    const double s1 = l1 < 0.0 ? -1.0 : 1.0;
+    const double u00 = -s0 * c1, u10 = s0 * c0, u01 = s1 * c0, u11 = s1 * c1;
 
     int a, b;
     double w;
@@ -191,8 +193,8 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
     } else {
         // diabatic |k><k| in the adiabatic basis: rho_ab = U_ka U_kb
         const int k = S.state;
-        const double uk0 = k ? e.u10 : e.u00;  // U_k0
-        const double uk1 = k ? e.u11 : e.u01;  // U_k1
+        const double uk0 = k ? u10 : u00;  // U_k0
+        const double uk1 = k ? u11 : u01;  // U_k1
         const double rs = fabs(uk0) + fabs(uk1);
         const double Z = rs * rs;
         const U4 x = philox10(U4{(uint32_t)gid, (uint32_t)(gid >> 32), 0u, 2u}, S.key0, S.key1);
@@ -219,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
     }
 
     double v[32];
-    bin_values<double>(v, live, a, b, w, 0.0, e);
+    bin_values<double>(v, live, a, b, w, 0.0, c0, c1, s0 * s1);
     block_reduce_store<32>(v, partials + ((int64_t)blockIdx.x * n_out + 0) * 32, lds);
 
     if (live) {
@@ -229,10 +231,10 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
             E.q[j * ld + i] = (R)q[j];
             E.p[j * ld + i] = (R)p[j];
         }
-        E.u[0 * ld + i] = (R)e.u00;
-        E.u[1 * ld + i] = (R)e.u01;
-        E.u[2 * ld + i] = (R)e.u10;
-        E.u[3 * ld + i] = (R)e.u11;
+        E.u[0 * ld + i] = (R)u00;
+        E.u[1 * ld + i] = (R)u01;
+        E.u[2 * ld + i] = (R)u10;
+        E.u[3 * ld + i] = (R)u11;
         E.w[i] = w;
         E.phase[i] = 0.0;
         E.a[i] = (uint8_t)a;
@@ -247,13 +249,13 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
 // p += (dt/2) * mean force of element (a,b):
 // (dt/2)(F_a + F_b)/2 = -hk q - hb - (dt/2)(a+b-1)(dl dlt + cc cpl)/r
 template <int M, typename R>
-__device__ __forceinline__ void mean_force_kick(const N2Const<M, R> &C, const Frame2<R> &e, R lam,
+__device__ __forceinline__ void mean_force_kick(const N2Const<M, R> &C, const Geo2<R> &g, R lam,
                                                 const R (&q)[M], R (&p)[M])
 {
-    const R g = lam * (C.hdt * e.rinv);
+    const R h = lam * (C.hdt * g.rinv);
 #pragma unroll
     for (int j = 0; j < M; ++j)
-        p[j] = p[j] - C.hk[j] * q[j] - C.hb[j] - g * (e.dl * C.dlt[j] + e.cc * C.cpl[j]);
+        p[j] = p[j] - C.hk[j] * q[j] - C.hb[j] - h * (g.dl * C.dlt[j] + g.cc * C.cpl[j]);
 }
 
 template <int M, typename R>
@@ -281,9 +283,12 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
     int b = E.b[li];
     uint32_t flag = 0;
 
-    Frame2<R> e;
-    frame_at<M, R>(C, q, e, flag);
-    align2<R>(e, p00, p10, p01, p11);
+    Geo2<R> g;
+    geo_at<M, R>(C, q, g, flag);
+    // column signs of the stored frame relative to the canonical one
+    R s0 = (p00 * (-g.x1) + p10 * g.x0) < R(0) ? R(-1) : R(1);
+    R s1 = (p01 * g.x0 + p11 * g.x1) < R(0) ? R(-1) : R(1);
+    const R sig = s0 * s1;  // invariant along the walker
 
     int64_t step = P.step0;
     const int64_t end = P.step0 + P.n_steps;
@@ -306,10 +311,10 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
                 dlv += vj * C.dlt[j];
                 cv += vj * C.cpl[j];
             }
-            const R D01 = dlv * (e.u00 * e.u01 - e.u10 * e.u11) + cv * (e.u00 * e.u11 + e.u10 * e.u01);
-            const R x = D01 * (R(0.5) * e.rinv);  // dt v.d_01
-            const R f0 = a == 0 ? x : -x;         // to (1-a, b): dt v.d_{a,1-a}
-            const R f1 = b == 0 ? x : -x;         // to (a, 1-b): dt v.d_{b,1-b}
+            // dt v.d_01 = s0 s1 (dl c_v - cc dl_v) / (2 r^2)
+            const R x = sig * (g.dl * cv - g.cc * dlv) * (R(0.5) * (g.rinv * g.rinv));
+            const R f0 = a == 0 ? x : -x;  // to (1-a, b): dt v.d_{a,1-a}
+            const R f1 = b == 0 ? x : -x;  // to (a, 1-b): dt v.d_{b,1-b}
             const R af0 = f0 < R(0) ? -f0 : f0;
             const R af1 = f1 < R(0) ? -f1 : f1;
             const R S = af0 + af1;
@@ -338,23 +343,27 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
 
             // 2. velocity Verlet on the mean force of the current element
             const R lam = R(a + b - 1);
-            const R r_old = e.r;
-            mean_force_kick<M, R>(C, e, lam, q, p);
+            const R r_old = g.r, xo0 = g.x0, xo1 = g.x1;
+            mean_force_kick<M, R>(C, g, lam, q, p);
 #pragma unroll
             for (int j = 0; j < M; ++j)
                 q[j] += C.dtm[j] * p[j];
-            const R o00 = e.u00, o10 = e.u10, o01 = e.u01, o11 = e.u11;
-            frame_at<M, R>(C, q, e, flag);
-            align2<R>(e, o00, o10, o01, o11);
-            mean_force_kick<M, R>(C, e, lam, q, p);
+            geo_at<M, R>(C, q, g, flag);
+            if (xo0 * g.x0 + xo1 * g.x1 < R(0)) {  // frame continuity
+                s0 = -s0;
+                s1 = -s1;
+            }
+            mean_force_kick<M, R>(C, g, lam, q, p);
 
             // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar = 2 (a - b) r / hbar
-            phase += (double)(a - b) * (C.dt_hbar * ((double)r_old + (double)e.r));
+            phase += (double)(a - b) * (C.dt_hbar * ((double)r_old + (double)g.r));
         }
         // 4. output bin at global step next_bin
         if (step == next_bin && next_bin / P.cadence < P.n_out) {
+            R c0, c1;
+            canon2<R>(g, c0, c1);
             double v[32];
-            bin_values<R>(v, live, a, b, w, phase, e);
+            bin_values<R>(v, live, a, b, w, phase, c0, c1, sig);
             block_reduce_store<32>(v, partials + ((int64_t)blockIdx.x * P.n_out + next_bin / P.cadence) * 32, lds);
         }
     }
@@ -362,15 +371,17 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
         flag |= kFlagNonfinite;
 
     if (live) {
+        R c0, c1;
+        canon2<R>(g, c0, c1);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             E.q[j * ld + i] = q[j];
             E.p[j * ld + i] = p[j];
         }
-        E.u[0 * ld + i] = e.u00;
-        E.u[1 * ld + i] = e.u01;
-        E.u[2 * ld + i] = e.u10;
-        E.u[3 * ld + i] = e.u11;
+        E.u[0 * ld + i] = -s0 * c1;
+        E.u[1 * ld + i] = s1 * c0;
+        E.u[2 * ld + i] = s0 * c0;
+        E.u[3 * ld + i] = s1 * c1;
         E.w[i] = w;
         E.phase[i] = phase;
         E.a[i] = (uint8_t)a;
