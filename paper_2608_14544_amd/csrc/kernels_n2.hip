@@ -30,8 +30,11 @@
 namespace qcl {
 namespace {
 
+// 1/sqrt.  binary32: the hardware v_rsq_f32 (about 1 ulp); arguments are
+// squared gaps that are either well above the binary32 denormal range or
+// re-solved in binary64.  binary64: the library rsqrt.
 __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
-__device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Geometry of the 2x2 problem at one point: dl, cc, r = sqrt(dl^2+cc^2),
 // 1/r and the unnormalised canonical upper eigenvector x.
@@ -76,20 +79,20 @@ __device__ __forceinline__ void coupling_coords(const N2Const<M, R> &C, const R 
     }
 }
 
-// binary64 re-solve of a near-degenerate point for the binary32 path
+// binary64 re-solve of a near-degenerate point for the binary32 path; the
+// binary64 constants are read from device memory only when needed
 template <int M>
-__device__ __forceinline__ void resolve64(const N2Const<M, float> &C, const float (&q)[M], Geo2<float> &g)
+__device__ __forceinline__ Geo2<float> resolve64(const double *__restrict__ c64, const float (&q)[M])
 {
-    double dl = C.dlt0_64, cc = C.c0_64;
+    double dl = c64[0], cc = c64[1];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        dl += C.dlt64[j] * (double)q[j];
-        cc += C.cpl64[j] * (double)q[j];
+        dl += c64[2 + j] * (double)q[j];
+        cc += c64[2 + M + j] * (double)q[j];
     }
     Geo2<double> d;
     geo2<double>(dl, cc, d);
-    g.dl = (float)d.dl; g.cc = (float)d.cc; g.r = (float)d.r; g.rinv = (float)d.rinv;
-    g.x0 = (float)d.x0; g.x1 = (float)d.x1;
+    return Geo2<float>{(float)d.dl, (float)d.cc, (float)d.r, (float)d.rinv, (float)d.x0, (float)d.x1};
 }
 
 template <int M, typename R>
@@ -100,7 +103,7 @@ __device__ __forceinline__ void geo_at(const N2Const<M, R> &C, const R (&q)[M], 
     geo2<R>(dl, cc, g);
     if constexpr (sizeof(R) == 4) {
         if (!(R(2) * g.r >= C.gap_thr)) {
-            resolve64<M>(C, q, g);
+            g = resolve64<M>(C.c64, q);
             flag |= kFlagResolved;
         }
     }
@@ -154,6 +157,7 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
                                                            double *__restrict__ partials, int32_t n_out)
 {
     __shared__ double lds[4 * 32];
+    const int slot = scatter_slot32(threadIdx.x & 63);
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool live = i < E.n_traj;
     const uint64_t gid = (uint64_t)(E.traj_offset + (live ? i : 0));
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
 
     double v[32];
     bin_values<double>(v, live, a, b, w, 0.0, c0, c1, s0 * s1);
-    block_reduce_store<32>(v, partials + ((int64_t)blockIdx.x * n_out + 0) * 32, lds);
+    block_reduce_store32(v, slot, partials + ((int64_t)blockIdx.x * n_out + 0) * 32, lds);
 
     if (live) {
         const int64_t ld = E.ld;
@@ -246,23 +250,33 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
 
 // ---------------------------------------------------------------- propagation
 
-// p += (dt/2) * mean force of element (a,b):
-// (dt/2)(F_a + F_b)/2 = -hk q - hb - (dt/2)(a+b-1)(dl dlt + cc cpl)/r
+// Element-independent part of the Hellmann-Feynman force at the current
+// point: G_j = dl dlt_j + cc cpl_j, so that dE_{0,1}/dq_j = kbar_j -+ G_j/r.
 template <int M, typename R>
-__device__ __forceinline__ void mean_force_kick(const N2Const<M, R> &C, const Geo2<R> &g, R lam,
-                                                const R (&q)[M], R (&p)[M])
+__device__ __forceinline__ void force_terms(const N2Const<M, R> &C, const Geo2<R> &g, R (&G)[M])
 {
-    const R h = lam * (C.hdt * g.rinv);
 #pragma unroll
     for (int j = 0; j < M; ++j)
-        p[j] = p[j] - C.hk[j] * q[j] - C.hb[j] - h * (g.dl * C.dlt[j] + g.cc * C.cpl[j]);
+        G[j] = g.dl * C.dlt[j] + g.cc * C.cpl[j];
 }
 
+// p += (dt/2) * mean force of element (a,b), lam = a + b - 1:
+// (dt/2)(F_a + F_b)/2 = -hk q - hb - (dt/2) lam G/r
 template <int M, typename R>
+__device__ __forceinline__ void mean_force_kick(const N2Const<M, R> &C, const R (&G)[M], R h, const R (&q)[M],
+                                                R (&p)[M])
+{
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        p[j] = (p[j] - C.hb[j]) - C.hk[j] * q[j] - h * G[j];
+}
+
+template <int M, typename R, int SCHEME>
 __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, PropArgs P, EnsDev<R> E,
                                                               double *__restrict__ partials)
 {
     __shared__ double lds[4 * 32];
+    const int slot = scatter_slot32(threadIdx.x & 63);
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool live = i < E.n_traj;
     const int64_t li = live ? i : E.n_traj - 1;  // idle lanes shadow a valid walker
@@ -285,10 +299,14 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
 
     Geo2<R> g;
     geo_at<M, R>(C, q, g, flag);
-    // column signs of the stored frame relative to the canonical one
-    R s0 = (p00 * (-g.x1) + p10 * g.x0) < R(0) ? R(-1) : R(1);
+    // column signs of the stored frame relative to the canonical one; the
+    // product s0 s1 is invariant along the walker, s1 is tracked
+    const R s0_in = (p00 * (-g.x1) + p10 * g.x0) < R(0) ? R(-1) : R(1);
     R s1 = (p01 * g.x0 + p11 * g.x1) < R(0) ? R(-1) : R(1);
-    const R sig = s0 * s1;  // invariant along the walker
+    const R sig = s0_in * s1;
+    R G[M];
+    force_terms<M, R>(C, g, G);
+    double r_old = (double)g.r;
 
     int64_t step = P.step0;
     const int64_t end = P.step0 + P.n_steps;
@@ -302,61 +320,62 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
             if ((step & 3) == 0)
                 rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
             const uint32_t word = pick_word(rnd, (uint32_t)(step & 3));
-
-            // 1. Monte Carlo move between elements at (q_n, p_n)
-            R dlv = R(0), cv = R(0);  // dt * sum_j v_j dlt_j, dt * sum_j v_j cpl_j
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-                const R vj = p[j] * C.dtm[j];
-                dlv += vj * C.dlt[j];
-                cv += vj * C.cpl[j];
-            }
-            // dt v.d_01 = s0 s1 (dl c_v - cc dl_v) / (2 r^2)
-            const R x = sig * (g.dl * cv - g.cc * dlv) * (R(0.5) * (g.rinv * g.rinv));
-            const R f0 = a == 0 ? x : -x;  // to (1-a, b): dt v.d_{a,1-a}
-            const R f1 = b == 0 ? x : -x;  // to (a, 1-b): dt v.d_{b,1-b}
-            const R af0 = f0 < R(0) ? -f0 : f0;
-            const R af1 = f1 < R(0) ? -f1 : f1;
-            const R S = af0 + af1;
             R u;
             if constexpr (sizeof(R) == 4) u = u24f(word); else u = u24d(word);
-            int pick = -1;
-            if (P.scheme == QCL_TRANS_LINEAR && S < R(1)) {
-                if (u < af0) pick = 0;
-                else if (u < S) pick = 1;
-                if (pick < 0) w = w / (double)(R(1) - S);
-                else w = w * ((pick == 0 ? f0 : f1) > R(0) ? 1.0 : -1.0);
+
+            // 1. Monte Carlo move between elements at (q_n, p_n).
+            // dt v.d_01 = s0 s1 (dl c_v - cc dl_v) / (2 r^2); the two
+            // candidates (1-a, b) and (a, 1-b) carry f0 = +-x, f1 = +-x.
+            R dlv = R(0), cv = R(0);
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                dlv += p[j] * C.vdl[j];
+                cv += p[j] * C.vcp[j];
+            }
+            const R x = sig * (g.dl * cv - g.cc * dlv) * (R(0.5) * (g.rinv * g.rinv));
+            const R ax = x < R(0) ? -x : x;
+            const R S = ax + ax;
+            const bool xpos = x > R(0);
+            int pick;     // -1 stay, 0 -> (1-a, b), 1 -> (a, 1-b)
+            double mul;   // weight factor
+            if (SCHEME == QCL_TRANS_LINEAR && S < R(1)) {
+                pick = (u < ax) ? 0 : ((u < S) ? 1 : -1);
+                mul = (double)(R(1) / (R(1) - S));
             } else {
-                if (P.scheme == QCL_TRANS_LINEAR)
+                if (SCHEME == QCL_TRANS_LINEAR)
                     flag |= kFlagFallback;
                 const R t = u * (R(1) + S);
-                if (!(t < R(1))) {
-                    if (t < R(1) + af0) pick = 0;
-                    else if (t < R(1) + S) pick = 1;
-                    else pick = af1 > R(0) ? 1 : (af0 > R(0) ? 0 : -1);
-                }
-                const double sg = pick < 0 ? 1.0 : ((pick == 0 ? f0 : f1) > R(0) ? 1.0 : -1.0);
-                w = w * (double)(R(1) + S) * sg;
+                pick = (t < R(1)) ? -1 : ((t < R(1) + ax) ? 0 : 1);
+                mul = (double)(R(1) + S);
             }
-            if (pick == 0) a = 1 - a;
-            if (pick == 1) b = 1 - b;
+            // sign of the chosen candidate's factor: f0 = (a ? -x : x), f1 = (b ? -x : x)
+            const bool fpos = (pick == 0) ? (xpos != (a != 0)) : (xpos != (b != 0));
+            if (SCHEME == QCL_TRANS_LINEAR && S < R(1)) {
+                if (pick < 0) w = w / (double)(R(1) - S);
+                else w = fpos ? w : -w;
+            } else {
+                w = w * mul;
+                w = (pick < 0 || fpos) ? w : -w;
+            }
+            a = (pick == 0) ? 1 - a : a;
+            b = (pick == 1) ? 1 - b : b;
 
             // 2. velocity Verlet on the mean force of the current element
             const R lam = R(a + b - 1);
-            const R r_old = g.r, xo0 = g.x0, xo1 = g.x1;
-            mean_force_kick<M, R>(C, g, lam, q, p);
+            const R xo0 = g.x0, xo1 = g.x1;
+            mean_force_kick<M, R>(C, G, lam * (C.hdt * g.rinv), q, p);
 #pragma unroll
             for (int j = 0; j < M; ++j)
                 q[j] += C.dtm[j] * p[j];
             geo_at<M, R>(C, q, g, flag);
-            if (xo0 * g.x0 + xo1 * g.x1 < R(0)) {  // frame continuity
-                s0 = -s0;
-                s1 = -s1;
-            }
-            mean_force_kick<M, R>(C, g, lam, q, p);
+            s1 = (xo0 * g.x0 + xo1 * g.x1 < R(0)) ? -s1 : s1;  // frame continuity
+            force_terms<M, R>(C, g, G);
+            mean_force_kick<M, R>(C, G, lam * (C.hdt * g.rinv), q, p);
 
             // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar = 2 (a - b) r / hbar
-            phase += (double)(a - b) * (C.dt_hbar * ((double)r_old + (double)g.r));
+            const double r_new = (double)g.r;
+            phase = fma((double)(a - b), C.dt_hbar * (r_old + r_new), phase);
+            r_old = r_new;
         }
         // 4. output bin at global step next_bin
         if (step == next_bin && next_bin / P.cadence < P.n_out) {
@@ -364,7 +383,8 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
             canon2<R>(g, c0, c1);
             double v[32];
             bin_values<R>(v, live, a, b, w, phase, c0, c1, sig);
-            block_reduce_store<32>(v, partials + ((int64_t)blockIdx.x * P.n_out + next_bin / P.cadence) * 32, lds);
+            block_reduce_store32(v, slot, partials + ((int64_t)blockIdx.x * P.n_out + next_bin / P.cadence) * 32,
+                                 lds);
         }
     }
     if (!(isfinite(w) && isfinite(phase)))
@@ -373,6 +393,7 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
     if (live) {
         R c0, c1;
         canon2<R>(g, c0, c1);
+        const R s0 = sig * s1;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             E.q[j * ld + i] = q[j];
@@ -400,19 +421,18 @@ N2Const<M, R> make_const(const qcl_model_s &m, double dt)
         const bool real = j < m.m;  // padded modes are inert
         C.dlt[j] = (R)(real ? m.dlt[j] : 0.0);
         C.cpl[j] = (R)(real ? m.cpl[j] : 0.0);
+        C.vdl[j] = (R)(real ? dt * m.minv[j] * m.dlt[j] : 0.0);
+        C.vcp[j] = (R)(real ? dt * m.minv[j] * m.cpl[j] : 0.0);
         C.hk[j] = (R)(real ? hdt * m.kq[j] : 0.0);
         C.hb[j] = (R)(real ? hdt * m.kbar[j] : 0.0);
         C.dtm[j] = (R)(real ? dt * m.minv[j] : 0.0);
-        C.dlt64[j] = real ? m.dlt[j] : 0.0;
-        C.cpl64[j] = real ? m.cpl[j] : 0.0;
     }
     C.dlt0 = (R)m.dlt0;
     C.c0 = (R)m.c0;
-    C.dlt0_64 = m.dlt0;
-    C.c0_64 = m.c0;
     C.hdt = (R)hdt;
     C.gap_thr = (R)(1e-4 * m.energy_scale);
     C.dt_hbar = dt / m.hbar;
+    C.c64 = m.d_model + m.c64_offset;
     return C;
 }
 
@@ -435,18 +455,30 @@ hipError_t sample_m(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemb
     return hipGetLastError();
 }
 
+template <int M, typename R>
+void propagate_mr(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
+                  hipStream_t s)
+{
+    const dim3 grid((unsigned)n_tiles(ens.n_traj)), block(kBlock);
+    const PropArgs P{ens.step, pd.n_steps, pd.cadence, pd.n_out, pd.scheme, (uint32_t)pd.seed,
+                     (uint32_t)(pd.seed >> 32)};
+    const N2Const<M, R> C = make_const<M, R>(m, pd.dt);
+    if (pd.scheme == QCL_TRANS_LINEAR)
+        hipLaunchKernelGGL((propagate_n2_kernel<M, R, QCL_TRANS_LINEAR>), grid, block, 0, s, C, P, ens_dev<R>(ens),
+                           partials);
+    else
+        hipLaunchKernelGGL((propagate_n2_kernel<M, R, QCL_TRANS_NORMALIZED>), grid, block, 0, s, C, P,
+                           ens_dev<R>(ens), partials);
+}
+
 template <int M>
 hipError_t propagate_m(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
                        hipStream_t s)
 {
-    const dim3 grid((unsigned)n_tiles(ens.n_traj)), block(kBlock);
-    PropArgs P{ens.step, pd.n_steps, pd.cadence, pd.n_out, pd.scheme, (uint32_t)pd.seed, (uint32_t)(pd.seed >> 32)};
     if (ens.prec == QCL_FP64)
-        hipLaunchKernelGGL((propagate_n2_kernel<M, double>), grid, block, 0, s, make_const<M, double>(m, pd.dt), P,
-                           ens_dev<double>(ens), partials);
+        propagate_mr<M, double>(m, ens, pd, partials, s);
     else
-        hipLaunchKernelGGL((propagate_n2_kernel<M, float>), grid, block, 0, s, make_const<M, float>(m, pd.dt), P,
-                           ens_dev<float>(ens), partials);
+        propagate_mr<M, float>(m, ens, pd, partials, s);
     return hipGetLastError();
 }
 

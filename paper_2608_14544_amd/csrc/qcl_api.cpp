@@ -164,15 +164,20 @@ qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out)
         delete m;
         return device_fail(e, "hipGetDevice");
     }
-    const size_t bytes = sizeof(double) * (m->v0.size() + m->k.size());
+    std::vector<double> packed(m->v0);
+    packed.insert(packed.end(), m->k.begin(), m->k.end());
+    m->c64_offset = packed.size();
+    packed.push_back(m->dlt0);
+    packed.push_back(m->c0);
+    packed.insert(packed.end(), m->dlt.begin(), m->dlt.end());
+    packed.insert(packed.end(), m->cpl.begin(), m->cpl.end());
+    const size_t bytes = sizeof(double) * packed.size();
     e = hipMalloc((void **)&m->d_model, bytes);
     if (e != hipSuccess) {
         delete m;
         return e == hipErrorOutOfMemory ? fail(QCL_ERR_OUT_OF_MEMORY, "hipMalloc of %zu bytes", bytes)
                                         : device_fail(e, "hipMalloc");
     }
-    std::vector<double> packed(m->v0);
-    packed.insert(packed.end(), m->k.begin(), m->k.end());
     e = hipMemcpy(m->d_model, packed.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(m->d_model);

@@ -30,6 +30,8 @@ template <int M, typename R>
 struct N2Const {
     R dlt[M];   // (K_00 - K_11)/2
     R cpl[M];   // K_01
+    R vdl[M];   // dt/m_j (K_00 - K_11)/2: p_j vdl_j sums to dt dl_v
+    R vcp[M];   // dt/m_j K_01
     R hk[M];    // (dt/2) m_j w_j^2
     R hb[M];    // (dt/2) (K_00 + K_11)/2
     R dtm[M];   // dt/m_j
@@ -38,10 +40,9 @@ struct N2Const {
     R hdt;      // dt/2
     R gap_thr;  // binary32 path: gaps 2r below this are re-solved in binary64
     double dt_hbar;
-    // binary64 copies for the re-solve of near-degenerate points
-    double dlt64[M];
-    double cpl64[M];
-    double dlt0_64, c0_64;
+    // binary64 copies [dlt0, c0, dlt_0..M-1, cpl_0..M-1] in device memory,
+    // read only by the binary32 path's near-degenerate re-solve
+    const double *c64;
 };
 
 template <typename R>
@@ -89,7 +90,9 @@ struct qcl_model_s {
     double dlt0 = 0.0, c0 = 0.0;
     double energy_scale = 1.0;
     int device = 0;
-    double *d_model = nullptr;  // device copy of V0 and K (general-N kernels)
+    double *d_model = nullptr;  // device: V0 [N*N], K [M*N*N], then two-state binary64
+                                // constants [dlt0, c0, dlt[M], cpl[M]]
+    size_t c64_offset = 0;      // element offset of the two-state constants
 };
 
 namespace qcl {
