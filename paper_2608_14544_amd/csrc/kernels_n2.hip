@@ -119,7 +119,14 @@ __device__ __forceinline__ void bin_values(double (&v)[32], bool live, int a, in
                                            R c0, R c1, R sig)
 {
     double sn, cs;
-    sincos_phase(phase, sn, cs);
+    if constexpr (sizeof(R) == 4) {
+        float s32, c32;
+        sincos_phase32(phase, s32, c32);
+        sn = (double)s32;
+        cs = (double)c32;
+    } else {
+        sincos_phase(phase, sn, cs);
+    }
     double re = w * cs, im = -w * sn;
     const bool ok = live && isfinite(w) && isfinite(phase);
     re = ok ? re : 0.0;
