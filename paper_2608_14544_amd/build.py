@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libqcl.so")
 
-SOURCES = ["qcl_api.cpp", "kernels_n2.hip", "reduce.hip"]
+SOURCES = ["qcl_api.cpp", "kernels_n2.hip", "kernels_gen2.hip", "kernels_gen3.hip", "kernels_gen4.hip", "reduce.hip"]
 
 # Packed-FP32 instructions are disabled on purpose: the step code is
 # written in scalar FP32/FP64 and relies on plain IEEE results.
@@ -31,11 +31,13 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    objs = []
+def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
+    """Compiles every source (in parallel) and links libqcl.so."""
+    from concurrent.futures import ThreadPoolExecutor
     obj_dir = os.path.join(PKG, "_build")
     os.makedirs(obj_dir, exist_ok=True)
-    for src in SOURCES:
+
+    def compile_one(src):
         path = os.path.join(CSRC, src)
         obj = os.path.join(obj_dir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
@@ -43,7 +45,11 @@ def build(verbose: bool = False, extra=()) -> str:
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+        return obj
+
+    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 2)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

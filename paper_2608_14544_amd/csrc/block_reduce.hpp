@@ -150,10 +150,11 @@ __device__ __forceinline__ void wave_reduce32(double (&v)[32], int lane)
     v[0] = v[0] + xlane<1>(v[0]);
 }
 
-// Sums v over the workgroup and writes the 32 totals to dst (threads 0..31).
-// lds holds 4*32 doubles; slot = scatter_slot32(lane).  All threads call it.
+// Sums v over the workgroup and writes the first n_valid of the 32 totals
+// to dst (threads 0..n_valid-1).  lds holds 4*32 doubles;
+// slot = scatter_slot32(lane).  All threads call it.
 __device__ __forceinline__ void block_reduce_store32(double (&v)[32], int slot, double *__restrict__ dst,
-                                                     double *lds)
+                                                     double *lds, int n_valid = 32)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -161,7 +162,7 @@ __device__ __forceinline__ void block_reduce_store32(double (&v)[32], int slot, 
     if ((lane & 1) == 0)
         lds[wave * 32 + slot] = v[0];
     __syncthreads();
-    if (threadIdx.x < 32) {
+    if (threadIdx.x < n_valid) {
         const int t = threadIdx.x;
         dst[t] = (lds[t] + lds[32 + t]) + (lds[64 + t] + lds[96 + t]);
     }

@@ -123,11 +123,6 @@ qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out)
     for (int j = 0; j < M; ++j)
         if (!symmetric(d->k + (size_t)j * n * n, n))
             return fail(QCL_ERR_INVALID_ARG, "K_%d is not symmetric", j);
-    if (n != 2)
-        return fail(QCL_ERR_UNSUPPORTED, "n_states %d: only two-state models are built in this library", n);
-    if (M > qcl::kMaxFastModes)
-        return fail(QCL_ERR_UNSUPPORTED, "n_modes %d: two-state kernels cover up to %d modes", M,
-                    qcl::kMaxFastModes);
 
     qcl_model_s *m = new (std::nothrow) qcl_model_s();
     if (!m)
@@ -139,25 +134,36 @@ qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out)
     m->omega.assign(d->omega, d->omega + M);
     m->v0.assign(d->v0, d->v0 + n * n);
     m->k.assign(d->k, d->k + (size_t)M * n * n);
-    // two-state constants
-    m->kq.resize(M);
-    m->minv.resize(M);
-    m->kbar.resize(M);
-    m->dlt.resize(M);
-    m->cpl.resize(M);
-    double scale = std::fabs(m->v0[0]) + std::fabs(m->v0[1]) + std::fabs(m->v0[3]);
+    m->fast2 = (n == 2 && M <= qcl::kMaxFastModes);
+    // energy scale: |V0| plus each mode's coupling over its zero-point-ish length
+    double scale = 0.0;
+    for (int i = 0; i < n * n; ++i)
+        scale += std::fabs(m->v0[i]);
     for (int j = 0; j < M; ++j) {
-        const double *K = &m->k[(size_t)j * 4];
-        m->kq[j] = m->mass[j] * m->omega[j] * m->omega[j];
-        m->minv[j] = 1.0 / m->mass[j];
-        m->kbar[j] = 0.5 * (K[0] + K[3]);
-        m->dlt[j] = 0.5 * (K[0] - K[3]);
-        m->cpl[j] = K[1];
-        scale += (std::fabs(K[0]) + std::fabs(K[1]) + std::fabs(K[3])) / std::sqrt(m->kq[j]);
+        double kj = 0.0;
+        for (int i = 0; i < n * n; ++i)
+            kj += std::fabs(m->k[(size_t)j * n * n + i]);
+        scale += kj / (m->omega[j] * std::sqrt(m->mass[j]));
     }
-    m->dlt0 = 0.5 * (m->v0[0] - m->v0[3]);
-    m->c0 = m->v0[1];
     m->energy_scale = scale > 0.0 ? scale : 1.0;
+    // two-state constants (closed-form kernels)
+    if (n == 2) {
+        m->kq.resize(M);
+        m->minv.resize(M);
+        m->kbar.resize(M);
+        m->dlt.resize(M);
+        m->cpl.resize(M);
+        for (int j = 0; j < M; ++j) {
+            const double *K = &m->k[(size_t)j * 4];
+            m->kq[j] = m->mass[j] * m->omega[j] * m->omega[j];
+            m->minv[j] = 1.0 / m->mass[j];
+            m->kbar[j] = 0.5 * (K[0] + K[3]);
+            m->dlt[j] = 0.5 * (K[0] - K[3]);
+            m->cpl[j] = K[1];
+        }
+        m->dlt0 = 0.5 * (m->v0[0] - m->v0[3]);
+        m->c0 = m->v0[1];
+    }
 
     hipError_t e = hipGetDevice(&m->device);
     if (e != hipSuccess) {
@@ -167,10 +173,40 @@ qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out)
     std::vector<double> packed(m->v0);
     packed.insert(packed.end(), m->k.begin(), m->k.end());
     m->c64_offset = packed.size();
-    packed.push_back(m->dlt0);
-    packed.push_back(m->c0);
-    packed.insert(packed.end(), m->dlt.begin(), m->dlt.end());
-    packed.insert(packed.end(), m->cpl.begin(), m->cpl.end());
+    if (n == 2) {
+        packed.push_back(m->dlt0);
+        packed.push_back(m->c0);
+        packed.insert(packed.end(), m->dlt.begin(), m->dlt.end());
+        packed.insert(packed.end(), m->cpl.begin(), m->cpl.end());
+    }
+    // general-N tables: v0 upper triangle, then per (zero-padded) mode
+    // m w^2, 1/m, K_j upper triangle; binary64 then binary32
+    const int T = n * (n + 1) / 2;
+    std::vector<double> gen;
+    for (int k = 0; k < n; ++k)
+        for (int l = k; l < n; ++l)
+            gen.push_back(m->v0[k * n + l]);
+    for (int j = 0; j < qcl::kMaxModesPad; ++j) {
+        const bool real = j < M;
+        gen.push_back(real ? m->mass[j] * m->omega[j] * m->omega[j] : 0.0);
+        gen.push_back(real ? 1.0 / m->mass[j] : 0.0);
+        for (int k = 0; k < n; ++k)
+            for (int l = k; l < n; ++l)
+                gen.push_back(real ? m->k[(size_t)j * n * n + k * n + l] : 0.0);
+    }
+    (void)T;
+    while (packed.size() % 32)
+        packed.push_back(0.0);
+    m->gen64_offset = packed.size();
+    packed.insert(packed.end(), gen.begin(), gen.end());
+    while (packed.size() % 32)
+        packed.push_back(0.0);
+    m->gen32_byte_offset = packed.size() * sizeof(double);
+    std::vector<float> gen32(gen.begin(), gen.end());
+    const size_t n32 = (gen32.size() + 1) / 2;  // floats packed two per double slot
+    const size_t base = packed.size();
+    packed.resize(base + n32, 0.0);
+    std::memcpy(packed.data() + base, gen32.data(), gen32.size() * sizeof(float));
     const size_t bytes = sizeof(double) * packed.size();
     e = hipMalloc((void **)&m->d_model, bytes);
     if (e != hipSuccess) {
@@ -309,7 +345,8 @@ qcl_status qcl_sample_initial(qcl_model m, const qcl_init_desc *init, uint64_t s
     ens->step = 0;
     if (ens->n_traj == 0)
         return QCL_OK;
-    hipError_t e = qcl::launch_sample_n2(*m, sa, *ens, partials, n_out, (hipStream_t)stream);
+    hipError_t e = m->fast2 ? qcl::launch_sample_n2(*m, sa, *ens, partials, n_out, (hipStream_t)stream)
+                            : qcl::launch_sample_general(*m, sa, *ens, partials, n_out, (hipStream_t)stream);
     if (e == hipErrorNotSupported)
         return fail(QCL_ERR_UNSUPPORTED, "no sampling kernel for this model");
     if (e != hipSuccess)
@@ -345,7 +382,8 @@ qcl_status qcl_propagate(qcl_model m, qcl_ensemble *ens, const qcl_prop_desc *pd
         ens->step += pd->n_steps;
         return QCL_OK;
     }
-    hipError_t e = qcl::launch_propagate_n2(*m, *ens, *pd, partials, (hipStream_t)stream);
+    hipError_t e = m->fast2 ? qcl::launch_propagate_n2(*m, *ens, *pd, partials, (hipStream_t)stream)
+                            : qcl::launch_propagate_general(*m, *ens, *pd, partials, (hipStream_t)stream);
     if (e == hipErrorNotSupported)
         return fail(QCL_ERR_UNSUPPORTED, "no propagation kernel for this model");
     if (e != hipSuccess)

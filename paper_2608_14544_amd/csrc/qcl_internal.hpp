@@ -45,6 +45,27 @@ struct N2Const {
     const double *c64;
 };
 
+// General-N model constants in device memory (both precisions):
+//   v0 [T] upper triangle of V0 (T = N(N+1)/2, row-major),
+//   md [kMaxModesPad][2 + T] per mode: m w^2, 1/m, K_j upper triangle,
+// zero-padded past the model's modes so that padded modes stay at rest.
+constexpr int kMaxModesPad = 128;
+
+template <typename R>
+struct GenConst {
+    const R *v0;
+    const R *md;
+    R dt, hdt;
+    double dt_hbar;
+    R gap_thr;  // binary32 path: gaps below this are re-solved in binary64
+    R jac_tol;  // Jacobi stop: off-diagonal^2 <= jac_tol * diagonal^2
+};
+
+inline int padded_modes(int m)
+{
+    return m <= 4 ? 4 : m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 128;
+}
+
 template <typename R>
 struct EnsDev {
     R *q;
@@ -67,6 +88,7 @@ struct SampleArgs {
     int32_t state;
     int32_t basis;
     uint32_t key0, key1;
+    int32_t m;  // modes actually present (general kernels)
 };
 
 struct PropArgs {
@@ -76,6 +98,7 @@ struct PropArgs {
     int32_t n_out;
     int32_t scheme;
     uint32_t key0, key1;
+    int32_t m;  // modes actually present (general kernels)
 };
 
 }  // namespace qcl
@@ -93,6 +116,9 @@ struct qcl_model_s {
     double *d_model = nullptr;  // device: V0 [N*N], K [M*N*N], then two-state binary64
                                 // constants [dlt0, c0, dlt[M], cpl[M]]
     size_t c64_offset = 0;      // element offset of the two-state constants
+    size_t gen64_offset = 0;    // element offset of the general-N binary64 constants
+    size_t gen32_byte_offset = 0;  // byte offset of the general-N binary32 constants
+    bool fast2 = false;         // two-state closed-form kernels apply (N = 2, M <= 8)
 };
 
 namespace qcl {
@@ -101,6 +127,43 @@ hipError_t launch_sample_n2(const qcl_model_s &m, const SampleArgs &sa, const qc
                             double *partials, int32_t n_out, hipStream_t stream);
 hipError_t launch_propagate_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
                                double *partials, hipStream_t stream);
+template <int K>
+struct int_ {};
+// one definition per state count (kernels_gen{2,3,4}.hip)
+hipError_t launch_sample_general_n(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,
+                                   double *partials, int32_t n_out, hipStream_t s, int_<2>);
+hipError_t launch_sample_general_n(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,
+                                   double *partials, int32_t n_out, hipStream_t s, int_<3>);
+hipError_t launch_sample_general_n(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,
+                                   double *partials, int32_t n_out, hipStream_t s, int_<4>);
+hipError_t launch_propagate_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
+                                      double *partials, hipStream_t s, int_<2>);
+hipError_t launch_propagate_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
+                                      double *partials, hipStream_t s, int_<3>);
+hipError_t launch_propagate_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
+                                      double *partials, hipStream_t s, int_<4>);
+
+inline hipError_t launch_sample_general(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,
+                                        double *partials, int32_t n_out, hipStream_t s)
+{
+    switch (m.n) {
+    case 2: return launch_sample_general_n(m, sa, ens, partials, n_out, s, int_<2>{});
+    case 3: return launch_sample_general_n(m, sa, ens, partials, n_out, s, int_<3>{});
+    case 4: return launch_sample_general_n(m, sa, ens, partials, n_out, s, int_<4>{});
+    default: return hipErrorNotSupported;
+    }
+}
+
+inline hipError_t launch_propagate_general(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
+                                           double *partials, hipStream_t s)
+{
+    switch (m.n) {
+    case 2: return launch_propagate_general_n(m, ens, pd, partials, s, int_<2>{});
+    case 3: return launch_propagate_general_n(m, ens, pd, partials, s, int_<3>{});
+    case 4: return launch_propagate_general_n(m, ens, pd, partials, s, int_<4>{});
+    default: return hipErrorNotSupported;
+    }
+}
 hipError_t launch_reduce(int n_states, double *partials, int64_t n_traj, int32_t n_out, double *out,
                          hipStream_t stream);
 

@@ -1,0 +1,76 @@
+"""Parity of the general-N HIP kernels (N = 2..4 states, up to 128 modes)
+with the FP64 CPU oracle, through the C ABI.
+
+The general kernels finish each eigen-solve with Jacobi rotations started
+from the previous frame, whereas the oracle starts every solve from the
+identity: both converge to the same eigenpairs, so FP64 walkers agree to
+rounding (tolerance as for the two-state path, 1e-10 relative, with a
+small allowance for walkers whose transition decisions flip).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from test_gpu_parity import compare_walkers, ensemble_close, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2608_14544_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+CASES = {
+    "n3_m3": lambda: W.random_lvc(1, n_states=3, n_modes=3, n_traj=2000, n_steps=200, cadence=20),
+    "n4_m5": lambda: W.random_lvc(2, n_states=4, n_modes=5, n_traj=2000, n_steps=200, cadence=20),
+    "n2_m12": lambda: W.spin_boson_ohmic(kT=1.0, n_traj=2000, n_steps=200, cadence=20, n_modes=12),
+    "n3_m20": lambda: W.random_lvc(5, n_states=3, n_modes=20, n_traj=1000, n_steps=100, cadence=20),
+    "n4_m40": lambda: W.random_lvc(6, n_states=4, n_modes=40, n_traj=600, n_steps=60, cadence=20),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_general_fp64_parity(P, name):
+    wl = CASES[name]()
+    out_g, st_g, s0_g, _ = gpu_run(P, wl)
+    out_o, st_o, s0_o, _ = oracle_run(wl)
+    compare_walkers(s0_g, s0_o, rtol=1e-11, label=name + " sample")
+    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label=name)
+    if nflip == 0:
+        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+
+
+@pytest.mark.parametrize("name", ["n3_m3", "n4_m5", "n2_m12"])
+def test_general_fp32_ensemble(P, name):
+    wl = CASES[name]()
+    wl.run.n_traj = 40_000
+    out_g, _, _, _ = gpu_run(P, wl, prec="fp32")
+    out_o, _, _, _ = oracle_run(wl)
+    d = np.abs(out_g[..., :2] - out_o[..., :2])
+    se = np.maximum(out_o[..., 2:], 1e-300)
+    print(name, "fp32 max abs err", d.max(), "max err/SE", (d / se).max(), flush=True)
+    assert np.all((d <= 1e-3) | (d <= 3 * se))
+
+
+@pytest.mark.parametrize("T", [1, 255, 257])
+def test_general_ragged(P, T):
+    wl = W.random_lvc(3, n_states=3, n_modes=4, n_traj=T, n_steps=40, cadence=7)
+    out_g, st_g, _, _ = gpu_run(P, wl)
+    out_o, st_o, _, _ = oracle_run(wl)
+    compare_walkers(st_g, st_o, rtol=1e-9, label=f"general T={T}")
+    assert ensemble_close(out_g, out_o, T)
+
+
+def test_general_determinism_and_slicing(P):
+    wl = W.random_lvc(4, n_states=4, n_modes=6, n_traj=3000, n_steps=90, cadence=10)
+    for prec in ("fp64", "fp32"):
+        out1, st1, _, _ = gpu_run(P, wl, prec=prec)
+        out2, st2, _, _ = gpu_run(P, wl, prec=prec, split=[13, 27, 50])
+        for k in st1:
+            assert np.array_equal(st1[k], st2[k]), (prec, k)
+        assert np.array_equal(out1, out2), prec
