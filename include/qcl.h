@@ -207,6 +207,43 @@ qcl_status qcl_sample_initial(qcl_model model, const qcl_init_desc *init, uint64
 qcl_status qcl_propagate(qcl_model model, qcl_ensemble *ens, const qcl_prop_desc *prop,
                          double *partials, void *stream);
 
+/* One instance of a batched propagation: the arguments of one
+ * qcl_propagate call. */
+typedef struct {
+    qcl_model model;
+    qcl_ensemble *ens;    /* host struct; ens->step is advanced */
+    qcl_prop_desc prop;
+    double *partials;     /* device, as for qcl_propagate */
+} qcl_batch_item;
+
+/* Device workspace needed by qcl_propagate_batch for these items (0 when
+ * no item has work).  Errors: as qcl_propagate_batch's validation. */
+qcl_status qcl_batch_workspace_bytes(const qcl_batch_item *items, int32_t n_items, size_t *bytes);
+
+/* Propagates many independent ensembles (Sec. II.B: the walkers of every
+ * instance are independent, so instances of different size, model and
+ * length can share the device).  The result of every item is bitwise the
+ * one qcl_propagate would give for it alone.
+ *
+ * Items that need the same kernel (two-state closed form with the same
+ * mode count; or the same state count N and padded mode count; same
+ * precision and transition rule) form one class.  Each class runs as ONE
+ * persistent launch (about one workgroup per free slot of the device);
+ * its workgroups take (item, tile of QCL_TILE walkers) pairs from a device
+ * counter, heaviest tiles first, so uneven instances balance across the
+ * device.  Classes run one after another on the stream, heaviest first.
+ *
+ * workspace: device, >= qcl_batch_workspace_bytes(items, n_items),
+ * 256-byte aligned; holds the descriptors and counters and is written by
+ * the call (no host buffer is kept).  Calls whose execution overlaps on
+ * the device must use different workspaces.  An ensemble or partials
+ * buffer may appear in one item only.  Errors: INVALID_ARG (any item
+ * invalid as for qcl_propagate, a shared ensemble, a small or misaligned
+ * workspace), UNSUPPORTED, DEVICE; nothing is launched and no step
+ * counter changes unless every item is valid. */
+qcl_status qcl_propagate_batch(const qcl_batch_item *items, int32_t n_items, void *workspace,
+                               size_t workspace_bytes, void *stream);
+
 /* Ensemble averages (Sec. II.B: deterministic-order reduction).  Sums the
  * tile partials over tiles in a fixed pairwise tree and writes, to device
  * memory out [n_out][2][N][N][4]:

@@ -2,6 +2,6 @@
 Liouville trajectory ensemble: C-ABI library ``libqcl.so`` (include/qcl.h)
 with a thin ctypes binding (:mod:`paper_2608_14544_amd.qcl`)."""
 from .qcl import (  # noqa: F401
-    Ensemble, Model, Partials, QCLError, load_library, qcl_propagate, qcl_reduce_observables,
-    qcl_sample_initial, run, QCL_FP64, QCL_FP32_ACC64, QCL_TRANS_LINEAR, QCL_TRANS_NORMALIZED,
+    BatchJob, Ensemble, Model, Partials, QCLError, Workspace, load_library, qcl_batch_workspace_bytes,
+    qcl_propagate, qcl_propagate_batch, qcl_reduce_observables, qcl_sample_initial, run, QCL_FP64, QCL_FP32_ACC64, QCL_TRANS_LINEAR, QCL_TRANS_NORMALIZED,
 )

@@ -22,6 +22,9 @@
 //     x_old . x_new < 0, so s0 s1 is constant along a walker.
 // Normalised eigenvectors are formed only for output bins and for the
 // frame stored at the end of a call.
+#include <algorithm>
+#include <cstring>
+
 #include "block_reduce.hpp"
 #include "phase_math.hpp"
 #include "philox.hpp"
@@ -278,13 +281,12 @@ __device__ __forceinline__ void mean_force_kick(const N2Const<M, R> &C, const R 
         p[j] = (p[j] - C.hb[j]) - C.hk[j] * q[j] - h * G[j];
 }
 
+// All steps of one tile of kBlock walkers (the whole workgroup calls it).
 template <int M, typename R, int SCHEME>
-__global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, PropArgs P, EnsDev<R> E,
-                                                              double *__restrict__ partials)
+__device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const PropArgs &P, const EnsDev<R> &E,
+                                                  double *__restrict__ partials, int64_t tile, int slot, double *lds)
 {
-    __shared__ double lds[4 * 32];
-    const int slot = scatter_slot32(threadIdx.x & 63);
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = tile * kBlock + threadIdx.x;
     const bool live = i < E.n_traj;
     const int64_t li = live ? i : E.n_traj - 1;  // idle lanes shadow a valid walker
     const int64_t ld = E.ld;
@@ -390,8 +392,7 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
             canon2<R>(g, c0, c1);
             double v[32];
             bin_values<R>(v, live, a, b, w, phase, c0, c1, sig);
-            block_reduce_store32(v, slot, partials + ((int64_t)blockIdx.x * P.n_out + next_bin / P.cadence) * 32,
-                                 lds);
+            block_reduce_store32(v, slot, partials + (tile * P.n_out + next_bin / P.cadence) * 32, lds);
         }
     }
     if (!(isfinite(w) && isfinite(phase)))
@@ -416,6 +417,48 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, P
         E.b[i] = (uint8_t)b;
         if (E.flags)
             E.flags[i] |= flag;
+    }
+}
+
+template <int M, typename R, int SCHEME>
+__global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, PropArgs P, EnsDev<R> E,
+                                                              double *__restrict__ partials)
+{
+    __shared__ double lds[4 * 32];
+    const int slot = scatter_slot32(threadIdx.x & 63);
+    propagate_n2_tile<M, R, SCHEME>(C, P, E, partials, (int64_t)blockIdx.x, slot, lds);
+}
+
+// Persistent launch over (instance, tile) work items of many two-state
+// instances of one kernel class; items are taken from an atomic counter
+// (descriptors are sorted by decreasing work per tile).
+template <int M, typename R, int SCHEME>
+__global__ __launch_bounds__(kBlock) void batch_n2_kernel(const BatchItemN2<M, R> *__restrict__ items, int32_t n_items,
+                                                          int64_t total_tiles, unsigned long long *counter)
+{
+    __shared__ double lds[4 * 32];
+    __shared__ long long item_sh;
+    const int slot = scatter_slot32(threadIdx.x & 63);
+    for (;;) {
+        if (threadIdx.x == 0)
+            item_sh = (long long)atomicAdd(counter, 1ull);
+        __syncthreads();
+        // wave-uniform by construction; readfirstlane lets the descriptor
+        // loads below go through the scalar unit
+        const long long raw = item_sh;
+        const long long item = (long long)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(raw >> 32)) << 32) |
+                                           (uint32_t)__builtin_amdgcn_readfirstlane((int)raw));
+        __syncthreads();
+        if (item >= total_tiles)
+            break;
+        int lo = 0, hi = n_items - 1;  // last descriptor with tile_begin <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].tile_begin <= item) lo = mid; else hi = mid - 1;
+        }
+        const BatchItemN2<M, R> &it = items[lo];
+        propagate_n2_tile<M, R, SCHEME>(it.C, it.P, it.E, it.partials, item - it.tile_begin, slot, lds);
+        __syncthreads();
     }
 }
 
@@ -489,7 +532,93 @@ hipError_t propagate_m(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_
     return hipGetLastError();
 }
 
+template <int M, typename R>
+size_t item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
+               int64_t tile_begin, void *out)
+{
+    if (out) {
+        BatchItemN2<M, R> it{};
+        it.C = make_const<M, R>(m, pd.dt);
+        it.P = PropArgs{ens.step, pd.n_steps, pd.cadence, pd.n_out, pd.scheme, (uint32_t)pd.seed,
+                        (uint32_t)(pd.seed >> 32), m.m};
+        it.E = ens_dev<R>(ens);
+        it.partials = partials;
+        it.tile_begin = tile_begin;
+        std::memcpy(out, &it, sizeof(it));
+    }
+    return sizeof(BatchItemN2<M, R>);
+}
+
+template <int M, typename R>
+hipError_t batch_m_r(int scheme, const void *items, int32_t n_items, int64_t total_tiles,
+                     unsigned long long *counter, hipStream_t s)
+{
+    int cus = 0, per_cu = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const void *fn = scheme == QCL_TRANS_LINEAR ? (const void *)batch_n2_kernel<M, R, QCL_TRANS_LINEAR>
+                                                : (const void *)batch_n2_kernel<M, R, QCL_TRANS_NORMALIZED>;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0);
+    const int64_t grid = std::min<int64_t>(total_tiles, (int64_t)std::max(1, cus) * std::max(1, per_cu));
+    const BatchItemN2<M, R> *it = (const BatchItemN2<M, R> *)items;
+    if (scheme == QCL_TRANS_LINEAR)
+        hipLaunchKernelGGL((batch_n2_kernel<M, R, QCL_TRANS_LINEAR>), dim3((unsigned)grid), dim3(kBlock), 0, s, it,
+                           n_items, total_tiles, counter);
+    else
+        hipLaunchKernelGGL((batch_n2_kernel<M, R, QCL_TRANS_NORMALIZED>), dim3((unsigned)grid), dim3(kBlock), 0, s,
+                           it, n_items, total_tiles, counter);
+    return hipGetLastError();
+}
+
+template <int M>
+size_t item_m(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
+              int64_t tile_begin, void *out)
+{
+    return ens.prec == QCL_FP64 ? item_n2<M, double>(m, ens, pd, partials, tile_begin, out)
+                                : item_n2<M, float>(m, ens, pd, partials, tile_begin, out);
+}
+
+template <int M>
+hipError_t batch_m(int prec, int scheme, const void *items, int32_t n_items, int64_t total_tiles,
+                   unsigned long long *counter, hipStream_t s)
+{
+    return prec == QCL_FP64 ? batch_m_r<M, double>(scheme, items, n_items, total_tiles, counter, s)
+                            : batch_m_r<M, float>(scheme, items, n_items, total_tiles, counter, s);
+}
+
 }  // namespace
+
+size_t batch_item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
+                     int64_t tile_begin, void *out)
+{
+    switch (m.m) {
+    case 1: return item_m<1>(m, ens, pd, partials, tile_begin, out);
+    case 2: return item_m<2>(m, ens, pd, partials, tile_begin, out);
+    case 3: return item_m<3>(m, ens, pd, partials, tile_begin, out);
+    case 4: return item_m<4>(m, ens, pd, partials, tile_begin, out);
+    case 5: return item_m<5>(m, ens, pd, partials, tile_begin, out);
+    case 6: return item_m<6>(m, ens, pd, partials, tile_begin, out);
+    case 7: return item_m<7>(m, ens, pd, partials, tile_begin, out);
+    case 8: return item_m<8>(m, ens, pd, partials, tile_begin, out);
+    default: return 0;
+    }
+}
+
+hipError_t launch_batch_n2(int modes, int prec, int scheme, const void *items, int32_t n_items, int64_t total_tiles,
+                           unsigned long long *counter, hipStream_t s)
+{
+    switch (modes) {
+    case 1: return batch_m<1>(prec, scheme, items, n_items, total_tiles, counter, s);
+    case 2: return batch_m<2>(prec, scheme, items, n_items, total_tiles, counter, s);
+    case 3: return batch_m<3>(prec, scheme, items, n_items, total_tiles, counter, s);
+    case 4: return batch_m<4>(prec, scheme, items, n_items, total_tiles, counter, s);
+    case 5: return batch_m<5>(prec, scheme, items, n_items, total_tiles, counter, s);
+    case 6: return batch_m<6>(prec, scheme, items, n_items, total_tiles, counter, s);
+    case 7: return batch_m<7>(prec, scheme, items, n_items, total_tiles, counter, s);
+    case 8: return batch_m<8>(prec, scheme, items, n_items, total_tiles, counter, s);
+    default: return hipErrorNotSupported;
+    }
+}
 
 hipError_t launch_sample_n2(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens, double *partials,
                             int32_t n_out, hipStream_t s)

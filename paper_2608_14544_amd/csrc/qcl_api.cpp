@@ -10,6 +10,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "qcl_internal.hpp"
 
@@ -89,6 +91,117 @@ qcl_status check_ensemble(const qcl_model_s &m, const qcl_ensemble *e)
             return fail(QCL_ERR_INVALID_ARG, "misaligned ensemble array");
     }
     (void)m;
+    return QCL_OK;
+}
+
+qcl_status check_propagate(qcl_model m, const qcl_ensemble *ens, const qcl_prop_desc *pd, const double *partials)
+{
+    if (qcl_status st = check_model(m))
+        return st;
+    if (qcl_status st = check_ensemble(*m, ens))
+        return st;
+    if (!pd)
+        return fail(QCL_ERR_INVALID_ARG, "prop is NULL");
+    if (!(pd->dt > 0.0) || !std::isfinite(pd->dt))
+        return fail(QCL_ERR_INVALID_ARG, "dt must be finite and > 0");
+    if (pd->n_steps < 0 || pd->cadence < 1 || pd->n_out < 1)
+        return fail(QCL_ERR_INVALID_ARG, "n_steps >= 0, cadence >= 1 and n_out >= 1 required");
+    if (pd->scheme != QCL_TRANS_NORMALIZED && pd->scheme != QCL_TRANS_LINEAR)
+        return fail(QCL_ERR_INVALID_ARG, "unknown transition scheme %d", pd->scheme);
+    if (pd->block != 0)
+        return fail(QCL_ERR_INVALID_ARG, "block must be 0");
+    const int64_t last_bin = (ens->step + pd->n_steps) / pd->cadence;
+    if (last_bin >= pd->n_out)
+        return fail(QCL_ERR_INVALID_ARG, "bin %lld would be written but n_out is %d", (long long)last_bin,
+                    pd->n_out);
+    if (ens->step + (int64_t)pd->n_steps > ((int64_t)1 << 33))
+        return fail(QCL_ERR_INVALID_ARG, "global step counter out of range");
+    if (ens->n_traj > 0 && (!partials || ((uintptr_t)partials % 8)))
+        return fail(QCL_ERR_INVALID_ARG, "partials is NULL or misaligned");
+    return QCL_OK;
+}
+
+// Items of one batch that share a kernel: same specialisation (two-state
+// closed form with M modes, or general N states with modes padded to MP),
+// precision and transition rule.
+struct BatchClass {
+    bool fast2;
+    int n, modes, prec, scheme;
+    std::vector<int32_t> order;  // item indices, most expensive tile first
+    size_t item_bytes = 0;
+    size_t counter_offset = 0;   // one 8-byte tile counter
+    size_t offset = 0;           // descriptor array
+    int64_t total_tiles = 0;
+    double cost = 0;             // estimated walker-steps x per-step weight
+};
+
+struct BatchPlan {
+    std::vector<BatchClass> classes;
+    size_t bytes = 0;
+};
+
+qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &plan)
+{
+    if (n_items < 0 || (n_items > 0 && !items))
+        return fail(QCL_ERR_INVALID_ARG, "items is NULL or n_items < 0");
+    if (n_items > (1 << 20))
+        return fail(QCL_ERR_INVALID_ARG, "at most 2^20 items per batch");
+    std::vector<double> weight(n_items, 0.0);
+    for (int32_t i = 0; i < n_items; ++i) {
+        const qcl_batch_item &it = items[i];
+        if (qcl_status st = check_propagate(it.model, it.ens, &it.prop, it.partials))
+            return fail(st, "item %d: %s", i, g_last_error.c_str());
+        if (it.ens->n_traj == 0 || it.prop.n_steps == 0)
+            continue;
+        const qcl_model_s &m = *it.model;
+        const int modes = m.fast2 ? m.m : qcl::padded_modes(m.m);
+        BatchClass *c = nullptr;
+        for (BatchClass &k : plan.classes)
+            if (k.fast2 == m.fast2 && k.n == m.n && k.modes == modes && k.prec == it.ens->prec &&
+                k.scheme == it.prop.scheme)
+                c = &k;
+        if (!c) {
+            plan.classes.push_back(BatchClass{m.fast2, m.n, modes, it.ens->prec, it.prop.scheme});
+            c = &plan.classes.back();
+            c->item_bytes = qcl::batch_item(m, *it.ens, it.prop, nullptr, 0, nullptr);
+            if (c->item_bytes == 0)
+                return fail(QCL_ERR_UNSUPPORTED, "item %d: no batched kernel for this model", i);
+        }
+        c->order.push_back(i);
+        // per-step work grows with the mode count and (for the Jacobi
+        // solver) with N^3; the weight only orders tiles, so it is rough
+        const double per_step = m.fast2 ? 40.0 + 30.0 * m.m : 60.0 * m.n * m.n * m.n + 12.0 * m.n * m.n * m.m;
+        weight[i] = per_step * it.prop.n_steps;
+        const int64_t t = qcl::n_tiles(it.ens->n_traj);
+        c->total_tiles += t;
+        c->cost += weight[i] * (double)it.ens->n_traj;
+    }
+    // a walker array or partials buffer may appear in one item only
+    std::vector<std::pair<const void *, int32_t>> keys;
+    keys.reserve(3 * (size_t)n_items);
+    for (int32_t i = 0; i < n_items; ++i) {
+        keys.push_back({items[i].ens, i});
+        if (items[i].ens->n_traj > 0) {
+            keys.push_back({items[i].ens->q, i});
+            keys.push_back({items[i].partials, i});
+        }
+    }
+    std::sort(keys.begin(), keys.end());
+    for (size_t k = 1; k < keys.size(); ++k)
+        if (keys[k].first == keys[k - 1].first && keys[k].second != keys[k - 1].second)
+            return fail(QCL_ERR_INVALID_ARG, "items %d and %d share an ensemble or partials buffer",
+                        keys[k - 1].second, keys[k].second);
+    // heaviest class first, heaviest tile first inside a class
+    std::stable_sort(plan.classes.begin(), plan.classes.end(),
+                     [](const BatchClass &x, const BatchClass &y) { return x.cost > y.cost; });
+    size_t off = 0;
+    for (BatchClass &c : plan.classes) {
+        std::stable_sort(c.order.begin(), c.order.end(), [&](int32_t x, int32_t y) { return weight[x] > weight[y]; });
+        c.counter_offset = off;
+        c.offset = off + 256;
+        off = align256(c.offset + c.item_bytes * c.order.size());
+    }
+    plan.bytes = off;
     return QCL_OK;
 }
 
@@ -356,28 +469,8 @@ qcl_status qcl_sample_initial(qcl_model m, const qcl_init_desc *init, uint64_t s
 
 qcl_status qcl_propagate(qcl_model m, qcl_ensemble *ens, const qcl_prop_desc *pd, double *partials, void *stream)
 {
-    if (qcl_status st = check_model(m))
+    if (qcl_status st = check_propagate(m, ens, pd, partials))
         return st;
-    if (qcl_status st = check_ensemble(*m, ens))
-        return st;
-    if (!pd)
-        return fail(QCL_ERR_INVALID_ARG, "prop is NULL");
-    if (!(pd->dt > 0.0) || !std::isfinite(pd->dt))
-        return fail(QCL_ERR_INVALID_ARG, "dt must be finite and > 0");
-    if (pd->n_steps < 0 || pd->cadence < 1 || pd->n_out < 1)
-        return fail(QCL_ERR_INVALID_ARG, "n_steps >= 0, cadence >= 1 and n_out >= 1 required");
-    if (pd->scheme != QCL_TRANS_NORMALIZED && pd->scheme != QCL_TRANS_LINEAR)
-        return fail(QCL_ERR_INVALID_ARG, "unknown transition scheme %d", pd->scheme);
-    if (pd->block != 0)
-        return fail(QCL_ERR_INVALID_ARG, "block must be 0");
-    const int64_t last_bin = (ens->step + pd->n_steps) / pd->cadence;
-    if (last_bin >= pd->n_out)
-        return fail(QCL_ERR_INVALID_ARG, "bin %lld would be written but n_out is %d", (long long)last_bin,
-                    pd->n_out);
-    if (ens->step + (int64_t)pd->n_steps > ((int64_t)1 << 33))
-        return fail(QCL_ERR_INVALID_ARG, "global step counter out of range");
-    if (ens->n_traj > 0 && (!partials || ((uintptr_t)partials % 8)))
-        return fail(QCL_ERR_INVALID_ARG, "partials is NULL or misaligned");
     if (ens->n_traj == 0 || pd->n_steps == 0) {
         ens->step += pd->n_steps;
         return QCL_OK;
@@ -389,6 +482,61 @@ qcl_status qcl_propagate(qcl_model m, qcl_ensemble *ens, const qcl_prop_desc *pd
     if (e != hipSuccess)
         return device_fail(e, "propagate kernel launch");
     ens->step += pd->n_steps;
+    return QCL_OK;
+}
+
+qcl_status qcl_batch_workspace_bytes(const qcl_batch_item *items, int32_t n_items, size_t *bytes)
+{
+    if (!bytes)
+        return fail(QCL_ERR_INVALID_ARG, "bytes is NULL");
+    BatchPlan plan;
+    if (qcl_status st = plan_batch(items, n_items, plan))
+        return st;
+    *bytes = plan.bytes;
+    return QCL_OK;
+}
+
+qcl_status qcl_propagate_batch(const qcl_batch_item *items, int32_t n_items, void *workspace, size_t workspace_bytes,
+                               void *stream)
+{
+    BatchPlan plan;
+    if (qcl_status st = plan_batch(items, n_items, plan))
+        return st;
+    if (plan.bytes > 0) {
+        if (!workspace || ((uintptr_t)workspace % 256))
+            return fail(QCL_ERR_INVALID_ARG, "workspace is NULL or not 256-byte aligned");
+        if (workspace_bytes < plan.bytes)
+            return fail(QCL_ERR_INVALID_ARG, "workspace holds %zu bytes, %zu needed", workspace_bytes, plan.bytes);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *ws = (uint8_t *)workspace;
+    std::vector<uint64_t> words(plan.bytes / 8, 0);
+    for (const BatchClass &c : plan.classes) {
+        int64_t tile_begin = 0;
+        for (size_t k = 0; k < c.order.size(); ++k) {
+            const qcl_batch_item &it = items[c.order[k]];
+            qcl::batch_item(*it.model, *it.ens, it.prop, it.partials, tile_begin,
+                            (uint8_t *)words.data() + c.offset + k * c.item_bytes);
+            tile_begin += qcl::n_tiles(it.ens->n_traj);
+        }
+    }
+    if (plan.bytes > 0) {
+        // counters (first word of each class block) are zero in the uploaded image
+        hipError_t e = qcl::upload_words(words.data(), words.size(), (uint64_t *)ws, s);
+        if (e != hipSuccess)
+            return device_fail(e, "batch descriptor upload");
+    }
+    for (const BatchClass &c : plan.classes) {
+        hipError_t e = qcl::launch_batch(*items[c.order[0]].model, c.prec, c.scheme, ws + c.offset,
+                                         (int32_t)c.order.size(), c.total_tiles,
+                                         (unsigned long long *)(ws + c.counter_offset), s);
+        if (e == hipErrorNotSupported)
+            return fail(QCL_ERR_UNSUPPORTED, "no batched kernel for this model class");
+        if (e != hipSuccess)
+            return device_fail(e, "batched propagate launch");
+    }
+    for (int32_t i = 0; i < n_items; ++i)
+        items[i].ens->step += items[i].prop.n_steps;
     return QCL_OK;
 }
 

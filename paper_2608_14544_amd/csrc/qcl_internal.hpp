@@ -101,6 +101,27 @@ struct PropArgs {
     int32_t m;  // modes actually present (general kernels)
 };
 
+// Batched work: one descriptor per instance, tile_begin = prefix sum of the
+// tiles of the preceding descriptors of the same kernel class.
+template <int M, typename R>
+struct BatchItemN2 {
+    N2Const<M, R> C;
+    PropArgs P;
+    EnsDev<R> E;
+    double *partials;
+    int64_t tile_begin;
+};
+
+template <typename R>
+struct BatchItemGen {
+    GenConst<R> C;
+    GenConst<double> C64;
+    PropArgs P;
+    EnsDev<R> E;
+    double *partials;
+    int64_t tile_begin;
+};
+
 }  // namespace qcl
 
 struct qcl_model_s {
@@ -142,6 +163,53 @@ hipError_t launch_propagate_general_n(const qcl_model_s &m, const qcl_ensemble &
                                       double *partials, hipStream_t s, int_<3>);
 hipError_t launch_propagate_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
                                       double *partials, hipStream_t s, int_<4>);
+
+size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
+                            double *partials, int64_t tile_begin, void *out, int_<2>);
+size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
+                            double *partials, int64_t tile_begin, void *out, int_<3>);
+size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
+                            double *partials, int64_t tile_begin, void *out, int_<4>);
+hipError_t launch_batch_general_n(int mp, int prec, int scheme, const void *items, int32_t n_items,
+                                  int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<2>);
+hipError_t launch_batch_general_n(int mp, int prec, int scheme, const void *items, int32_t n_items,
+                                  int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<3>);
+hipError_t launch_batch_general_n(int mp, int prec, int scheme, const void *items, int32_t n_items,
+                                  int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<4>);
+size_t batch_item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
+                     int64_t tile_begin, void *out);
+hipError_t launch_batch_n2(int modes, int prec, int scheme, const void *items, int32_t n_items, int64_t total_tiles,
+                           unsigned long long *counter, hipStream_t s);
+// device-side copy of host words carried in kernel arguments; zeroing of counters
+hipError_t upload_words(const uint64_t *words, size_t n_words, uint64_t *dst, hipStream_t s);
+hipError_t zero_words(uint64_t *dst, size_t n_words, hipStream_t s);
+
+inline size_t batch_item(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
+                         int64_t tile_begin, void *out)
+{
+    if (m.fast2)
+        return batch_item_n2(m, ens, pd, partials, tile_begin, out);
+    switch (m.n) {
+    case 2: return batch_item_general_n(m, ens, pd, partials, tile_begin, out, int_<2>{});
+    case 3: return batch_item_general_n(m, ens, pd, partials, tile_begin, out, int_<3>{});
+    case 4: return batch_item_general_n(m, ens, pd, partials, tile_begin, out, int_<4>{});
+    default: return 0;
+    }
+}
+
+inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, const void *items, int32_t n_items,
+                               int64_t total_tiles, unsigned long long *counter, hipStream_t s)
+{
+    if (m.fast2)
+        return launch_batch_n2(m.m, prec, scheme, items, n_items, total_tiles, counter, s);
+    const int mp = padded_modes(m.m);
+    switch (m.n) {
+    case 2: return launch_batch_general_n(mp, prec, scheme, items, n_items, total_tiles, counter, s, int_<2>{});
+    case 3: return launch_batch_general_n(mp, prec, scheme, items, n_items, total_tiles, counter, s, int_<3>{});
+    case 4: return launch_batch_general_n(mp, prec, scheme, items, n_items, total_tiles, counter, s, int_<4>{});
+    default: return hipErrorNotSupported;
+    }
+}
 
 inline hipError_t launch_sample_general(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,
                                         double *partials, int32_t n_out, hipStream_t s)

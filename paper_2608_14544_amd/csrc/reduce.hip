@@ -7,6 +7,7 @@
 // until one row remains.  The final kernel turns the sums into means and
 // standard errors.  The work is HBM-bound and tiny next to propagation.
 #include <algorithm>
+#include <cstring>
 
 #include "qcl_internal.hpp"
 
@@ -47,7 +48,50 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict_
     out[4 * g + 3] = (T > 1.0 && vi > 0.0) ? sqrt(vi) : 0.0;
 }
 
+// Host words travel inside the kernel arguments (captured at launch), so the
+// copy is asynchronous with no host buffer to keep alive, and graph-safe.
+constexpr int kUploadWords = 480;
+struct WordChunk {
+    uint64_t w[kUploadWords];
+    int32_t n;
+};
+
+__global__ __launch_bounds__(256) void upload_kernel(WordChunk c, uint64_t *__restrict__ dst)
+{
+    for (int i = threadIdx.x; i < c.n; i += blockDim.x)
+        dst[i] = c.w[i];
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(uint64_t *__restrict__ dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = 0;
+}
+
 }  // namespace
+
+hipError_t upload_words(const uint64_t *words, size_t n_words, uint64_t *dst, hipStream_t s)
+{
+    for (size_t off = 0; off < n_words; off += kUploadWords) {
+        WordChunk c;
+        c.n = (int32_t)std::min<size_t>(kUploadWords, n_words - off);
+        std::memcpy(c.w, words + off, sizeof(uint64_t) * c.n);
+        hipLaunchKernelGGL(upload_kernel, dim3(1), dim3(256), 0, s, c, dst + off);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t zero_words(uint64_t *dst, size_t n_words, hipStream_t s)
+{
+    if (n_words == 0)
+        return hipSuccess;
+    const int64_t blocks = std::min<int64_t>(((int64_t)n_words + 255) / 256, 1024);
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, (int64_t)n_words);
+    return hipGetLastError();
+}
 
 hipError_t launch_reduce(int n_states, double *partials, int64_t n_traj, int32_t n_out, double *out, hipStream_t s)
 {

@@ -71,9 +71,15 @@ class qcl_prop_desc(C.Structure):
                 ("block", C.c_int32), ("reserved", C.c_int32)]
 
 
+class qcl_batch_item(C.Structure):
+    _fields_ = [("model", C.c_void_p), ("ens", C.POINTER(qcl_ensemble)), ("prop", qcl_prop_desc),
+                ("partials", C.c_void_p)]
+
+
 EXPORTS = ("qcl_create_model", "qcl_destroy_model", "qcl_model_states", "qcl_model_modes",
            "qcl_ensemble_bytes", "qcl_ensemble_bind", "qcl_partials_bytes",
-           "qcl_sample_initial", "qcl_propagate", "qcl_reduce_observables", "qcl_last_error")
+           "qcl_sample_initial", "qcl_propagate", "qcl_batch_workspace_bytes", "qcl_propagate_batch",
+           "qcl_reduce_observables", "qcl_last_error")
 
 _lock = threading.Lock()
 _lib = None
@@ -101,6 +107,8 @@ def load_library(path: str = LIB_PATH):
         L.qcl_sample_initial.argtypes = [vp, C.POINTER(qcl_init_desc), u64, C.POINTER(qcl_ensemble),
                                          vp, i32, vp]
         L.qcl_propagate.argtypes = [vp, C.POINTER(qcl_ensemble), C.POINTER(qcl_prop_desc), vp, vp]
+        L.qcl_batch_workspace_bytes.argtypes = [C.POINTER(qcl_batch_item), i32, C.POINTER(sz)]
+        L.qcl_propagate_batch.argtypes = [C.POINTER(qcl_batch_item), i32, vp, sz, vp]
         L.qcl_reduce_observables.argtypes = [vp, vp, i64, i32, vp, vp]
         L.qcl_last_error.argtypes = []
         L.qcl_last_error.restype = C.c_char_p
@@ -270,6 +278,58 @@ def qcl_propagate(model: Model, ens: Ensemble, dt: float, n_steps: int, cadence:
     pd = qcl_prop_desc(float(dt), int(n_steps), int(cadence), partials.n_out, int(scheme), int(seed), 0, 0)
     _check(load_library().qcl_propagate(model.handle, C.byref(ens.c), C.byref(pd), partials.ptr,
                                         C.c_void_p(_stream_handle(stream))))
+
+
+class BatchJob:
+    """Arguments of one qcl_propagate call, as an item of a batch."""
+
+    def __init__(self, model: Model, ens: Ensemble, partials: Partials, dt: float, n_steps: int,
+                 cadence: int, seed: int, scheme: int = QCL_TRANS_NORMALIZED):
+        self.model, self.ens, self.partials = model, ens, partials
+        self.dt, self.n_steps, self.cadence = float(dt), int(n_steps), int(cadence)
+        self.seed, self.scheme = int(seed), int(scheme)
+
+    def item(self) -> qcl_batch_item:
+        pd = qcl_prop_desc(self.dt, self.n_steps, self.cadence, self.partials.n_out, self.scheme,
+                           self.seed, 0, 0)
+        return qcl_batch_item(self.model.handle, C.pointer(self.ens.c), pd, self.partials.ptr)
+
+
+class Workspace:
+    """Device workspace for qcl_propagate_batch, grown on demand."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.tensor = None
+
+    def get(self, nbytes: int):
+        torch = _torch()
+        if nbytes == 0:
+            return None, 0
+        if self.tensor is None or self.tensor.numel() < nbytes:
+            # torch's caching allocator returns 512-byte aligned blocks
+            self.tensor = torch.empty(max(nbytes, 1 << 16), dtype=torch.uint8, device=self.device)
+        return C.c_void_p(self.tensor.data_ptr()), self.tensor.numel()
+
+
+def qcl_batch_workspace_bytes(jobs) -> int:
+    arr = (qcl_batch_item * len(jobs))(*[j.item() for j in jobs])
+    nb = C.c_size_t(0)
+    _check(load_library().qcl_batch_workspace_bytes(arr, len(jobs), C.byref(nb)))
+    return nb.value
+
+
+def qcl_propagate_batch(jobs, workspace: Optional[Workspace] = None, stream=None):
+    """Advances every job by its n_steps in per-class persistent launches;
+    each job's result is bitwise its solo qcl_propagate result."""
+    L = load_library()
+    arr = (qcl_batch_item * len(jobs))(*[j.item() for j in jobs])
+    nb = C.c_size_t(0)
+    _check(L.qcl_batch_workspace_bytes(arr, len(jobs), C.byref(nb)))
+    ws = workspace or Workspace()
+    ptr, have = ws.get(nb.value)
+    _check(L.qcl_propagate_batch(arr, len(jobs), ptr, have, C.c_void_p(_stream_handle(stream))))
+    return ws
 
 
 def qcl_reduce_observables(model: Model, partials: Partials, n_traj: int, out=None, stream=None):

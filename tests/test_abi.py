@@ -78,6 +78,19 @@ def test_null_arguments_rejected():
     assert L.qcl_ensemble_bytes(None, 10, 0, C.byref(ld), C.byref(b)) == qcl.QCL_ERR_INVALID_ARG
     assert L.qcl_partials_bytes(None, 10, 1, C.byref(b)) == qcl.QCL_ERR_INVALID_ARG
     assert L.qcl_propagate(None, None, None, None, None) == qcl.QCL_ERR_INVALID_ARG
+
+
+def test_batch_validation_on_host():
+    qcl, L = _lib()
+    b = C.c_size_t(123)
+    assert L.qcl_batch_workspace_bytes(None, 0, C.byref(b)) == qcl.QCL_OK and b.value == 0
+    assert L.qcl_batch_workspace_bytes(None, 1, C.byref(b)) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_batch_workspace_bytes(None, -1, C.byref(b)) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_propagate_batch(None, 0, None, 0, None) == qcl.QCL_OK
+    items = (qcl.qcl_batch_item * 2)()
+    assert L.qcl_batch_workspace_bytes(items, 2, C.byref(b)) == qcl.QCL_ERR_INVALID_ARG
+    assert b"item 0" in L.qcl_last_error()
+    assert L.qcl_propagate_batch(items, 2, None, 0, None) == qcl.QCL_ERR_INVALID_ARG
     assert L.qcl_sample_initial(None, None, 0, None, None, 1, None) == qcl.QCL_ERR_INVALID_ARG
     assert L.qcl_reduce_observables(None, None, 1, 1, None, None) == qcl.QCL_ERR_INVALID_ARG
 

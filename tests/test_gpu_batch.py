@@ -1,0 +1,120 @@
+"""Batched propagation (one persistent launch per kernel class over
+(instance, tile) work items): every instance's walkers and observables
+must be bitwise those of its solo qcl_propagate run, whatever else shares
+the launch, and a batch must agree with the FP64 oracle like a solo run."""
+import numpy as np
+import pytest
+
+import workloads as W
+from test_gpu_parity import compare_walkers, ensemble_close, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2608_14544_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def _mix():
+    """Uneven instances covering every kernel family: two-state closed form
+    (1, 3 and 8 modes), general N = 2 (12 modes), 3 and 4 states, both
+    precisions and both transition rules, ragged walker counts."""
+    return [
+        (W.spin_boson_1mode(), "fp64", 0, 700),
+        (W.pyrazine_ci(n_traj=1000, n_steps=120, cadence=10), "fp32", 0, 1000),
+        (W.pyrazine_ci(n_traj=257, n_steps=77, cadence=7, seed=11), "fp32", 0, 257),
+        (W.random_lvc(7, n_states=2, n_modes=8, n_traj=513, n_steps=90, cadence=9), "fp64", 1, 513),
+        (W.spin_boson_ohmic(kT=1.0, n_traj=300, n_steps=60, cadence=20, n_modes=12), "fp64", 0, 300),
+        (W.random_lvc(8, n_states=3, n_modes=4, n_traj=900, n_steps=100, cadence=10), "fp32", 0, 900),
+        (W.random_lvc(9, n_states=3, n_modes=4, n_traj=64, n_steps=30, cadence=10), "fp32", 0, 64),
+        (W.random_lvc(10, n_states=4, n_modes=6, n_traj=1, n_steps=50, cadence=25), "fp64", 0, 1),
+        (W.random_lvc(11, n_states=4, n_modes=20, n_traj=400, n_steps=40, cadence=20), "fp64", 1, 400),
+    ]
+
+
+def _setup(P, wl, prec, T):
+    r = wl.run
+    model = P.Model(wl.model)
+    ens = P.Ensemble(model, T, prec)
+    part = P.Partials(model, T, r.n_steps // r.cadence + 1)
+    P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
+    return model, ens, part
+
+
+def _solo(P, wl, prec, scheme, T):
+    model, ens, part = _setup(P, wl, prec, T)
+    r = wl.run
+    P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part, scheme)
+    out = P.qcl_reduce_observables(model, part, T)
+    return out.cpu().numpy(), ens.to_numpy()
+
+
+def _batched(P, mix, slices=(None,)):
+    import torch
+    runs = [(_setup(P, wl, prec, T), wl, scheme, T) for wl, prec, scheme, T in mix]
+    ws = P.Workspace()
+    done = [0] * len(runs)
+    for frac in slices:
+        jobs = []
+        for i, ((model, ens, part), wl, scheme, T) in enumerate(runs):
+            r = wl.run
+            n = r.n_steps - done[i] if frac is None else min(r.n_steps - done[i], int(r.n_steps * frac))
+            done[i] += n
+            jobs.append(P.BatchJob(model, ens, part, r.dt, n, r.cadence, r.seed, scheme))
+        P.qcl_propagate_batch(jobs, ws)
+    outs = []
+    for i, ((model, ens, part), wl, scheme, T) in enumerate(runs):
+        assert done[i] == wl.run.n_steps and ens.step == wl.run.n_steps
+        outs.append((P.qcl_reduce_observables(model, part, T).cpu().numpy(), ens.to_numpy()))
+    torch.cuda.synchronize()
+    return outs
+
+
+def _assert_same(a, b, label):
+    out_a, st_a = a
+    out_b, st_b = b
+    for k in st_a:
+        assert np.array_equal(st_a[k], st_b[k]), (label, k)
+    assert np.array_equal(out_a, out_b), label
+
+
+def test_batch_bitwise_equals_solo(P):
+    mix = _mix()
+    solo = [_solo(P, wl, prec, scheme, T) for wl, prec, scheme, T in mix]
+    batch = _batched(P, mix)
+    for i, (s, b) in enumerate(zip(solo, batch)):
+        _assert_same(s, b, f"item {i}")
+
+
+def test_batch_sliced_equals_solo(P):
+    """K-step slices of a batch (continuous-batching quanta) change nothing."""
+    mix = _mix()[:6]
+    solo = [_solo(P, wl, prec, scheme, T) for wl, prec, scheme, T in mix]
+    batch = _batched(P, mix, slices=(0.3, 0.3, None))
+    for i, (s, b) in enumerate(zip(solo, batch)):
+        _assert_same(s, b, f"item {i}")
+
+
+def test_batch_matches_oracle(P):
+    mix = [m for m in _mix() if m[1] == "fp64" and m[2] == 0]
+    batch = _batched(P, mix)
+    for (wl, prec, scheme, T), (out_g, st_g) in zip(mix, batch):
+        out_o, st_o, _, _ = oracle_run(wl, n_traj=T)
+        nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label="batch")
+        if nflip == 0:
+            assert ensemble_close(out_g, out_o, T)
+
+
+def test_batch_rejects_shared_ensemble(P):
+    wl = W.pyrazine_ci(n_traj=100, n_steps=20, cadence=10)
+    model, ens, part = _setup(P, wl, "fp64", 100)
+    r = wl.run
+    jobs = [P.BatchJob(model, ens, part, r.dt, 10, r.cadence, r.seed)] * 2
+    with pytest.raises(P.QCLError):
+        P.qcl_propagate_batch(jobs)
+    assert ens.step == 0
