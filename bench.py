@@ -10,9 +10,18 @@ value = walkers * time steps / wall time of the step, in trajectory-steps/s,
 for the headline precision (binary32 propagation with binary64 phase,
 weights and sums).  The plain binary64 path is timed the same way and
 reported beside it, with the largest population difference between the
-two.  Prints one JSON line.
+two.  Two further legs are reported in the same line:
+
+  batched  256 seeded N-state (2-4) harmonic instances (1-64 modes, 1e4-1e6
+           walkers, 500-4000 steps, binary32) advanced by one
+           qcl_propagate_batch call: walker-steps/s of that call;
+  served   a Poisson stream of jobs (20 jobs/s) through the
+           continuous-batching server: walker-steps/s and p50/p99 latency.
+
+Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--prec fp32|fp64] [--n-traj T]
+                    [--legs headline,batched,served]
 """
 from __future__ import annotations
 
@@ -98,6 +107,57 @@ def cpu_baseline(wl, target_s: float):
                       f"{dt:.1f} s, FP64 C oracle, OpenMP over walkers"}
 
 
+def batched_leg(P, torch, n_instances=256):
+    """One qcl_propagate_batch call over the seeded heterogeneous instances
+    (ensembles sampled beforehand, resident in HBM)."""
+    import workloads as W
+    wls = W.batched_instances(n_instances)
+    jobs, tot = [], 0
+    stream = torch.cuda.current_stream()
+    for wl in wls:
+        r = wl.run
+        model = P.Model(wl.model)
+        ens = P.Ensemble(model, r.n_traj, "fp32", zero=False)
+        part = P.Partials(model, r.n_traj, r.n_out)
+        P.qcl_sample_initial(model, wl.init, r.seed, ens, part, stream)
+        jobs.append(P.BatchJob(model, ens, part, r.dt, r.n_steps, r.cadence, r.seed))
+        tot += r.n_traj * r.n_steps
+    ws = P.Workspace()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    P.qcl_propagate_batch(jobs, ws, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    classes = {}
+    for wl in wls:
+        N, M = wl.model.n_states, wl.model.n_modes
+        classes[(N, M)] = classes.get((N, M), 0) + 1
+    return {"workload": f"{n_instances} seeded N-state harmonic instances (N 2-4, M 1-64, 1e4-1e6 walkers, "
+                        "500-4000 steps), fp32, one qcl_propagate_batch call",
+            "value": tot / (ms / 1e3), "unit": "trajectory-steps/s", "walker_steps": tot,
+            "ms": ms, "wall_ms": wall * 1e3}
+
+
+def served_leg(P, torch, n_jobs=40, rate=20.0, quantum=50):
+    import workloads as W
+    from paper_2608_14544_amd.serve import DeviceBackend, JobSpec, Server, latency_stats
+    arrivals, wls = W.served_stream(n_jobs, rate=rate)
+    specs = [JobSpec(wl, prec="fp32", name=f"job{i}") for i, wl in enumerate(wls)]
+    srv = Server(DeviceBackend(), quantum_steps=quantum)
+    res = srv.run(arrivals, specs)
+    st = latency_stats(res)
+    st.update({"workload": f"{n_jobs} jobs, Poisson arrivals at {rate} jobs/s: 1-mode and 3-mode spin-boson, "
+                           "pyrazine-like CI, N-state (2-4) harmonic models with up to 100 modes and 1e5-1e8 "
+                           "walkers; fp32",
+               "rounds": srv.rounds, "quantum_steps": quantum,
+               "memory_budget_GB": srv.budget / 1e9})
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +168,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--legs", default="headline,batched,served",
+                    help="comma-separated subset of headline,batched,served")
+    ap.add_argument("--served-jobs", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -199,6 +262,16 @@ def main():
         print(f"[bench] {other}: {ms2:.2f} ms/step, propagate {mp2:.2f} ms; max |dP| {dpop} over {n_res} "
               f"resolved bins", file=sys.stderr, flush=True)
 
+    legs = set(args.legs.split(","))
+    if "batched" in legs:
+        line["batched"] = batched_leg(P, torch)
+        print(f"[bench] batched: {line['batched']['value']:.3e} trajectory-steps/s "
+              f"({line['batched']['ms']:.0f} ms)", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    if "served" in legs:
+        line["served"] = served_leg(P, torch, args.served_jobs)
+        print(f"[bench] served: {line['served']}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -169,6 +169,14 @@ class Model:
         except Exception:
             pass
 
+    @staticmethod
+    def ensemble_bytes(handle, n_traj: int, prec) -> int:
+        ld = C.c_int64()
+        b = C.c_size_t()
+        pr = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        _check(load_library().qcl_ensemble_bytes(handle, int(n_traj), pr, C.byref(ld), C.byref(b)))
+        return int(b.value)
+
     def partials_bytes(self, n_traj: int, n_out: int) -> int:
         b = C.c_size_t()
         _check(load_library().qcl_partials_bytes(self.handle, int(n_traj), int(n_out), C.byref(b)))
@@ -180,7 +188,8 @@ class Model:
 class Ensemble:
     """Device-resident walker ensemble in one torch allocation."""
 
-    def __init__(self, model: Model, n_traj: int, prec="fp64", traj_offset: int = 0, device="cuda"):
+    def __init__(self, model: Model, n_traj: int, prec="fp64", traj_offset: int = 0, device="cuda",
+                 zero: bool = True):
         torch = _torch()
         L = load_library()
         self.model = model
@@ -188,7 +197,10 @@ class Ensemble:
         ld = C.c_int64()
         nbytes = C.c_size_t()
         _check(L.qcl_ensemble_bytes(model.handle, int(n_traj), self.prec, C.byref(ld), C.byref(nbytes)))
-        self.buffer = torch.zeros(int(nbytes.value), dtype=torch.uint8, device=device)
+        # qcl_sample_initial writes every array entry a kernel reads, so an
+        # ensemble that is sampled next need not be cleared
+        alloc = torch.zeros if zero else torch.empty
+        self.buffer = alloc(int(nbytes.value), dtype=torch.uint8, device=device)
         self.c = qcl_ensemble()
         _check(L.qcl_ensemble_bind(model.handle, C.c_void_p(self.buffer.data_ptr()), int(n_traj), self.prec,
                                    int(traj_offset), C.byref(self.c)))

@@ -1,0 +1,371 @@
+"""Continuous-batching job server for QCL ensembles on one GPU.
+
+Jobs (a model, an initial state, a walker count, a step count, a
+precision) arrive over time.  The server keeps every admitted ensemble
+resident in device memory and advances all of them together in quanta of
+at most ``quantum_steps`` steps, one ``qcl_propagate_batch`` call per
+quantum (Sec. II.B: walkers are independent, so ensembles of different
+models and sizes can share a launch).  Between quanta it
+
+  * admits queued jobs while their device footprint (walker arrays,
+    partial sums, result buffer) fits the memory budget and a slot is free
+    (first come first served; a job that does not fit lets smaller ones
+    behind it start, until it has waited ``max_backfill_wait`` seconds);
+  * retires jobs whose last step has been enqueued: their observables are
+    reduced on the device, copied to host memory asynchronously and their
+    device buffers are given back.
+
+Because a batched launch and any split of the steps into calls leave each
+ensemble's arithmetic unchanged, a job's result is bitwise the one it gets
+when run alone.
+
+The device work sits behind a small backend interface so that the
+scheduling logic can be exercised without a GPU (see ``SimBackend``).
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Deque, Dict, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class JobSpec:
+    """One simulation request: ``workload`` is a ``workloads.Workload``."""
+    workload: object
+    prec: str = "fp32"
+    scheme: int = 0
+    name: str = ""
+
+    @property
+    def n_traj(self) -> int:
+        return int(self.workload.run.n_traj)
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.workload.run.n_steps)
+
+    @property
+    def walker_steps(self) -> int:
+        return self.n_traj * self.n_steps
+
+
+@dataclasses.dataclass
+class JobResult:
+    job_id: int
+    name: str
+    out: Optional[np.ndarray]     # [n_out, 2, N, N, 4] (mean Re, mean Im, SE Re, SE Im)
+    arrival: float                # seconds on the server clock
+    admitted: float
+    finished: float
+    walker_steps: int
+    error: str = ""
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+@dataclasses.dataclass
+class _Job:
+    job_id: int
+    spec: JobSpec
+    arrival: float
+    footprint: int
+    admitted: float = -1.0
+    done_steps: int = 0
+    handle: object = None
+    pending: object = None        # backend result future once retired
+
+
+class DeviceBackend:
+    """Device work through the C ABI (one stream, default priority)."""
+
+    def __init__(self, stream=None):
+        import torch
+        from . import qcl as Q
+        self.Q = Q
+        self.torch = torch
+        Q.load_library()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        # descriptors are uploaded by a kernel on the same stream, so one
+        # workspace serves every round
+        self.ws = Q.Workspace()
+        self._models: Dict[tuple, object] = {}
+
+    def _model(self, lvc):
+        key = (lvc.name, lvc.hbar, lvc.mass.tobytes(), lvc.omega.tobytes(), lvc.v0.tobytes(), lvc.k.tobytes())
+        m = self._models.get(key)
+        if m is None:
+            m = self.Q.Model(lvc)
+            self._models[key] = m
+        return m
+
+    def footprint(self, spec: JobSpec) -> int:
+        m = self._model(spec.workload.model)
+        r = spec.workload.run
+        n_out = r.n_steps // r.cadence + 1
+        N = m.n_states
+        return (self.Q.Model.ensemble_bytes(m.handle, r.n_traj, spec.prec)
+                + m.partials_bytes(r.n_traj, n_out) + n_out * 2 * N * N * 4 * 8)
+
+    def start(self, spec: JobSpec):
+        Q = self.Q
+        wl = spec.workload
+        r = wl.run
+        m = self._model(wl.model)
+        with self.torch.cuda.stream(self.stream):
+            ens = Q.Ensemble(m, r.n_traj, spec.prec, zero=False)
+            part = Q.Partials(m, r.n_traj, r.n_steps // r.cadence + 1)
+            Q.qcl_sample_initial(m, wl.init, r.seed, ens, part, stream=self.stream)
+        return (m, ens, part)
+
+    def advance(self, work):
+        """work: list of (handle, spec, n_steps); one batched launch."""
+        Q = self.Q
+        jobs = [Q.BatchJob(h[0], h[1], h[2], s.workload.run.dt, n, s.workload.run.cadence,
+                           s.workload.run.seed, s.scheme) for h, s, n in work]
+        with self.torch.cuda.stream(self.stream):
+            Q.qcl_propagate_batch(jobs, self.ws, stream=self.stream)
+
+    def finish(self, handle, spec: JobSpec):
+        """Enqueues the reduction and the copy to host; returns a future."""
+        torch = self.torch
+        m, ens, part = handle
+        with torch.cuda.stream(self.stream):
+            out = self.Q.qcl_reduce_observables(m, part, spec.n_traj, stream=self.stream)
+            host = torch.empty(out.shape, dtype=out.dtype, pin_memory=True)
+            host.copy_(out, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        return _DeviceFuture(ev, host, (out, part, ens))
+
+    def release(self, handle):
+        pass  # tensors go back to the stream-ordered caching allocator with the handle
+
+    def barrier(self):
+        ev = self.torch.cuda.Event()
+        ev.record(self.stream)
+        return ev
+
+    def wait(self, token):
+        token.synchronize()
+
+
+class _DeviceFuture:
+    def __init__(self, ev, host, keep):
+        self.ev, self.host, self.keep = ev, host, keep
+
+    def ready(self) -> bool:
+        if self.ev.query():
+            self.keep = None
+            return True
+        return False
+
+    def result(self) -> np.ndarray:
+        self.ev.synchronize()
+        self.keep = None
+        return self.host.numpy().copy()
+
+
+class Server:
+    def __init__(self, backend=None, memory_budget: Optional[int] = None, max_slots: int = 64,
+                 quantum_steps: int = 50, max_backfill_wait: float = 2.0,
+                 clock: Callable[[], float] = time.perf_counter, max_in_flight: int = 2):
+        self.backend = backend if backend is not None else DeviceBackend()
+        if memory_budget is None:
+            import torch
+            free, _ = torch.cuda.mem_get_info()
+            memory_budget = int(0.85 * free)
+        self.budget = int(memory_budget)
+        self.max_slots = int(max_slots)
+        self.quantum = int(quantum_steps)
+        self.max_backfill_wait = float(max_backfill_wait)
+        self.clock = clock
+        self.t0 = clock()
+        self.max_in_flight = max(1, int(max_in_flight))
+        self.queue: Deque[_Job] = collections.deque()
+        self.active: List[_Job] = []
+        self.draining: List[_Job] = []
+        self.results: List[JobResult] = []
+        self.used = 0
+        self.next_id = 0
+        self.tokens: Deque[object] = collections.deque()
+        self.rounds = 0
+
+    def now(self) -> float:
+        return self.clock() - self.t0
+
+    # ---------------------------------------------------------------- API
+    def submit(self, spec: JobSpec, arrival: Optional[float] = None) -> int:
+        jid = self.next_id
+        self.next_id += 1
+        t = self.now() if arrival is None else float(arrival)
+        fp = int(self.backend.footprint(spec))
+        job = _Job(jid, spec, t, fp)
+        if fp > self.budget:
+            self.results.append(JobResult(jid, spec.name, None, t, t, t, 0,
+                                          error=f"footprint {fp} B exceeds the memory budget {self.budget} B"))
+        else:
+            self.queue.append(job)
+        return jid
+
+    def idle(self) -> bool:
+        return not (self.queue or self.active or self.draining)
+
+    def step(self) -> List[JobResult]:
+        """One scheduling round: retire, admit, launch one quantum."""
+        done = self._collect()
+        self._admit()
+        if self.active:
+            while len(self.tokens) >= self.max_in_flight:
+                self.backend.wait(self.tokens.popleft())
+            work = []
+            for j in self.active:
+                n = min(self.quantum, j.spec.n_steps - j.done_steps)
+                work.append((j.handle, j.spec, n))
+                j.done_steps += n
+            self.backend.advance([w for w in work if w[2] > 0])
+            self.tokens.append(self.backend.barrier())
+            self.rounds += 1
+            still = []
+            for j in self.active:
+                if j.done_steps >= j.spec.n_steps:
+                    j.pending = self.backend.finish(j.handle, j.spec)
+                    self.backend.release(j.handle)
+                    j.handle = None
+                    self.used -= j.footprint
+                    self.draining.append(j)
+                else:
+                    still.append(j)
+            self.active = still
+        return done
+
+    def run(self, arrivals: Optional[List[float]] = None, specs: Optional[List[JobSpec]] = None,
+            idle_sleep: float = 2e-4) -> List[JobResult]:
+        """Serves ``specs`` arriving at ``arrivals`` (seconds from now) and
+        returns every result in completion order."""
+        specs = specs or []
+        arrivals = list(arrivals or [0.0] * len(specs))
+        assert len(arrivals) == len(specs) and arrivals == sorted(arrivals)
+        self.t0 = self.clock()
+        k = 0
+        while k < len(specs) or not self.idle():
+            t = self.now()
+            while k < len(specs) and arrivals[k] <= t:
+                self.submit(specs[k], arrival=arrivals[k])
+                k += 1
+            self.step()
+            if not self.active and not self.draining and not self.queue and k < len(specs):
+                time.sleep(max(0.0, min(idle_sleep * 50, arrivals[k] - self.now())))
+            elif not self.active and self.draining:
+                time.sleep(idle_sleep)
+        return self.results
+
+    # ------------------------------------------------------------ internals
+    def _collect(self) -> List[JobResult]:
+        done, keep = [], []
+        for j in self.draining:
+            if j.pending.ready():
+                r = JobResult(j.job_id, j.spec.name, j.pending.result(), j.arrival, j.admitted, self.now(),
+                              j.spec.walker_steps)
+                self.results.append(r)
+                done.append(r)
+            else:
+                keep.append(j)
+        self.draining = keep
+        return done
+
+    def _admit(self):
+        now = self.now()
+        blocked_head = None
+        for j in list(self.queue):
+            if len(self.active) >= self.max_slots:
+                break
+            fits = self.used + j.footprint <= self.budget
+            if blocked_head is not None and now - blocked_head.arrival > self.max_backfill_wait:
+                break  # stop backfilling so memory drains for the head
+            if not fits:
+                if blocked_head is None:
+                    blocked_head = j
+                continue
+            self.queue.remove(j)
+            j.handle = self.backend.start(j.spec)
+            j.admitted = now
+            self.used += j.footprint
+            self.active.append(j)
+
+
+def latency_stats(results: List[JobResult]) -> dict:
+    ok = [r for r in results if not r.error]
+    lat = np.array([r.latency for r in ok])
+    if len(lat) == 0:
+        return {"n_jobs": 0}
+    span = max(r.finished for r in ok) - min(r.arrival for r in ok)
+    return {
+        "n_jobs": len(ok), "n_rejected": len(results) - len(ok),
+        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+        "mean_s": float(lat.mean()), "max_s": float(lat.max()),
+        "makespan_s": float(span),
+        "walker_steps_per_s": float(sum(r.walker_steps for r in ok) / span) if span > 0 else None,
+    }
+
+
+class SimBackend:
+    """Host-only stand-in for the device: footprints from a formula, work
+    completes after a modelled time.  Lets the scheduler run without a GPU."""
+
+    def __init__(self, clock: Callable[[], float], bytes_per_walker: int = 100,
+                 walker_steps_per_s: float = 1e9, sleep_until: Optional[Callable[[float], None]] = None):
+        self.clock = clock
+        self.sleep_until = sleep_until
+        self.bpw = bytes_per_walker
+        self.rate = walker_steps_per_s
+        self.busy_until = 0.0
+        self.log: List[list] = []
+        self.started: List[int] = []
+
+    def footprint(self, spec: JobSpec) -> int:
+        return spec.n_traj * self.bpw
+
+    def start(self, spec: JobSpec):
+        self.started.append(id(spec))
+        return {"spec": spec, "steps": 0}
+
+    def advance(self, work):
+        t = max(self.clock(), self.busy_until)
+        cost = sum(s.n_traj * n for _, s, n in work) / self.rate
+        self.busy_until = t + cost
+        for h, s, n in work:
+            h["steps"] += n
+        self.log.append([(s.name, n) for _, s, n in work])
+
+    def finish(self, handle, spec):
+        return _SimFuture(self, self.busy_until, handle)
+
+    def release(self, handle):
+        pass
+
+    def barrier(self):
+        return self.busy_until
+
+    def wait(self, token):
+        if self.sleep_until is not None:
+            self.sleep_until(token)
+            return
+        while self.clock() < token:
+            time.sleep(1e-4)
+
+
+class _SimFuture:
+    def __init__(self, be, t, handle):
+        self.be, self.t, self.handle = be, t, handle
+
+    def ready(self):
+        return self.be.clock() >= self.t
+
+    def result(self):
+        return np.array([self.handle["steps"]], dtype=np.float64)
