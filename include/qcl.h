@@ -82,7 +82,9 @@ typedef enum {
 /* per-walker diagnostic bits (qcl_ensemble.flags) */
 #define QCL_FLAG_NONFINITE 1u   /* w or Phi not finite: walker excluded from sums */
 #define QCL_FLAG_DEGENERATE 2u  /* an adiabatic gap below DBL_MIN was met */
-#define QCL_FLAG_RESOLVED64 4u  /* binary32 path re-solved a small gap in binary64 */
+#define QCL_FLAG_RESOLVED64 4u  /* binary32 path met a gap below the model threshold and
+                                   treated it in binary64 (N = 2: closed form re-evaluated;
+                                   N > 2: closest pair re-rotated) */
 #define QCL_FLAG_FALLBACK 8u    /* linear rule fell back to the normalized one */
 
 typedef struct qcl_model_s *qcl_model; /* opaque, library-owned, immutable */

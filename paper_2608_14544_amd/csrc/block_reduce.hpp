@@ -169,4 +169,69 @@ __device__ __forceinline__ void block_reduce_store32(double (&v)[32], int slot, 
     __syncthreads();
 }
 
+// Value index each lane holds after wave_reduce16.
+__device__ __forceinline__ int scatter_slot16(int lane)
+{
+    using namespace rdetail;
+    int id[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        int a = i, b = i + 8;
+        swap32i(a, b);
+        id[i] = a;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int a = id[i], b = id[i + 4];
+        swap16i(a, b);
+        id[i] = a;
+    }
+    id[0] = (lane & 8) ? id[2] : id[0];
+    id[1] = (lane & 8) ? id[3] : id[1];
+    id[0] = (lane & 4) ? id[1] : id[0];
+    return id[0];
+}
+
+// Reduce-scatter of 16 doubles over the 64 lanes (the same stages as
+// wave_reduce32 with half the values live): lane l ends with the wavefront
+// total of value scatter_slot16(l) in v[0] (lanes l, l^1, l^2, l^3 agree).
+__device__ __forceinline__ void wave_reduce16(double (&v)[16], int lane)
+{
+    using namespace rdetail;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        double a = v[i], b = v[i + 8];
+        swap32(a, b);
+        v[i] = a + b;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double a = v[i], b = v[i + 4];
+        swap16(a, b);
+        v[i] = a + b;
+    }
+    narrow_stage<8, 2>(v, (lane & 8) != 0);
+    narrow_stage<4, 1>(v, (lane & 4) != 0);
+    v[0] = v[0] + xlane<2>(v[0]);
+    v[0] = v[0] + xlane<1>(v[0]);
+}
+
+// block_reduce_store32 for 16 values; lds holds 4*16 doubles,
+// slot = scatter_slot16(lane).
+__device__ __forceinline__ void block_reduce_store16(double (&v)[16], int slot, double *__restrict__ dst,
+                                                     double *lds, int n_valid = 16)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    wave_reduce16(v, lane);
+    if ((lane & 3) == 0)
+        lds[wave * 16 + slot] = v[0];
+    __syncthreads();
+    if (threadIdx.x < n_valid) {
+        const int t = threadIdx.x;
+        dst[t] = (lds[t] + lds[16 + t]) + (lds[32 + t] + lds[48 + t]);
+    }
+    __syncthreads();
+}
+
 }  // namespace qcl

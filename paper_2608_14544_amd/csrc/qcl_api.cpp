@@ -61,6 +61,65 @@ size_t real_size(int32_t prec) { return prec == QCL_FP64 ? sizeof(double) : size
 
 int64_t leading_dim(int64_t n_traj) { return std::max<int64_t>(64, (n_traj + 63) / 64 * 64); }
 
+// Orthonormal basis of the span of the M coupling rows K_j (each the T
+// upper-triangle slots of K_j) by pivoted Gram-Schmidt with
+// re-orthogonalisation; coef[j][r] = <K_j, B_r>.  Directions whose residual
+// falls below 1e-13 of the largest row are dropped, so sum_r coef B_r
+// reproduces every K_j to that relative accuracy.  Returns the rank.
+int factor_couplings(int M, int T, const std::vector<double> &kmat, std::vector<double> &basis,
+                     std::vector<double> &coef)
+{
+    auto dot = [T](const double *x, const double *y) {
+        double s = 0.0;
+        for (int i = 0; i < T; ++i)
+            s += x[i] * y[i];
+        return s;
+    };
+    std::vector<double> res(kmat);
+    double kmax = 0.0;
+    for (int j = 0; j < M; ++j)
+        kmax = std::max(kmax, std::sqrt(dot(&kmat[(size_t)j * T], &kmat[(size_t)j * T])));
+    basis.clear();
+    int rank = 0;
+    while (rank < T && kmax > 0.0) {
+        int best = -1;
+        double bn = 0.0;
+        for (int j = 0; j < M; ++j) {
+            const double nj = std::sqrt(dot(&res[(size_t)j * T], &res[(size_t)j * T]));
+            if (nj > bn) {
+                bn = nj;
+                best = j;
+            }
+        }
+        if (best < 0 || bn <= 1e-13 * kmax)
+            break;
+        std::vector<double> b(res.begin() + (size_t)best * T, res.begin() + (size_t)(best + 1) * T);
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int r = 0; r < rank; ++r) {
+                const double pr = dot(b.data(), &basis[(size_t)r * T]);
+                for (int i = 0; i < T; ++i)
+                    b[i] -= pr * basis[(size_t)r * T + i];
+            }
+            const double nb = std::sqrt(dot(b.data(), b.data()));
+            for (int i = 0; i < T; ++i)
+                b[i] /= nb;
+        }
+        basis.insert(basis.end(), b.begin(), b.end());
+        ++rank;
+        for (int j = 0; j < M; ++j)
+            for (int pass = 0; pass < 2; ++pass) {
+                const double pr = dot(&res[(size_t)j * T], b.data());
+                for (int i = 0; i < T; ++i)
+                    res[(size_t)j * T + i] -= pr * b[i];
+            }
+    }
+    coef.assign((size_t)M * std::max(rank, 1), 0.0);
+    for (int j = 0; j < M; ++j)
+        for (int r = 0; r < rank; ++r)
+            coef[(size_t)j * rank + r] = dot(&kmat[(size_t)j * T], &basis[(size_t)r * T]);
+    return rank;
+}
+
 qcl_status check_model(qcl_model m)
 {
     if (!m)
@@ -154,7 +213,8 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
         if (it.ens->n_traj == 0 || it.prop.n_steps == 0)
             continue;
         const qcl_model_s &m = *it.model;
-        const int modes = m.fast2 ? m.m : qcl::padded_modes(m.m);
+        // general kernels are specialised on padded modes and rank bucket
+        const int modes = m.fast2 ? m.m : qcl::padded_modes(m.m) * 64 + m.rank_pad;
         BatchClass *c = nullptr;
         for (BatchClass &k : plan.classes)
             if (k.fast2 == m.fast2 && k.n == m.n && k.modes == modes && k.prec == it.ens->prec &&
@@ -292,22 +352,32 @@ qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out)
         packed.insert(packed.end(), m->dlt.begin(), m->dlt.end());
         packed.insert(packed.end(), m->cpl.begin(), m->cpl.end());
     }
-    // general-N tables: v0 upper triangle, then per (zero-padded) mode
-    // m w^2, 1/m, K_j upper triangle; binary64 then binary32
+    // general-N tables (factored couplings), binary64 then binary32
     const int T = n * (n + 1) / 2;
+    std::vector<double> kmat((size_t)M * T), basis, coef;
+    for (int j = 0; j < M; ++j)
+        for (int k = 0, s = 0; k < n; ++k)
+            for (int l = k; l < n; ++l, ++s)
+                kmat[(size_t)j * T + s] = m->k[(size_t)j * n * n + k * n + l];
+    m->rank = factor_couplings(M, T, kmat, basis, coef);
+    m->rank_pad = qcl::rank_bucket(m->rank, n);
+    const int RB = m->rank_pad;
     std::vector<double> gen;
     for (int k = 0; k < n; ++k)
         for (int l = k; l < n; ++l)
             gen.push_back(m->v0[k * n + l]);
+    for (int r = 0; r < RB; ++r)
+        for (int s = 0; s < T; ++s)
+            gen.push_back(r < m->rank ? basis[(size_t)r * T + s] : 0.0);
     for (int j = 0; j < qcl::kMaxModesPad; ++j) {
         const bool real = j < M;
         gen.push_back(real ? m->mass[j] * m->omega[j] * m->omega[j] : 0.0);
         gen.push_back(real ? 1.0 / m->mass[j] : 0.0);
-        for (int k = 0; k < n; ++k)
-            for (int l = k; l < n; ++l)
-                gen.push_back(real ? m->k[(size_t)j * n * n + k * n + l] : 0.0);
+        for (int r = 0; r < RB; ++r)
+            gen.push_back(real && r < m->rank ? coef[(size_t)j * m->rank + r] : 0.0);
+        for (int r = 0; r < RB; ++r)
+            gen.push_back(real && r < m->rank ? coef[(size_t)j * m->rank + r] / m->mass[j] : 0.0);
     }
-    (void)T;
     while (packed.size() % 32)
         packed.push_back(0.0);
     m->gen64_offset = packed.size();

@@ -45,26 +45,33 @@ struct N2Const {
     const double *c64;
 };
 
-// General-N model constants in device memory (both precisions):
-//   v0 [T] upper triangle of V0 (T = N(N+1)/2, row-major),
-//   md [kMaxModesPad][2 + T] per mode: m w^2, 1/m, K_j upper triangle,
+// General-N model constants in device memory (both precisions).  The
+// mode couplings are factored as K_j = sum_r C_jr B_r over an orthonormal
+// basis {B_r} of the span of the K_j (rank R <= T = N(N+1)/2 upper-triangle
+// slots), padded with zero rows to a rank bucket RB in {1, N, T}:
+//   v0    [T]                        upper triangle of V0 (row-major)
+//   basis [RB][T]                    B_r
+//   modes [kMaxModesPad][2 + 2 RB]   m w^2, 1/m, C_j0..C_j(RB-1), C_jr/m_j
 // zero-padded past the model's modes so that padded modes stay at rest.
 constexpr int kMaxModesPad = 128;
 
 template <typename R>
 struct GenConst {
     const R *v0;
-    const R *md;
+    const R *basis;
+    const R *modes;
     R dt, hdt;
     double dt_hbar;
     R gap_thr;  // binary32 path: gaps below this are re-solved in binary64
-    R jac_tol;  // Jacobi stop: off-diagonal^2 <= jac_tol * diagonal^2
+    R rot_eps;  // Jacobi: rotate while |a_pq| > rot_eps * ||A||_F
 };
 
 inline int padded_modes(int m)
 {
-    return m <= 4 ? 4 : m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 128;
+    return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 128;
 }
+
+inline int rank_bucket(int rank, int n) { return rank <= 1 ? 1 : rank <= n ? n : n * (n + 1) / 2; }
 
 template <typename R>
 struct EnsDev {
@@ -139,6 +146,8 @@ struct qcl_model_s {
     size_t c64_offset = 0;      // element offset of the two-state constants
     size_t gen64_offset = 0;    // element offset of the general-N binary64 constants
     size_t gen32_byte_offset = 0;  // byte offset of the general-N binary32 constants
+    int32_t rank = 0;           // rank of the mode couplings (general-N factorisation)
+    int32_t rank_pad = 1;       // rank bucket RB the general kernels are specialised on
     bool fast2 = false;         // two-state closed-form kernels apply (N = 2, M <= 8)
 };
 
@@ -170,11 +179,11 @@ size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const
                             double *partials, int64_t tile_begin, void *out, int_<3>);
 size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
                             double *partials, int64_t tile_begin, void *out, int_<4>);
-hipError_t launch_batch_general_n(int mp, int prec, int scheme, const void *items, int32_t n_items,
+hipError_t launch_batch_general_n(int mp, int rb, int prec, int scheme, const void *items, int32_t n_items,
                                   int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<2>);
-hipError_t launch_batch_general_n(int mp, int prec, int scheme, const void *items, int32_t n_items,
+hipError_t launch_batch_general_n(int mp, int rb, int prec, int scheme, const void *items, int32_t n_items,
                                   int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<3>);
-hipError_t launch_batch_general_n(int mp, int prec, int scheme, const void *items, int32_t n_items,
+hipError_t launch_batch_general_n(int mp, int rb, int prec, int scheme, const void *items, int32_t n_items,
                                   int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<4>);
 size_t batch_item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
                      int64_t tile_begin, void *out);
@@ -202,11 +211,11 @@ inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, const
 {
     if (m.fast2)
         return launch_batch_n2(m.m, prec, scheme, items, n_items, total_tiles, counter, s);
-    const int mp = padded_modes(m.m);
+    const int mp = padded_modes(m.m), rb = m.rank_pad;
     switch (m.n) {
-    case 2: return launch_batch_general_n(mp, prec, scheme, items, n_items, total_tiles, counter, s, int_<2>{});
-    case 3: return launch_batch_general_n(mp, prec, scheme, items, n_items, total_tiles, counter, s, int_<3>{});
-    case 4: return launch_batch_general_n(mp, prec, scheme, items, n_items, total_tiles, counter, s, int_<4>{});
+    case 2: return launch_batch_general_n(mp, rb, prec, scheme, items, n_items, total_tiles, counter, s, int_<2>{});
+    case 3: return launch_batch_general_n(mp, rb, prec, scheme, items, n_items, total_tiles, counter, s, int_<3>{});
+    case 4: return launch_batch_general_n(mp, rb, prec, scheme, items, n_items, total_tiles, counter, s, int_<4>{});
     default: return hipErrorNotSupported;
     }
 }
