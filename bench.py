@@ -15,8 +15,9 @@ two.  Two further legs are reported in the same line:
   batched  256 seeded N-state (2-4) harmonic instances (1-64 modes, 1e4-1e6
            walkers, 500-4000 steps, binary32) advanced by one
            qcl_propagate_batch call: walker-steps/s of that call;
-  served   a Poisson stream of jobs (20 jobs/s) through the
-           continuous-batching server: walker-steps/s and p50/p99 latency.
+  served   a Poisson stream of 200 jobs (20 jobs/s) through the
+           continuous-batching server: walker-steps/s and p50/p99 latency;
+  scaling  the headline model at 1e4..1e8 walkers in both precisions.
 
 Prints one JSON line.
 
@@ -111,7 +112,11 @@ def batched_leg(P, torch, n_instances=256):
     """One qcl_propagate_batch call over the seeded heterogeneous instances
     (ensembles sampled beforehand, resident in HBM)."""
     import workloads as W
+    from paper_2608_14544_amd.tune import autotune
     wls = W.batched_instances(n_instances)
+    t0 = time.perf_counter()
+    table = autotune(wls, "fp32")  # untimed: one short run per kernel class and build
+    tune_s = time.perf_counter() - t0
     jobs, tot = [], 0
     stream = torch.cuda.current_stream()
     for wl in wls:
@@ -120,7 +125,8 @@ def batched_leg(P, torch, n_instances=256):
         ens = P.Ensemble(model, r.n_traj, "fp32", zero=False)
         part = P.Partials(model, r.n_traj, r.n_out)
         P.qcl_sample_initial(model, wl.init, r.seed, ens, part, stream)
-        jobs.append(P.BatchJob(model, ens, part, r.dt, r.n_steps, r.cadence, r.seed))
+        jobs.append(P.BatchJob(model, ens, part, r.dt, r.n_steps, r.cadence, r.seed,
+                               occupancy=table.occupancy(model, "fp32")))
         tot += r.n_traj * r.n_steps
     ws = P.Workspace()
     torch.cuda.synchronize()
@@ -132,30 +138,53 @@ def batched_leg(P, torch, n_instances=256):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    classes = {}
-    for wl in wls:
-        N, M = wl.model.n_states, wl.model.n_modes
-        classes[(N, M)] = classes.get((N, M), 0) + 1
     return {"workload": f"{n_instances} seeded N-state harmonic instances (N 2-4, M 1-64, 1e4-1e6 walkers, "
                         "500-4000 steps), fp32, one qcl_propagate_batch call",
             "value": tot / (ms / 1e3), "unit": "trajectory-steps/s", "walker_steps": tot,
-            "ms": ms, "wall_ms": wall * 1e3}
+            "ms": ms, "wall_ms": wall * 1e3,
+            "autotune": {"classes": len(table.choice), "capped_register_budget": sum(
+                1 for v in table.choice.values() if v == 3), "seconds": tune_s}}, table
 
 
-def served_leg(P, torch, n_jobs=40, rate=20.0, quantum=50):
+def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=50, full=False, table=None):
+    """The served stream through the continuous-batching server.  Default:
+    the sub-saturation variant (walkers log-uniform over 1e5-1e7); ``full``
+    uses 1e5-1e8, whose offered load exceeds one device."""
     import workloads as W
     from paper_2608_14544_amd.serve import DeviceBackend, JobSpec, Server, latency_stats
-    arrivals, wls = W.served_stream(n_jobs, rate=rate)
+    traj_range = (1e5, 1e8) if full else (1e5, 1e7)
+    arrivals, wls = W.served_stream(n_jobs, rate=rate, traj_range=traj_range)
     specs = [JobSpec(wl, prec="fp32", name=f"job{i}") for i, wl in enumerate(wls)]
-    srv = Server(DeviceBackend(), quantum_steps=quantum)
+    from paper_2608_14544_amd.tune import autotune
+    table = autotune(wls, "fp32", table)  # untimed; classes already tuned are kept
+    srv = Server(DeviceBackend(tuning=table), quantum_steps=quantum)
     res = srv.run(arrivals, specs)
     st = latency_stats(res)
-    st.update({"workload": f"{n_jobs} jobs, Poisson arrivals at {rate} jobs/s: 1-mode and 3-mode spin-boson, "
-                           "pyrazine-like CI, N-state (2-4) harmonic models with up to 100 modes and 1e5-1e8 "
-                           "walkers; fp32",
+    offered = sum(sp.walker_steps for sp in specs) / max(arrivals[-1], 1e-9)
+    st.update({"workload": f"{n_jobs} jobs, Poisson arrivals at {rate} jobs/s, equal odds of: 1-mode spin-boson, "
+                           "3-mode spin-boson kT 0.2, the same at kT 1.0, pyrazine-like CI (1e7 walkers), N-state "
+                           f"(2-4) harmonic model with M log-U[1,100], walkers log-U[{traj_range[0]:.0e},"
+                           f"{traj_range[1]:.0e}], 500-2000 steps; fp32",
+               "variant": "full" if full else "sub-saturation",
+               "offered_walker_steps_per_s": offered,
                "rounds": srv.rounds, "quantum_steps": quantum,
                "memory_budget_GB": srv.budget / 1e9})
     return st
+
+
+def scaling_leg(P, torch, wl, sizes=(10_000, 100_000, 1_000_000, 10_000_000, 100_000_000)):
+    """Time of one sample+propagate+reduce pass of the headline model
+    against the walker count, both precisions (time should be linear)."""
+    out = []
+    r = wl.run
+    model = P.Model(wl.model)
+    for prec in ("fp32", "fp64"):
+        for T in sizes:
+            ms_step, ms_prop, _ = time_path(P, torch, model, wl, prec, T, 1, 1 if T <= 1_000_000 else 0)
+            out.append({"prec": prec, "n_traj": T, "ms": ms_step, "propagate_ms": ms_prop,
+                        "walker_steps_per_s": T * r.n_steps / (ms_step / 1e3)})
+            torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -168,9 +197,11 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--legs", default="headline,batched,served",
-                    help="comma-separated subset of headline,batched,served")
-    ap.add_argument("--served-jobs", type=int, default=40)
+    ap.add_argument("--legs", default="headline,batched,served,scaling",
+                    help="comma-separated subset of headline,batched,served,scaling")
+    ap.add_argument("--served-jobs", type=int, default=200)
+    ap.add_argument("--served-full", action="store_true",
+                    help="served stream with 1e5-1e8 walkers per random job (offered load above capacity)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -263,15 +294,20 @@ def main():
               f"resolved bins", file=sys.stderr, flush=True)
 
     legs = set(args.legs.split(","))
+    table = None
     if "batched" in legs:
-        line["batched"] = batched_leg(P, torch)
+        line["batched"], table = batched_leg(P, torch)
         print(f"[bench] batched: {line['batched']['value']:.3e} trajectory-steps/s "
               f"({line['batched']['ms']:.0f} ms)", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     if "served" in legs:
-        line["served"] = served_leg(P, torch, args.served_jobs)
+        line["served"] = served_leg(P, torch, args.served_jobs, full=args.served_full, table=table)
         print(f"[bench] served: {line['served']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
+    if "scaling" in legs:
+        line["scaling_sweep"] = scaling_leg(P, torch, wl)
+        print(f"[bench] scaling sweep: " + ", ".join(f"{x['prec']} {x['n_traj']:.0e}: {x['ms']:.1f} ms"
+                                                    for x in line["scaling_sweep"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)

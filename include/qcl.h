@@ -147,7 +147,14 @@ typedef struct {
                              reached by this call must be < n_out */
     int32_t scheme;       /* qcl_transition */
     uint64_t seed;        /* Philox key */
-    int32_t block;        /* reserved, 0 */
+    int32_t occupancy;    /* register budget of the general kernels: 0 = the
+                             compiler's choice; 3 = at most a third of the
+                             register file per wave (3 waves per SIMD), for
+                             binary32 ensembles of models with N > 2 or M > 8
+                             and at most 32 modes (other models ignore it).
+                             The result is bitwise the same either way; the
+                             faster choice depends on the model (see the
+                             tuner in the Python package). */
     int32_t reserved;
 } qcl_prop_desc;
 
@@ -162,6 +169,10 @@ qcl_status qcl_destroy_model(qcl_model model);
 
 int32_t qcl_model_states(qcl_model model);
 int32_t qcl_model_modes(qcl_model model);
+/* Rank of the mode couplings: the number of orthonormal directions B_r with
+ * K_j = sum_r C_jr B_r that qcl_create_model found (0 when every K_j is 0;
+ * 0 for a NULL model). */
+int32_t qcl_model_rank(qcl_model model);
 
 /* Layout of one ensemble in a single caller allocation: *ld is the
  * leading dimension and *bytes the size of a buffer that

@@ -167,8 +167,8 @@ qcl_status check_propagate(qcl_model m, const qcl_ensemble *ens, const qcl_prop_
         return fail(QCL_ERR_INVALID_ARG, "n_steps >= 0, cadence >= 1 and n_out >= 1 required");
     if (pd->scheme != QCL_TRANS_NORMALIZED && pd->scheme != QCL_TRANS_LINEAR)
         return fail(QCL_ERR_INVALID_ARG, "unknown transition scheme %d", pd->scheme);
-    if (pd->block != 0)
-        return fail(QCL_ERR_INVALID_ARG, "block must be 0");
+    if (pd->occupancy != 0 && pd->occupancy != 3)
+        return fail(QCL_ERR_INVALID_ARG, "occupancy must be 0 or 3");
     const int64_t last_bin = (ens->step + pd->n_steps) / pd->cadence;
     if (last_bin >= pd->n_out)
         return fail(QCL_ERR_INVALID_ARG, "bin %lld would be written but n_out is %d", (long long)last_bin,
@@ -185,7 +185,7 @@ qcl_status check_propagate(qcl_model m, const qcl_ensemble *ens, const qcl_prop_
 // precision and transition rule.
 struct BatchClass {
     bool fast2;
-    int n, modes, prec, scheme;
+    int n, modes, prec, scheme, occ;
     std::vector<int32_t> order;  // item indices, most expensive tile first
     size_t item_bytes = 0;
     size_t counter_offset = 0;   // one 8-byte tile counter
@@ -216,12 +216,13 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
         // general kernels are specialised on padded modes and rank bucket
         const int modes = m.fast2 ? m.m : qcl::padded_modes(m.m) * 64 + m.rank_pad;
         BatchClass *c = nullptr;
+        const int occ = qcl::occupancy_variant(m, it.ens->prec, it.prop.occupancy);
         for (BatchClass &k : plan.classes)
             if (k.fast2 == m.fast2 && k.n == m.n && k.modes == modes && k.prec == it.ens->prec &&
-                k.scheme == it.prop.scheme)
+                k.scheme == it.prop.scheme && k.occ == occ)
                 c = &k;
         if (!c) {
-            plan.classes.push_back(BatchClass{m.fast2, m.n, modes, it.ens->prec, it.prop.scheme});
+            plan.classes.push_back(BatchClass{m.fast2, m.n, modes, it.ens->prec, it.prop.scheme, occ});
             c = &plan.classes.back();
             c->item_bytes = qcl::batch_item(m, *it.ens, it.prop, nullptr, 0, nullptr);
             if (c->item_bytes == 0)
@@ -419,6 +420,7 @@ qcl_status qcl_destroy_model(qcl_model m)
 
 int32_t qcl_model_states(qcl_model m) { return m ? m->n : 0; }
 int32_t qcl_model_modes(qcl_model m) { return m ? m->m : 0; }
+int32_t qcl_model_rank(qcl_model m) { return m ? m->rank : 0; }
 
 qcl_status qcl_ensemble_bytes(qcl_model m, int64_t n_traj, int32_t prec, int64_t *ld, size_t *bytes)
 {
@@ -597,7 +599,7 @@ qcl_status qcl_propagate_batch(const qcl_batch_item *items, int32_t n_items, voi
             return device_fail(e, "batch descriptor upload");
     }
     for (const BatchClass &c : plan.classes) {
-        hipError_t e = qcl::launch_batch(*items[c.order[0]].model, c.prec, c.scheme, ws + c.offset,
+        hipError_t e = qcl::launch_batch(*items[c.order[0]].model, c.prec, c.scheme, c.occ, ws + c.offset,
                                          (int32_t)c.order.size(), c.total_tiles,
                                          (unsigned long long *)(ws + c.counter_offset), s);
         if (e == hipErrorNotSupported)

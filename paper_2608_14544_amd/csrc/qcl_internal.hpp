@@ -179,11 +179,11 @@ size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const
                             double *partials, int64_t tile_begin, void *out, int_<3>);
 size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
                             double *partials, int64_t tile_begin, void *out, int_<4>);
-hipError_t launch_batch_general_n(int mp, int rb, int prec, int scheme, const void *items, int32_t n_items,
+hipError_t launch_batch_general_n(int mp, int rb, int prec, int occ, const void *items, int32_t n_items,
                                   int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<2>);
-hipError_t launch_batch_general_n(int mp, int rb, int prec, int scheme, const void *items, int32_t n_items,
+hipError_t launch_batch_general_n(int mp, int rb, int prec, int occ, const void *items, int32_t n_items,
                                   int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<3>);
-hipError_t launch_batch_general_n(int mp, int rb, int prec, int scheme, const void *items, int32_t n_items,
+hipError_t launch_batch_general_n(int mp, int rb, int prec, int occ, const void *items, int32_t n_items,
                                   int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<4>);
 size_t batch_item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
                      int64_t tile_begin, void *out);
@@ -206,16 +206,24 @@ inline size_t batch_item(const qcl_model_s &m, const qcl_ensemble &ens, const qc
     }
 }
 
-inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, const void *items, int32_t n_items,
-                               int64_t total_tiles, unsigned long long *counter, hipStream_t s)
+// The register-budget variant a call runs: 3 where such kernels exist
+// (binary32, general kernels, at most 32 padded modes) and it was asked
+// for, else 0.
+inline int occupancy_variant(const qcl_model_s &m, int prec, int requested)
 {
-    if (m.fast2)
+    return (requested == 3 && !m.fast2 && prec == QCL_FP32_ACC64 && padded_modes(m.m) <= 32) ? 3 : 0;
+}
+
+inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, int occ, const void *items,
+                               int32_t n_items, int64_t total_tiles, unsigned long long *counter, hipStream_t s)
+{
+    if (m.fast2)  // the transition rule is a template parameter of the two-state kernels
         return launch_batch_n2(m.m, prec, scheme, items, n_items, total_tiles, counter, s);
     const int mp = padded_modes(m.m), rb = m.rank_pad;
     switch (m.n) {
-    case 2: return launch_batch_general_n(mp, rb, prec, scheme, items, n_items, total_tiles, counter, s, int_<2>{});
-    case 3: return launch_batch_general_n(mp, rb, prec, scheme, items, n_items, total_tiles, counter, s, int_<3>{});
-    case 4: return launch_batch_general_n(mp, rb, prec, scheme, items, n_items, total_tiles, counter, s, int_<4>{});
+    case 2: return launch_batch_general_n(mp, rb, prec, occ, items, n_items, total_tiles, counter, s, int_<2>{});
+    case 3: return launch_batch_general_n(mp, rb, prec, occ, items, n_items, total_tiles, counter, s, int_<3>{});
+    case 4: return launch_batch_general_n(mp, rb, prec, occ, items, n_items, total_tiles, counter, s, int_<4>{});
     default: return hipErrorNotSupported;
     }
 }

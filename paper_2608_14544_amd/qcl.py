@@ -68,7 +68,7 @@ class qcl_ensemble(C.Structure):
 class qcl_prop_desc(C.Structure):
     _fields_ = [("dt", C.c_double), ("n_steps", C.c_int32), ("cadence", C.c_int32),
                 ("n_out", C.c_int32), ("scheme", C.c_int32), ("seed", C.c_uint64),
-                ("block", C.c_int32), ("reserved", C.c_int32)]
+                ("occupancy", C.c_int32), ("reserved", C.c_int32)]
 
 
 class qcl_batch_item(C.Structure):
@@ -76,7 +76,7 @@ class qcl_batch_item(C.Structure):
                 ("partials", C.c_void_p)]
 
 
-EXPORTS = ("qcl_create_model", "qcl_destroy_model", "qcl_model_states", "qcl_model_modes",
+EXPORTS = ("qcl_create_model", "qcl_destroy_model", "qcl_model_states", "qcl_model_modes", "qcl_model_rank",
            "qcl_ensemble_bytes", "qcl_ensemble_bind", "qcl_partials_bytes",
            "qcl_sample_initial", "qcl_propagate", "qcl_batch_workspace_bytes", "qcl_propagate_batch",
            "qcl_reduce_observables", "qcl_last_error")
@@ -101,6 +101,8 @@ def load_library(path: str = LIB_PATH):
         L.qcl_model_states.restype = i32
         L.qcl_model_modes.argtypes = [vp]
         L.qcl_model_modes.restype = i32
+        L.qcl_model_rank.argtypes = [vp]
+        L.qcl_model_rank.restype = i32
         L.qcl_ensemble_bytes.argtypes = [vp, i64, i32, C.POINTER(i64), C.POINTER(sz)]
         L.qcl_ensemble_bind.argtypes = [vp, vp, i64, i32, i64, C.POINTER(qcl_ensemble)]
         L.qcl_partials_bytes.argtypes = [vp, i64, i32, C.POINTER(sz)]
@@ -157,6 +159,7 @@ class Model:
         self.handle = h
         self.n_states = int(L.qcl_model_states(h))
         self.n_modes = int(L.qcl_model_modes(h))
+        self.rank = int(L.qcl_model_rank(h))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -286,8 +289,9 @@ def qcl_sample_initial(model: Model, init, seed: int, ens: Ensemble, partials: P
 
 
 def qcl_propagate(model: Model, ens: Ensemble, dt: float, n_steps: int, cadence: int, seed: int,
-                  partials: Partials, scheme: int = QCL_TRANS_NORMALIZED, stream=None):
-    pd = qcl_prop_desc(float(dt), int(n_steps), int(cadence), partials.n_out, int(scheme), int(seed), 0, 0)
+                  partials: Partials, scheme: int = QCL_TRANS_NORMALIZED, stream=None, occupancy: int = 0):
+    pd = qcl_prop_desc(float(dt), int(n_steps), int(cadence), partials.n_out, int(scheme), int(seed),
+                       int(occupancy), 0)
     _check(load_library().qcl_propagate(model.handle, C.byref(ens.c), C.byref(pd), partials.ptr,
                                         C.c_void_p(_stream_handle(stream))))
 
@@ -296,14 +300,14 @@ class BatchJob:
     """Arguments of one qcl_propagate call, as an item of a batch."""
 
     def __init__(self, model: Model, ens: Ensemble, partials: Partials, dt: float, n_steps: int,
-                 cadence: int, seed: int, scheme: int = QCL_TRANS_NORMALIZED):
+                 cadence: int, seed: int, scheme: int = QCL_TRANS_NORMALIZED, occupancy: int = 0):
         self.model, self.ens, self.partials = model, ens, partials
         self.dt, self.n_steps, self.cadence = float(dt), int(n_steps), int(cadence)
-        self.seed, self.scheme = int(seed), int(scheme)
+        self.seed, self.scheme, self.occupancy = int(seed), int(scheme), int(occupancy)
 
     def item(self) -> qcl_batch_item:
         pd = qcl_prop_desc(self.dt, self.n_steps, self.cadence, self.partials.n_out, self.scheme,
-                           self.seed, 0, 0)
+                           self.seed, self.occupancy, 0)
         return qcl_batch_item(self.model.handle, C.pointer(self.ens.c), pd, self.partials.ptr)
 
 

@@ -84,11 +84,12 @@ class _Job:
 class DeviceBackend:
     """Device work through the C ABI (one stream, default priority)."""
 
-    def __init__(self, stream=None):
+    def __init__(self, stream=None, tuning=None):
         import torch
         from . import qcl as Q
         self.Q = Q
         self.torch = torch
+        self.tuning = tuning  # tune.TuningTable: register-budget choice per kernel class
         Q.load_library()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         # descriptors are uploaded by a kernel on the same stream, so one
@@ -126,8 +127,9 @@ class DeviceBackend:
     def advance(self, work):
         """work: list of (handle, spec, n_steps); one batched launch."""
         Q = self.Q
+        occ = (lambda m, p: self.tuning.occupancy(m, p)) if self.tuning is not None else (lambda m, p: 0)
         jobs = [Q.BatchJob(h[0], h[1], h[2], s.workload.run.dt, n, s.workload.run.cadence,
-                           s.workload.run.seed, s.scheme) for h, s, n in work]
+                           s.workload.run.seed, s.scheme, occupancy=occ(h[0], s.prec)) for h, s, n in work]
         with self.torch.cuda.stream(self.stream):
             Q.qcl_propagate_batch(jobs, self.ws, stream=self.stream)
 

@@ -225,30 +225,33 @@ def batched_instances(n_instances: int = 256, key: int = 4, **kw) -> List[Worklo
     return [random_lvc(i, key=key, **kw) for i in range(n_instances)]
 
 
-def served_stream(n_jobs: int = 40, rate: float = 20.0, seed: int = 5, traj_scale: float = 1.0,
-                  step_scale: float = 1.0, max_modes: int = 100, traj_range=(1e5, 1e8),
-                  steps_range=(100, 1000)):
-    """A job stream for the server: Poisson arrivals at ``rate`` jobs/s;
-    each job is, with equal odds, the one-mode spin-boson run, the 3-mode
-    Ohmic spin-boson run (kT 0.2 or 1.0), the pyrazine-like
-    conical-intersection run, or an N-state (2-4) harmonic model with up to
-    ``max_modes`` modes and log-uniform walker count over ``traj_range``.
-    Walker and step counts are multiplied by ``traj_scale`` and
-    ``step_scale`` (small streams for tests).  Returns (arrival times,
-    workloads)."""
-    rng = np.random.Generator(np.random.Philox(key=[seed, 0x5E27]))
+def served_stream(n_jobs: int = 200, rate: float = 20.0, seed: int = 5, traj_range=(1e5, 1e8),
+                  max_modes: int = 100, steps_range=(500, 2000), traj_scale: float = 1.0,
+                  step_scale: float = 1.0):
+    """A job stream for the server: Poisson arrivals at ``rate`` jobs/s; each
+    job is, with equal odds, the one-mode spin-boson run, the 3-mode Ohmic
+    spin-boson run at kT 0.2, the same at kT 1.0, the pyrazine-like
+    conical-intersection run, or an N-state (2-4) harmonic model with M
+    log-uniform over [1, ``max_modes``], walkers log-uniform over
+    ``traj_range`` and steps uniform over ``steps_range``.  Walker and step
+    counts are multiplied by ``traj_scale`` and ``step_scale`` (small
+    streams for tests).  Returns (arrival times, workloads)."""
+    rng = np.random.Generator(np.random.Philox(key=[seed, 0]))
     t, arrivals, jobs = 0.0, [], []
     for i in range(n_jobs):
         t += float(rng.exponential(1.0 / rate))
-        kind = int(rng.integers(0, 4))
+        kind = int(rng.integers(0, 5))
         if kind == 0:
             wl = spin_boson_1mode()
         elif kind == 1:
-            wl = spin_boson_ohmic(kT=0.2 if rng.random() < 0.5 else 1.0)
+            wl = spin_boson_ohmic(kT=0.2)
         elif kind == 2:
+            wl = spin_boson_ohmic(kT=1.0)
+        elif kind == 3:
             wl = pyrazine_ci()
         else:
-            wl = random_lvc(i, key=seed + 1000, max_modes=max_modes, traj_range=traj_range,
+            m = int(round(math.exp(rng.uniform(0.0, math.log(max_modes)))))
+            wl = random_lvc(i, key=seed + 1000, n_modes=max(1, min(max_modes, m)), traj_range=traj_range,
                             steps_range=steps_range, cadence=50)
         r = wl.run
         r.n_traj = max(1, int(round(r.n_traj * traj_scale)))
