@@ -38,6 +38,36 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X published dense vector peaks
 
+# HBM bytes of one propagate launch, from the committed rocprofv3 counter
+# summary; valid only while the kernel's sources are the ones it measured.
+HBM_PROFILE = os.path.join(ROOT, "profiles", "propagate_n2_pyrazine_1e7_hbm_counters.md")
+KERNEL_SOURCES = ["kernels_n2.hip", "block_reduce.hpp", "phase_math.hpp", "philox.hpp", "qcl_internal.hpp"]
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2608_14544_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n_traj: int, prec: str):
+    """Counter-derived bytes per launch if they apply to this build and
+    workload, else None."""
+    if not os.path.exists(HBM_PROFILE):
+        return None
+    vals = {}
+    for line in open(HBM_PROFILE):
+        k, _, v = line.strip().partition(":")
+        if k in ("traffic_bytes_per_launch", "n_traj", "precision", "kernel_sources_sha256"):
+            vals[k] = v.strip()
+    if (vals.get("kernel_sources_sha256") != kernel_sources_sha256() or vals.get("n_traj") != str(n_traj)
+            or vals.get("precision") != prec or "traffic_bytes_per_launch" not in vals):
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
 
 def flops_per_traj_step(n_modes: int) -> int:
     """Algorithmic floating-point work of one two-state walker step (FMA = 2):
@@ -259,7 +289,8 @@ def main():
                    "n_traj": n_traj, "n_steps": r.n_steps, "cadence": r.cadence, "precision": args.prec},
         "propagate_ms": ms_prop,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(n_traj, args.prec),
+                     "traffic_unit": "bytes per launch (HBM, FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
                      "kernel": "propagate_n2_kernel", "flops_per_traj_step": fl},
     }
     print(f"[bench] {args.prec}: {ms_step:.2f} ms/step, propagate {ms_prop:.2f} ms", file=sys.stderr, flush=True)

@@ -1,0 +1,28 @@
+"""Host-side parts of bench.py: the multi-GPU refusal and the guarded
+lookup of counter-derived HBM traffic."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_traffic_only_for_the_profiled_build(tmp_path, monkeypatch):
+    import bench
+    good = bench.kernel_sources_sha256()
+    prof = tmp_path / "p.md"
+    prof.write_text("x\n    traffic_bytes_per_launch: 123\n    n_traj: 1000\n    precision: fp32\n"
+                    f"    kernel_sources_sha256: {good}\n")
+    monkeypatch.setattr(bench, "HBM_PROFILE", str(prof))
+    assert bench.measured_traffic(1000, "fp32") == 123
+    assert bench.measured_traffic(2000, "fp32") is None
+    assert bench.measured_traffic(1000, "fp64") is None
+    prof.write_text(prof.read_text().replace(good, "0" * 64))
+    assert bench.measured_traffic(1000, "fp32") is None
