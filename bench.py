@@ -17,7 +17,9 @@ two.  Two further legs are reported in the same line:
            qcl_propagate_batch call: walker-steps/s of that call;
   served   a Poisson stream of 200 jobs (20 jobs/s) through the
            continuous-batching server: walker-steps/s and p50/p99 latency;
-  scaling  the headline model at 1e4..1e8 walkers in both precisions.
+  scaling  the headline model at 1e4..1e8 walkers in both precisions;
+  spin_boson  the 3-mode Ohmic spin-boson runs (1e6 walkers, 2000 steps,
+           kT 0.2 and 1.0) in both precisions with their population difference.
 
 Prints one JSON line.
 
@@ -110,32 +112,89 @@ def time_path(P, torch, model, wl, prec, n_traj, steps, warmup):
     return ms_step, ms_prop, res
 
 
-def cpu_baseline(wl, target_s: float):
-    """The FP64 oracle on the host cores, on a bounded slice of the same
-    workload (same model, same 1000 steps, fewer walkers)."""
+def _oracle_rate(wl, n):
+    """Walker-steps/s of the FP64 oracle on n walkers of ``wl`` (sample +
+    propagate + reduce), and the seconds it took."""
     import numpy as np
     import oracle.core as oc
     r = wl.run
     m = oc.Model(wl.model)
+    t = time.perf_counter()
+    st, s0 = oc.sample(m, wl.init, r.seed, n)
+    sums = np.zeros((r.n_out, 2, m.n, m.n, 4))
+    sums[0] = s0
+    oc.propagate(m, st, r.dt, r.n_steps, r.cadence, r.seed, r.n_out, sums)
+    oc.finalize(sums, n)
+    dt = time.perf_counter() - t
+    return n * r.n_steps / dt, dt
 
-    def run(n):
-        t = time.perf_counter()
-        st, s0 = oc.sample(m, wl.init, r.seed, n)
-        sums = np.zeros((r.n_out, 2, 2, 2, 4))
-        sums[0] = s0
-        oc.propagate(m, st, r.dt, r.n_steps, r.cadence, r.seed, r.n_out, sums)
-        oc.finalize(sums, n)
-        return time.perf_counter() - t
 
-    cal_n = 4096
-    dt_cal = run(cal_n)
-    n = int(max(cal_n, min(5_000_000, cal_n * target_s / max(dt_cal, 1e-6))))
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, target_s: float):
+    """The FP64 oracle on the host cores, on a bounded slice of the same
+    workload (same model, same 1000 steps, fewer walkers): all threads, and
+    one thread in a child process (OMP_NUM_THREADS=1)."""
+    import subprocess
+    import oracle.core as oc
+    cal_n = 16384
+    _, dt_cal = _oracle_rate(wl, cal_n)
+    n = int(max(cal_n, min(20_000_000, cal_n * target_s / max(dt_cal, 1e-6))))
     n = (n // 1024) * 1024
-    dt = run(n)
-    return {"value": n * r.n_steps / dt, "unit": "trajectory-steps/s", "cores": oc.num_threads(),
-            "kind": "oracle",
-            "sample": f"{n} walkers x {r.n_steps} steps of the same model (sample+propagate+reduce), "
-                      f"{dt:.1f} s, FP64 C oracle, OpenMP over walkers"}
+    rate, dt = _oracle_rate(wl, n)
+    # about 5 s on one thread
+    n1 = max(1024, (int(5.0 * rate / max(oc.num_threads(), 1) / wl.run.n_steps) // 1024) * 1024)
+    code = ("import sys; sys.path.insert(0, %r); import bench, workloads as W; "
+            "r, dt = bench._oracle_rate(W.pyrazine_ci(), %d); print(r, dt)" % (ROOT, n1))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    single = None
+    try:
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+        if out.returncode == 0:
+            r1, dt1 = (float(x) for x in out.stdout.split()[-2:])
+            single = {"value": r1, "walkers": n1, "seconds": dt1}
+    except (subprocess.TimeoutExpired, ValueError):
+        single = None
+    return {"value": rate, "unit": "trajectory-steps/s", "cores": oc.num_threads(), "kind": "oracle",
+            "sample": f"{n} walkers x {wl.run.n_steps} steps of the same model (sample+propagate+reduce), "
+                      f"{dt:.1f} s, FP64 C oracle, OpenMP over walkers",
+            "cpu_model": _cpu_model(), "single_thread": single}
+
+
+def spin_boson_leg(P, torch):
+    """The 3-mode Ohmic spin-boson runs (1e6 walkers, 2000 steps) at kT 0.2
+    and 1.0, FP32_ACC64 beside FP64, with the largest population difference
+    between the two over the bins the FP64 run resolves (SE < 0.01)."""
+    import numpy as np
+    import workloads as W
+    out = []
+    for kT in (0.2, 1.0):
+        wl = W.spin_boson_ohmic(kT=kT)
+        r = wl.run
+        model = P.Model(wl.model)
+        res = {}
+        for prec in ("fp32", "fp64"):
+            ms_step, ms_prop, o = time_path(P, torch, model, wl, prec, r.n_traj, 3, 1)
+            res[prec] = (ms_step, ms_prop, o)
+        r64, r32 = res["fp64"][2], res["fp32"][2]
+        se = np.max(np.stack([r64[:, 0, i, i, 2] for i in range(2)]), axis=0)
+        bad = np.nonzero(~(se < 0.01))[0]
+        n_res = int(bad[0]) if len(bad) else len(se)
+        dpop = max(float(np.max(np.abs(r32[:n_res, 0, i, i, 0] - r64[:n_res, 0, i, i, 0]))) for i in range(2))
+        out.append({"kT": kT, "n_traj": r.n_traj, "n_steps": r.n_steps,
+                    "fp32": {"value": r.n_traj * r.n_steps / (res["fp32"][0] / 1e3), "ms": res["fp32"][0]},
+                    "fp64": {"value": r.n_traj * r.n_steps / (res["fp64"][0] / 1e3), "ms": res["fp64"][0]},
+                    "fp32_vs_fp64_max_abs_population_diff": dpop, "resolved_bins": n_res, "bins": len(se)})
+        torch.cuda.empty_cache()
+    return out
 
 
 def batched_leg(P, torch, n_instances=256):
@@ -226,9 +285,9 @@ def main():
     ap.add_argument("--n-traj", type=int, default=None)
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--legs", default="headline,batched,served,scaling",
-                    help="comma-separated subset of headline,batched,served,scaling")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling",
+                    help="comma-separated subset of headline,spin_boson,batched,served,scaling")
     ap.add_argument("--served-jobs", type=int, default=200)
     ap.add_argument("--served-full", action="store_true",
                     help="served stream with 1e5-1e8 walkers per random job (offered load above capacity)")
@@ -325,6 +384,12 @@ def main():
               f"resolved bins", file=sys.stderr, flush=True)
 
     legs = set(args.legs.split(","))
+    if "spin_boson" in legs:
+        line["spin_boson"] = spin_boson_leg(P, torch)
+        print(f"[bench] spin-boson: " + ", ".join(
+            f"kT {x['kT']}: fp32 {x['fp32']['value']:.3e}, fp64 {x['fp64']['value']:.3e}, "
+            f"|dP| {x['fp32_vs_fp64_max_abs_population_diff']:.1e} over {x['resolved_bins']}/{x['bins']} bins"
+            for x in line["spin_boson"]), file=sys.stderr, flush=True)
     table = None
     if "batched" in legs:
         line["batched"], table = batched_leg(P, torch)
