@@ -325,10 +325,7 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const 
     while (step < end) {
         const int64_t next_bin = (step / P.cadence + 1) * P.cadence;
         const int64_t stop = next_bin < end ? next_bin : end;
-        // 32-bit trip count: the loop test stays on the scalar unit
-        const int32_t n_here = (int32_t)(stop - step);
-#pragma unroll 2
-        for (int32_t t = 0; t < n_here; ++t, ++step) {
+        for (; step < stop; ++step) {
             if ((step & 3) == 0)
                 rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
             const uint32_t word = pick_word(rnd, (uint32_t)(step & 3));
