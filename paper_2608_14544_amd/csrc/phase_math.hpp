@@ -24,7 +24,9 @@
 namespace qcl {
 
 // 1/3!, 1/5!, ..., 1/17! with alternating signs, then 1/2!, 1/4!, ..., 1/18!
-// (defined here; this header is included by a single translation unit)
+// Defined in every translation unit that includes this header: each unit's
+// device code object holds its own copy (device code is not relocatable
+// across units), and the host-side shadows are local symbols.
 __device__ double kTaylorSinCos[18] = {
     -1.0 / 6.0, 1.0 / 120.0, -1.0 / 5040.0, 1.0 / 362880.0, -1.0 / 39916800.0, 1.0 / 6227020800.0,
     -1.0 / 1307674368000.0, 1.0 / 355687428096000.0, 0.0,
