@@ -32,6 +32,9 @@
  *     valid once the stream has reached the point of the call.
  *   - Nothing in qcl_sample_initial, qcl_propagate or
  *     qcl_reduce_observables allocates memory.
+ *   - A model's constants live on the device that was current when it was
+ *     created; qcl_sample_initial, qcl_propagate and qcl_propagate_batch
+ *     must be called with that device current (INVALID_ARG otherwise).
  */
 #ifndef QCL_H
 #define QCL_H

@@ -31,8 +31,10 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
-    """Compiles every source (in parallel) and links libqcl.so."""
+def build(verbose: bool = False, extra=(), jobs: int = 0, only=None) -> str:
+    """Compiles every source (in parallel) and links libqcl.so.  ``only``
+    restricts compilation to the named sources (the other objects must exist
+    from a previous build of the same tree)."""
     from concurrent.futures import ThreadPoolExecutor
     obj_dir = os.path.join(PKG, "_build")
     os.makedirs(obj_dir, exist_ok=True)
@@ -47,9 +49,14 @@ def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
         subprocess.run(cmd, check=True)
         return obj
 
-    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 2)))
+    todo = [src for src in SOURCES if only is None or src in only]
+    jobs = jobs or min(len(todo) or 1, max(1, (os.cpu_count() or 2)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+        list(ex.map(compile_one, todo))
+    objs = [os.path.join(obj_dir, src + ".o") for src in SOURCES]
+    missing = [o for o in objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"objects missing (build everything once first): {missing}")
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
@@ -60,5 +67,6 @@ def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    args = [a for a in sys.argv[1:] if a != "-v"]
+    build(verbose="-v" in sys.argv, only=args or None)
     print(LIB)

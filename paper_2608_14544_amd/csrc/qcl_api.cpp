@@ -127,6 +127,19 @@ qcl_status check_model(qcl_model m)
     return QCL_OK;
 }
 
+// Kernels read the model's constant block on the device that holds it:
+// the calling thread's current device must be that device.
+qcl_status check_device(const qcl_model_s &m)
+{
+    int dev = -1;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return device_fail(e, "hipGetDevice");
+    if (dev != m.device)
+        return fail(QCL_ERR_INVALID_ARG, "the model lives on device %d but device %d is current", m.device, dev);
+    return QCL_OK;
+}
+
 qcl_status check_ensemble(const qcl_model_s &m, const qcl_ensemble *e)
 {
     if (!e)
@@ -177,6 +190,8 @@ qcl_status check_propagate(qcl_model m, const qcl_ensemble *ens, const qcl_prop_
         return fail(QCL_ERR_INVALID_ARG, "global step counter out of range");
     if (ens->n_traj > 0 && (!partials || ((uintptr_t)partials % 8)))
         return fail(QCL_ERR_INVALID_ARG, "partials is NULL or misaligned");
+    if (ens->n_traj > 0 && pd->n_steps > 0)
+        return check_device(*m);
     return QCL_OK;
 }
 
@@ -527,15 +542,19 @@ qcl_status qcl_sample_initial(qcl_model m, const qcl_init_desc *init, uint64_t s
     sa.basis = init->basis;
     sa.key0 = (uint32_t)seed;
     sa.key1 = (uint32_t)(seed >> 32);
-    ens->step = 0;
-    if (ens->n_traj == 0)
+    if (ens->n_traj == 0) {
+        ens->step = 0;
         return QCL_OK;
+    }
+    if (qcl_status st = check_device(*m))
+        return st;
     hipError_t e = m->fast2 ? qcl::launch_sample_n2(*m, sa, *ens, partials, n_out, (hipStream_t)stream)
                             : qcl::launch_sample_general(*m, sa, *ens, partials, n_out, (hipStream_t)stream);
     if (e == hipErrorNotSupported)
         return fail(QCL_ERR_UNSUPPORTED, "no sampling kernel for this model");
     if (e != hipSuccess)
         return device_fail(e, "sample kernel launch");
+    ens->step = 0;
     return QCL_OK;
 }
 

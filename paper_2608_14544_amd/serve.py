@@ -206,7 +206,11 @@ class Server:
         jid = self.next_id
         self.next_id += 1
         t = self.now() if arrival is None else float(arrival)
-        fp = int(self.backend.footprint(spec))
+        try:
+            fp = int(self.backend.footprint(spec))
+        except Exception as exc:  # an invalid job is answered, not fatal to the server
+            self.results.append(JobResult(jid, spec.name, None, t, t, t, 0, error=f"rejected: {exc}"))
+            return jid
         job = _Job(jid, spec, t, fp)
         if fp > self.budget:
             self.results.append(JobResult(jid, spec.name, None, t, t, t, 0,
@@ -295,7 +299,12 @@ class Server:
                     blocked_head = j
                 continue
             self.queue.remove(j)
-            j.handle = self.backend.start(j.spec)
+            try:
+                j.handle = self.backend.start(j.spec)
+            except Exception as exc:  # e.g. the device ran out of memory: answer the job, keep serving
+                self.results.append(JobResult(j.job_id, j.spec.name, None, j.arrival, now, now, 0,
+                                              error=f"start failed: {exc}"))
+                continue
             j.admitted = now
             self.used += j.footprint
             self.active.append(j)

@@ -132,3 +132,27 @@ def test_tuning_classes_and_table_roundtrip(tmp_path):
     t.save(path)
     u = TuningTable(path)
     assert u.choice == t.choice
+
+
+def test_failing_jobs_are_answered_not_fatal():
+    srv, be, clock = make(budget=10 ** 6)
+
+    class Flaky(SimBackend):
+        def footprint(self, spec):
+            if spec.name == "bad":
+                raise ValueError("invalid model")
+            return super().footprint(spec)
+
+        def start(self, spec):
+            if spec.name == "oom":
+                raise MemoryError("device out of memory")
+            return super().start(spec)
+
+    fb = Flaky(clock, bytes_per_walker=1, walker_steps_per_s=1e6, sleep_until=clock.until)
+    srv.backend = fb
+    for name in ("bad", "oom", "good"):
+        srv.submit(spec(name, 100, 20))
+    drive(srv, clock)
+    res = {r.name: r for r in srv.results}
+    assert "invalid model" in res["bad"].error and "out of memory" in res["oom"].error
+    assert not res["good"].error and srv.used == 0
