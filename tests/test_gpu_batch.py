@@ -141,3 +141,78 @@ def test_register_budget_variants_bitwise(P):
     t = TuningTable()
     choice = t.tune(wl, "fp32", n_traj=1 << 16, n_steps=20)
     assert choice in (0, 3) and t.occupancy(P.Model(wl.model), "fp32") == choice
+
+
+def test_batched_workload_full_size():
+    """The 256-instance batched workload at full size in the benchmark's
+    launch configuration (binary32, tuned register budgets, one batched
+    call): the smallest instances' ensembles against the FP64 oracle run
+    in full (1e-3 or 3 SE); then a binary64 batch of full-size instances
+    covering N = 2, 3, 4 and up to 64 modes, with sampled walkers
+    recomputed one by one by the oracle."""
+    import torch
+    import paper_2608_14544_amd as P
+    import oracle.core as oc
+    from paper_2608_14544_amd.tune import autotune
+    from test_gpu_parity import _oracle_state
+    P.load_library()
+    wls = W.batched_instances(256)
+    table = autotune(wls, "fp32")
+    runs, jobs = [], []
+    for wl in wls:
+        r = wl.run
+        model, ens, part = _setup(P, wl, "fp32", r.n_traj)
+        runs.append((model, ens, part))
+        jobs.append(P.BatchJob(model, ens, part, r.dt, r.n_steps, r.cadence, r.seed,
+                               occupancy=table.occupancy(model, "fp32")))
+    P.qcl_propagate_batch(jobs)
+    torch.cuda.synchronize()
+    order = sorted(range(len(wls)), key=lambda i: wls[i].run.n_traj * wls[i].run.n_steps * wls[i].model.n_states)
+    checked = 0
+    for i in order:
+        wl = wls[i]
+        if wl.model.n_states == 4:  # keep the host oracle's share of the test short
+            continue
+        model, ens, part = runs[i]
+        out_g = P.qcl_reduce_observables(model, part, wl.run.n_traj).cpu().numpy()
+        out_o, _, _, _ = oracle_run(wl)
+        d = np.abs(out_g[..., :2] - out_o[..., :2])
+        se = np.maximum(out_o[..., 2:], 1e-300)
+        print(f"instance {i}: N={wl.model.n_states} M={wl.model.n_modes} T={wl.run.n_traj} "
+              f"steps={wl.run.n_steps} max err {d.max():.3g} max err/SE {(d / se).max():.3g}", flush=True)
+        assert np.all((d <= 1e-3) | (d <= 3 * se)), i
+        checked += 1
+        if checked == 4:
+            break
+    del runs, jobs
+    torch.cuda.empty_cache()
+    # binary64: full-size instances, per-walker parity on sampled walkers
+    picks = [10, 13, 82, 97, 168, 214]
+    sub = [wls[i] for i in picks]
+    runs, jobs = [], []
+    for wl in sub:
+        r = wl.run
+        model, ens, part = _setup(P, wl, "fp64", r.n_traj)
+        runs.append((model, ens, part))
+        jobs.append(P.BatchJob(model, ens, part, r.dt, r.n_steps, r.cadence, r.seed))
+    P.qcl_propagate_batch(jobs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    for wl, (model, ens, part), idx in zip(sub, runs, picks):
+        r = wl.run
+        T, N = r.n_traj, wl.model.n_states
+        ids = np.unique(np.concatenate([[0, 255, 256, T - 1], rng.integers(0, T, 6)]))
+        t = ens.tensors()
+        g = {"q": t["q"][:, ids].cpu().numpy().T, "p": t["p"][:, ids].cpu().numpy().T,
+             "U": t["u"][:, ids].cpu().numpy().T.reshape(-1, N, N), "w": t["w"][ids].cpu().numpy(),
+             "phase": t["phase"][ids].cpu().numpy(), "a": t["a"][ids].cpu().numpy().astype(np.int32),
+             "b": t["b"][ids].cpu().numpy().astype(np.int32)}
+        m = oc.Model(wl.model)
+        o = {k: [] for k in g}
+        for i in ids:
+            st, _ = oc.sample(m, wl.init, r.seed, 1, traj_offset=int(i))
+            oc.propagate(m, st, r.dt, r.n_steps, r.cadence, r.seed, r.n_out)
+            for k, v in _oracle_state(st).items():
+                o[k].append(v[0])
+        o = {k: np.array(v) for k, v in o.items()}
+        compare_walkers(g, o, rtol=1e-8, max_flip_frac=0.2, label=f"batched instance {idx} fp64 sampled")
