@@ -108,6 +108,9 @@ def time_path(P, torch, model, wl, prec, n_traj, steps, warmup):
     ms_step = (t1 - t0) * 1e3 / steps
     ms_prop = sum(a.elapsed_time(b) for a, b in ev) / steps
     res = out.cpu().numpy()
+    fl = ens.tensors()["flags"][:n_traj]
+    time_path.flag_counts = {name: int(((fl & bit) != 0).sum().item())
+                             for name, bit in (("nonfinite", 1), ("degenerate", 2), ("resolved64", 4))}
     del ens, part
     return ms_step, ms_prop, res
 
@@ -243,12 +246,18 @@ def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=50, full=False, table=No
     from paper_2608_14544_amd.serve import DeviceBackend, JobSpec, Server, latency_stats
     traj_range = (1e5, 1e8) if full else (1e5, 1e7)
     arrivals, wls = W.served_stream(n_jobs, rate=rate, traj_range=traj_range)
-    specs = [JobSpec(wl, prec="fp32", name=f"job{i}") for i, wl in enumerate(wls)]
+    specs = [JobSpec(wl, prec="fp32", name=f"{i}:{wl.model.name}") for i, wl in enumerate(wls)]
     from paper_2608_14544_amd.tune import autotune
     table = autotune(wls, "fp32", table)  # untimed; classes already tuned are kept
     srv = Server(DeviceBackend(tuning=table), quantum_steps=quantum)
     res = srv.run(arrivals, specs)
     st = latency_stats(res)
+    kinds = {}
+    for rr in res:
+        kind = rr.name.split(":", 1)[1] if ":" in rr.name else "job"
+        kind = "random_lvc" if kind.startswith("random_lvc") else kind
+        kinds.setdefault(kind, []).append(rr)
+    st["by_kind"] = {k: {kk: latency_stats(v)[kk] for kk in ("n_jobs", "p50_s", "p99_s")} for k, v in kinds.items()}
     offered = sum(sp.walker_steps for sp in specs) / max(arrivals[-1], 1e-9)
     st.update({"workload": f"{n_jobs} jobs, Poisson arrivals at {rate} jobs/s, equal odds of: 1-mode spin-boson, "
                            "3-mode spin-boson kT 0.2, the same at kT 1.0, pyrazine-like CI (1e7 walkers), N-state "
@@ -325,6 +334,7 @@ def main():
           flush=True)
 
     ms_step, ms_prop, res = time_path(P, torch, model, wl, args.prec, n_traj, args.steps, args.warmup)
+    flags = dict(time_path.flag_counts)
     tsteps = n_traj * r.n_steps
     value = tsteps / (ms_step / 1e3)
     fl = flops_per_traj_step(wl.model.n_modes)
@@ -379,6 +389,7 @@ def main():
             "resolved_until_fs": (n_res - 1) * r.cadence * dt_fs if n_res else 0.0,
             "criterion": "population SE < 0.01 (fp64 run)",
             "population_se_at_last_bin": float(se_pop[-1]),
+            f"{args.prec}_walker_flags": flags,
         }
         print(f"[bench] {other}: {ms2:.2f} ms/step, propagate {mp2:.2f} ms; max |dP| {dpop} over {n_res} "
               f"resolved bins", file=sys.stderr, flush=True)
