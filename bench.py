@@ -238,7 +238,7 @@ def batched_leg(P, torch, n_instances=256):
                 1 for v in table.choice.values() if v == 3), "seconds": tune_s}}, table
 
 
-def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=50, full=False, table=None):
+def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=None, quantum_work=2e8):
     """The served stream through the continuous-batching server.  Default:
     the sub-saturation variant (walkers log-uniform over 1e5-1e7); ``full``
     uses 1e5-1e8, whose offered load exceeds one device."""
@@ -249,9 +249,13 @@ def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=50, full=False, table=No
     specs = [JobSpec(wl, prec="fp32", name=f"{i}:{wl.model.name}") for i, wl in enumerate(wls)]
     from paper_2608_14544_amd.tune import autotune
     table = autotune(wls, "fp32", table)  # untimed; classes already tuned are kept
-    srv = Server(DeviceBackend(tuning=table), quantum_steps=quantum)
+    srv = Server(DeviceBackend(tuning=table), quantum_steps=quantum, quantum_work=quantum_work)
     res = srv.run(arrivals, specs)
     st = latency_stats(res)
+    # the same stream with a fixed 50-step quantum per job, for comparison
+    srv2 = Server(DeviceBackend(tuning=table), quantum_steps=50)
+    st2 = latency_stats(srv2.run(arrivals, specs))
+    st["fixed_50_step_quantum"] = {k: st2[k] for k in ("p50_s", "p99_s", "walker_steps_per_s", "makespan_s")}
     kinds = {}
     for rr in res:
         kind = rr.name.split(":", 1)[1] if ":" in rr.name else "job"
@@ -265,7 +269,8 @@ def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=50, full=False, table=No
                            f"{traj_range[1]:.0e}], 500-2000 steps; fp32",
                "variant": "full" if full else "sub-saturation",
                "offered_walker_steps_per_s": offered,
-               "rounds": srv.rounds, "quantum_steps": quantum,
+               "rounds": srv.rounds, "quantum": f"{quantum_work:.0e} walker-steps per job per round, "
+                                                 f"at most {quantum} steps",
                "memory_budget_GB": srv.budget / 1e9})
     return st
 
@@ -298,6 +303,8 @@ def main():
     ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling",
                     help="comma-separated subset of headline,spin_boson,batched,served,scaling")
     ap.add_argument("--served-jobs", type=int, default=200)
+    ap.add_argument("--served-quantum-work", type=float, default=2e8,
+                    help="walker-steps per resident job per serving round")
     ap.add_argument("--served-full", action="store_true",
                     help="served stream with 1e5-1e8 walkers per random job (offered load above capacity)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -408,7 +415,8 @@ def main():
               f"({line['batched']['ms']:.0f} ms)", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     if "served" in legs:
-        line["served"] = served_leg(P, torch, args.served_jobs, full=args.served_full, table=table)
+        line["served"] = served_leg(P, torch, args.served_jobs, full=args.served_full, table=table,
+                                    quantum_work=args.served_quantum_work)
         print(f"[bench] served: {line['served']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     if "scaling" in legs:

@@ -247,7 +247,11 @@ qcl_status qcl_batch_workspace_bytes(const qcl_batch_item *items, int32_t n_item
  * persistent launch (about one workgroup per free slot of the device);
  * its workgroups take (item, tile of QCL_TILE walkers) pairs from a device
  * counter, heaviest tiles first, so uneven instances balance across the
- * device.  Classes run one after another on the stream, heaviest first.
+ * device.  Several classes run concurrently on internal streams forked
+ * from the given stream and joined back into it (the call stays ordered on
+ * the given stream); the first call with more than one class on a device
+ * creates those streams and their events, which live until the process
+ * ends.
  *
  * workspace: device, >= qcl_batch_workspace_bytes(items, n_items),
  * 256-byte aligned; holds the descriptors and counters and is written by

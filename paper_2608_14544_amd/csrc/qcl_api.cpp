@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -213,6 +214,46 @@ struct BatchPlan {
     std::vector<BatchClass> classes;
     size_t bytes = 0;
 };
+
+// Side streams for running the classes of one batched call concurrently:
+// forked from the caller's stream by an event and joined back into it, so
+// the call stays ordered on the caller's stream.  Created on a device's
+// first multi-class call (default priority) and kept until the process
+// ends; the mutex keeps the fork/join sequences of concurrent host threads
+// apart.
+constexpr int kSideStreams = 4;
+struct Fan {
+    bool ready = false;
+    hipStream_t s[kSideStreams];
+    hipEvent_t fork;
+    hipEvent_t join[kSideStreams];
+};
+std::mutex g_fan_mutex;
+std::vector<Fan> g_fans;
+
+hipError_t device_fan(Fan *&out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if ((int)g_fans.size() <= dev)
+        g_fans.resize(dev + 1);
+    Fan &f = g_fans[dev];
+    if (!f.ready) {
+        for (int k = 0; k < kSideStreams; ++k)
+            if ((e = hipStreamCreateWithFlags(&f.s[k], hipStreamNonBlocking)) != hipSuccess)
+                return e;
+        if ((e = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming)) != hipSuccess)
+            return e;
+        for (int k = 0; k < kSideStreams; ++k)
+            if ((e = hipEventCreateWithFlags(&f.join[k], hipEventDisableTiming)) != hipSuccess)
+                return e;
+        f.ready = true;
+    }
+    out = &f;
+    return hipSuccess;
+}
 
 qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &plan)
 {
@@ -617,15 +658,42 @@ qcl_status qcl_propagate_batch(const qcl_batch_item *items, int32_t n_items, voi
         if (e != hipSuccess)
             return device_fail(e, "batch descriptor upload");
     }
-    for (const BatchClass &c : plan.classes) {
-        hipError_t e = qcl::launch_batch(*items[c.order[0]].model, c.prec, c.scheme, c.occ, ws + c.offset,
-                                         (int32_t)c.order.size(), c.total_tiles,
-                                         (unsigned long long *)(ws + c.counter_offset), s);
-        if (e == hipErrorNotSupported)
-            return fail(QCL_ERR_UNSUPPORTED, "no batched kernel for this model class");
-        if (e != hipSuccess)
-            return device_fail(e, "batched propagate launch");
+    auto launch_class = [&](const BatchClass &c, hipStream_t on) {
+        return qcl::launch_batch(*items[c.order[0]].model, c.prec, c.scheme, c.occ, ws + c.offset,
+                                 (int32_t)c.order.size(), c.total_tiles,
+                                 (unsigned long long *)(ws + c.counter_offset), on);
+    };
+    hipError_t e = hipSuccess;
+    if (plan.classes.size() == 1) {
+        e = launch_class(plan.classes[0], s);
+    } else if (plan.classes.size() > 1) {
+        // heaviest class first, one side stream per class in turn; a class
+        // whose last tiles leave CUs idle is overlapped by the next class
+        std::lock_guard<std::mutex> lock(g_fan_mutex);
+        Fan *f = nullptr;
+        if ((e = device_fan(f)) != hipSuccess)
+            return device_fail(e, "side stream set-up");
+        const int used = (int)std::min<size_t>(kSideStreams, plan.classes.size());
+        if ((e = hipEventRecord(f->fork, s)) != hipSuccess)
+            return device_fail(e, "hipEventRecord");
+        for (int k = 0; k < used; ++k)
+            if ((e = hipStreamWaitEvent(f->s[k], f->fork, 0)) != hipSuccess)
+                return device_fail(e, "hipStreamWaitEvent");
+        for (size_t i = 0; i < plan.classes.size() && e == hipSuccess; ++i)
+            e = launch_class(plan.classes[i], f->s[i % used]);
+        // join whatever was launched back into the caller's stream
+        for (int k = 0; k < used; ++k) {
+            hipError_t ej = hipEventRecord(f->join[k], f->s[k]);
+            if (ej == hipSuccess)
+                ej = hipStreamWaitEvent(s, f->join[k], 0);
+            if (ej != hipSuccess && e == hipSuccess)
+                e = ej;
+        }
     }
+    if (e == hipErrorNotSupported)
+        return fail(QCL_ERR_UNSUPPORTED, "no batched kernel for this model class");
+    if (e != hipSuccess)
+        return device_fail(e, "batched propagate launch");
     for (int32_t i = 0; i < n_items; ++i)
         items[i].ens->step += items[i].prop.n_steps;
     return QCL_OK;

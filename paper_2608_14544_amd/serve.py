@@ -2,9 +2,8 @@
 
 Jobs (a model, an initial state, a walker count, a step count, a
 precision) arrive over time.  The server keeps every admitted ensemble
-resident in device memory and advances all of them together in quanta of
-at most ``quantum_steps`` steps, one ``qcl_propagate_batch`` call per
-quantum (Sec. II.B: walkers are independent, so ensembles of different
+resident in device memory and advances all of them together in quanta,
+one ``qcl_propagate_batch`` call per quantum (Sec. II.B: walkers are independent, so ensembles of different
 models and sizes can share a launch).  Between quanta it
 
   * admits queued jobs while their device footprint (walker arrays,
@@ -14,6 +13,12 @@ models and sizes can share a launch).  Between quanta it
   * retires jobs whose last step has been enqueued: their observables are
     reduced on the device, copied to host memory asynchronously and their
     device buffers are given back.
+
+A quantum is either a fixed step count per job (``quantum_steps``) or a
+fixed amount of work per job (``quantum_work`` walker-steps, i.e.
+quantum_work / n_traj steps, at least one and at most ``quantum_steps``):
+the second shares the device roughly equally between resident jobs, so a
+small job is not held back by rounds sized for large ones.
 
 Because a batched launch and any split of the steps into calls leave each
 ensemble's arithmetic unchanged, a job's result is bitwise the one it gets
@@ -176,7 +181,8 @@ class _DeviceFuture:
 class Server:
     def __init__(self, backend=None, memory_budget: Optional[int] = None, max_slots: int = 64,
                  quantum_steps: int = 50, max_backfill_wait: float = 2.0,
-                 clock: Callable[[], float] = time.perf_counter, max_in_flight: int = 2):
+                 clock: Callable[[], float] = time.perf_counter, max_in_flight: int = 2,
+                 quantum_work: Optional[float] = None):
         self.backend = backend if backend is not None else DeviceBackend()
         if memory_budget is None:
             import torch
@@ -185,6 +191,7 @@ class Server:
         self.budget = int(memory_budget)
         self.max_slots = int(max_slots)
         self.quantum = int(quantum_steps)
+        self.quantum_work = None if quantum_work is None else float(quantum_work)
         self.max_backfill_wait = float(max_backfill_wait)
         self.clock = clock
         self.t0 = clock()
@@ -231,7 +238,7 @@ class Server:
                 self.backend.wait(self.tokens.popleft())
             work = []
             for j in self.active:
-                n = min(self.quantum, j.spec.n_steps - j.done_steps)
+                n = min(self._steps_per_round(j.spec), j.spec.n_steps - j.done_steps)
                 work.append((j.handle, j.spec, n))
                 j.done_steps += n
             self.backend.advance([w for w in work if w[2] > 0])
@@ -272,6 +279,11 @@ class Server:
         return self.results
 
     # ------------------------------------------------------------ internals
+    def _steps_per_round(self, spec: JobSpec) -> int:
+        if self.quantum_work is None:
+            return self.quantum
+        return max(1, min(self.quantum, int(self.quantum_work // max(spec.n_traj, 1))))
+
     def _collect(self) -> List[JobResult]:
         done, keep = [], []
         for j in self.draining:

@@ -156,3 +156,19 @@ def test_failing_jobs_are_answered_not_fatal():
     res = {r.name: r for r in srv.results}
     assert "invalid model" in res["bad"].error and "out of memory" in res["oom"].error
     assert not res["good"].error and srv.used == 0
+
+
+def test_work_based_quanta():
+    clock = Clock()
+    be = SimBackend(clock, bytes_per_walker=1, walker_steps_per_s=1e6, sleep_until=clock.until)
+    srv = Server(be, memory_budget=10 ** 9, quantum_steps=1000, quantum_work=10_000, clock=clock)
+    srv.submit(spec("small", 100, 300))     # 100 steps per round: done in 3 rounds
+    srv.submit(spec("large", 10_000, 20))   # 1 step per round
+    drive(srv, clock)
+    steps = {}
+    for rnd in be.log:
+        for name, n in rnd:
+            steps.setdefault(name, []).append(n)
+    assert steps["small"] == [100, 100, 100] and steps["large"] == [1] * 20
+    res = {r.name: r for r in srv.results}
+    assert res["small"].finished < res["large"].finished
