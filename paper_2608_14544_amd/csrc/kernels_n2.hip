@@ -149,7 +149,9 @@ __device__ __forceinline__ void bin_values(double (&v)[32], bool live, int a, in
     const double ub0 = b ? d0 : -d1;  // C_0b
     const double ub1 = b ? d1 : d0;   // C_1b
     const double sg = (a == b) ? 1.0 : (double)sig;
-    const double c[4] = {sg * (ua0 * ub0), sg * (ua0 * ub1), sg * (ua1 * ub0), sg * (ua1 * ub1)};
+    // an excluded walker contributes exact zeros (its frame may be NaN)
+    const double c[4] = {ok ? sg * (ua0 * ub0) : 0.0, ok ? sg * (ua0 * ub1) : 0.0, ok ? sg * (ua1 * ub0) : 0.0,
+                         ok ? sg * (ua1 * ub1) : 0.0};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const double r = re * c[t], m = im * c[t];
@@ -190,6 +192,10 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
     geo_at<M, double>(C, q, g, flag);
     double c0, c1;
     canon2<double>(g, c0, c1);
+    if (!(g.r > 0.0)) {  // exact degeneracy: any basis diagonalises V; take the identity
+        c0 = 0.0;
+        c1 = 1.0;
+    }
     // column signs without a previous frame: U_kk > 0, else the first
     // nonzero entry of the column positive.  Column 0 = s0 (-c1, c0),
     // column 1 = s1 (c0, c1).
