@@ -103,3 +103,35 @@ def test_general_fp32_near_degenerate(P):
     se = np.maximum(out_o[..., 2:], 1e-300)
     print("crossing3 fp32 max abs err", d.max(), "max err/SE", (d / se).max(), flush=True)
     assert np.all((d <= 1e-3) | (d <= 3 * se))
+
+
+@pytest.mark.parametrize("name", ["n3_m3", "n4_m5"])
+def test_general_linear_rule_parity(P, name):
+    """The linear transition rule (with its fallback to the normalized one
+    when S >= 1) on the general kernels, binary64, per walker."""
+    wl = CASES[name]()
+    out_g, st_g, _, _ = gpu_run(P, wl, scheme=1)
+    out_o, st_o, _, fl_o = oracle_run(wl, scheme=1)
+    assert np.array_equal(st_g["flags"] & 8, np.asarray(fl_o) & 8)  # same walkers fell back
+    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label=name + " linear")
+    if nflip == 0:
+        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+
+
+@pytest.mark.parametrize("n_states", [2, 3, 4])
+def test_adiabatic_initial_state(P, n_states):
+    """Start in an adiabatic state (element (k, k), weight 1) on both kernel
+    families: samples and propagated walkers against the oracle."""
+    if n_states == 2:
+        wl = W.pyrazine_ci(n_traj=2000, n_steps=60, cadence=10)
+    else:
+        wl = W.random_lvc(30 + n_states, n_states=n_states, n_modes=6, n_traj=2000, n_steps=60, cadence=10)
+    wl.init.basis = W.INIT_ADIABATIC
+    wl.init.state = n_states - 1
+    out_g, st_g, s0_g, _ = gpu_run(P, wl)
+    out_o, st_o, s0_o, _ = oracle_run(wl)
+    assert np.all(s0_g["a"] == n_states - 1) and np.all(s0_g["b"] == n_states - 1) and np.all(s0_g["w"] == 1.0)
+    compare_walkers(s0_g, s0_o, rtol=1e-11, label=f"adiabatic N{n_states} sample")
+    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label=f"adiabatic N{n_states}")
+    if nflip == 0:
+        assert ensemble_close(out_g, out_o, wl.run.n_traj)
