@@ -19,7 +19,9 @@ two.  Two further legs are reported in the same line:
            continuous-batching server: walker-steps/s and p50/p99 latency;
   scaling  the headline model at 1e4..1e8 walkers in both precisions;
   spin_boson  the 3-mode Ohmic spin-boson runs (1e6 walkers, 2000 steps,
-           kT 0.2 and 1.0) in both precisions with their population difference.
+           kT 0.2 and 1.0) in both precisions with their population difference;
+  convergence  the pyrazine-like and spin-boson (kT 0.2) models at 1e6, 1e7
+           and 1e8 walkers: horizons of agreement and the decay rate.
 
 Prints one JSON line.
 
@@ -290,6 +292,39 @@ def scaling_leg(P, torch, wl, sizes=(10_000, 100_000, 1_000_000, 10_000_000, 100
     return out
 
 
+def _json_safe(x):
+    """inf/NaN -> None (the JSON line stays strict JSON)."""
+    if isinstance(x, float):
+        return x if math.isfinite(x) else None
+    if isinstance(x, dict):
+        return {k: _json_safe(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_json_safe(v) for v in x]
+    return x
+
+
+def convergence_leg(P, torch, counts=(10**6, 10**7, 10**8)):
+    """Walker-count convergence (the paper's Figs. 3-4): the pyrazine-like
+    model over 100 fs in 1 fs bins and the 3-mode spin-boson model (kT 0.2)
+    at 1e6, 1e7 and 1e8 walkers on disjoint walker-id ranges, both
+    precisions; per run the device time, the resolved and agreement
+    horizons (tolerance 0.02 in population) and, for the pyrazine-like
+    model, the decay rate of the excited adiabatic population."""
+    import workloads as W
+    from paper_2608_14544_amd import study
+    res = {}
+    cases = (("pyrazine_ci", W.pyrazine_ci(n_traj=0, n_steps=200, cadence=2), True),
+             ("spin_boson_kT0.2", W.spin_boson_ohmic(kT=0.2, n_traj=0), False))
+    for name, wl, fit in cases:
+        for prec in ("fp32", "fp64"):
+            summary, _ = study.walker_study(wl, counts, prec=prec, tol=0.02, fit=fit)
+            summary["time_unit"] = "fs" if wl.model.time_unit_fs else "reduced"
+            summary["n_steps"], summary["cadence"] = wl.run.n_steps, wl.run.cadence
+            res[f"{name}_{prec}"] = _json_safe(summary)
+            torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,7 +335,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling",
+    ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling,convergence",
                     help="comma-separated subset of headline,spin_boson,batched,served,scaling")
     ap.add_argument("--served-jobs", type=int, default=200)
     ap.add_argument("--served-quantum-work", type=float, default=2e8,
@@ -423,6 +458,13 @@ def main():
         line["scaling_sweep"] = scaling_leg(P, torch, wl)
         print(f"[bench] scaling sweep: " + ", ".join(f"{x['prec']} {x['n_traj']:.0e}: {x['ms']:.1f} ms"
                                                     for x in line["scaling_sweep"]), file=sys.stderr, flush=True)
+    if "convergence" in legs:
+        line["convergence"] = convergence_leg(P, torch)
+        for key, v in line["convergence"].items():
+            print(f"[bench] convergence {key}: " + "; ".join(
+                f"{r['n_traj']:.0e} {r['seconds']:.2f} s resolved<={r['resolved_until']}"
+                + (f" rate {r['rate']:.4f}+-{r['rate_se']:.4f}" if r.get("rate") is not None else "")
+                for r in v["runs"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)

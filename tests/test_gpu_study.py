@@ -1,0 +1,97 @@
+"""Walker-count convergence and decay-rate study (Sec. III.B, Figs. 3-4) on
+the device, against the oracle at small sizes and by its properties at the
+paper's sizes (1e6, 1e7, 1e8 walkers)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle.core as oc
+import oracle.decay as D
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2608_14544_amd as pkg
+    pkg.load_library()
+    from paper_2608_14544_amd import study
+    return study
+
+
+def test_study_parity_fp64(S):
+    wl = W.pyrazine_ci(n_traj=0, n_steps=60, cadence=2)
+    counts = [2000, 8000, 32000]
+    offsets = [40000, 32000, 0]  # disjoint id ranges, largest run first
+    res, curves = S.walker_study(wl, counts, prec="fp64", tol=0.02)
+    assert [c.traj_offset for c in curves] == offsets
+    ora = []
+    for n, off in zip(counts, offsets):
+        out, _, _ = oc.run(wl, n_traj=n, traj_offset=off)
+        m, se = D.excited_population(out)
+        ora.append((np.array(m), np.array(se)))
+    t = curves[0].t
+    assert np.allclose(t, np.arange(31) * 1.0, rtol=0, atol=1e-12)  # 1 fs bins
+    for c, (m, se) in zip(curves, ora):
+        rms = np.sqrt(se ** 2 * c.n_traj + m ** 2)
+        err = np.abs(c.p - m)
+        print(f"n={c.n_traj} max|dP|={err.max():.3e} max|dSE|={np.abs(c.se - se).max():.3e}", flush=True)
+        assert np.all(err <= 1e-9 * np.maximum(1.0, rms))
+        assert np.all(np.abs(c.se - se) <= 1e-9 * np.maximum(1.0, rms))
+    m_ref = ora[2][0]
+    t0 = D.first_time_at_or_below(t, m_ref, 0.8)
+    t1 = D.first_time_at_or_below(t, m_ref, 0.3)
+    assert res["window"] == [t0, t1] and t1 - t0 >= 3.0
+    fitted = 0
+    for row, (m, se) in zip(res["runs"], ora):
+        assert row["resolved_until"] == D.horizon(t, se, 0.02)
+        if row["n_traj"] != 32000:
+            assert row["agrees_until"] == D.horizon(t, m - m_ref, 0.02)
+        try:
+            k, ks, a, used = D.decay_rate(t, m, se, t0, t1)
+        except ValueError:  # P <= 0 inside the window: neither side fits
+            print(f"n={row['n_traj']} no fit: {row.get('fit_error')}", flush=True)
+            assert row["rate"] is None
+            continue
+        print(f"n={row['n_traj']} rate={row['rate']:.6f}+-{row['rate_se']:.6f} oracle {k:.6f}", flush=True)
+        assert math.isclose(row["rate"], k, rel_tol=1e-8) and math.isclose(row["rate_se"], ks, rel_tol=1e-8)
+        assert math.isclose(row["amplitude"], a, rel_tol=1e-8) and row["fit_bins"] == used
+        fitted += 1
+    assert fitted >= 1
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_study_paper_sizes(S, prec):
+    """The pyrazine-like model at 1e6, 1e7 and 1e8 walkers (100 fs, 1 fs
+    bins).  Properties that hold at any size: the standard error falls as
+    1/sqrt(N) (ratio at the first bins), the resolved horizon does not shrink
+    with N, every run agrees with the largest within the tolerance while both
+    are resolved, and the smallest run already fixes the decay rate within
+    three combined standard errors (the paper's statement for 1e6 walkers)."""
+    wl = W.pyrazine_ci(n_traj=0, n_steps=200, cadence=2)
+    counts = [10**6, 10**7, 10**8]
+    res, curves = S.walker_study(wl, counts, prec=prec, tol=0.02)
+    rows = res["runs"]
+    for r in rows:
+        print({k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}, flush=True)
+    print("window", res["window"], flush=True)
+    for r in rows:
+        assert r["nonfinite"] == 0 and r["degenerate"] == 0
+    for small, big in zip(curves[:-1], curves[1:]):
+        ratio = small.se[1:4] / big.se[1:4]
+        assert np.all(np.abs(ratio / math.sqrt(10.0) - 1.0) < 0.15), ratio
+    hz = [r["resolved_until"] for r in rows]
+    assert hz[0] <= hz[1] <= hz[2] and hz[2] >= 20.0
+    for r, c in zip(rows[:-1], curves[:-1]):
+        ok = min(S.first_exceed(c.se, 0.01), S.first_exceed(curves[-1].se, 0.01))
+        dev = np.abs(c.p - curves[-1].p)[:ok]
+        comb = np.sqrt(c.se ** 2 + curves[-1].se ** 2)[:ok]
+        assert np.all(dev <= 5.0 * comb + 1e-12), (r["n_traj"], float((dev / comb).max()))
+    k6, k8 = rows[0], rows[2]
+    assert k6["rate"] is not None and k8["rate"] is not None
+    assert abs(k6["rate"] - k8["rate"]) <= 3.0 * math.hypot(k6["rate_se"], k8["rate_se"])
+    assert 0.05 < k8["rate"] < 1.0  # per fs: the fast decay takes a few fs
