@@ -34,7 +34,13 @@ class Enumerator:
 
     # -- electronic structure (numpy eigh + sign conventions) -------------
     def V(self, q):
-        return self.m.v0 + np.tensordot(q, self.m.k, axes=(0, 0))
+        """V0 + sum_j q_j K_j (+ sum_j sum_k q_j^k A_jk for models with higher powers)."""
+        v = self.m.v0 + np.tensordot(q, self.m.k, axes=(0, 0))
+        poly = getattr(self.m, "poly", None)
+        if poly is not None:
+            for k in range(2, poly.shape[1] + 2):
+                v = v + np.tensordot(np.asarray(q) ** k, poly[:, k - 2], axes=(0, 0))
+        return v
 
     def eig(self, q, Uprev=None):
         E, U = np.linalg.eigh(self.V(q))

@@ -45,7 +45,7 @@ class _Model(C.Structure):
     _fields_ = [("n_states", C.c_int32), ("n_modes", C.c_int32),
                 ("mass", C.POINTER(C.c_double)), ("omega", C.POINTER(C.c_double)),
                 ("v0", C.POINTER(C.c_double)), ("k", C.POINTER(C.c_double)),
-                ("hbar", C.c_double)]
+                ("hbar", C.c_double), ("degree", C.c_int32), ("a", C.POINTER(C.c_double))]
 
 
 _dp = C.POINTER(C.c_double)
@@ -69,7 +69,7 @@ def lib():
             L.or_gauge.argtypes = [C.c_int, _dp, _dp]
             L.or_adiabatic.argtypes = [C.POINTER(_Model), _dp, _dp, _dp, _dp]
             L.or_mean_force.argtypes = [C.POINTER(_Model), _dp, _dp, C.c_int, C.c_int, _dp]
-            L.or_velocity_nac.argtypes = [C.POINTER(_Model), _dp, _dp, _dp, _dp]
+            L.or_velocity_nac.argtypes = [C.POINTER(_Model), _dp, _dp, _dp, _dp, _dp]
             L.or_candidates.argtypes = [C.c_int, _dp, C.c_double, C.c_int, C.c_int, _dp, _ip, _ip]
             L.or_candidates.restype = C.c_int
             L.or_transition.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int,
@@ -111,8 +111,11 @@ class Model:
         self.k = np.ascontiguousarray(m.k, np.float64)
         self.n = int(self.v0.shape[0])
         self.M = int(self.mass.shape[0])
+        poly = getattr(m, "poly", None)
+        self.degree = 1 if poly is None else int(poly.shape[1]) + 1
+        self.a = None if poly is None else np.ascontiguousarray(poly, np.float64)
         self.c = _Model(self.n, self.M, _d(self.mass), _d(self.omega), _d(self.v0), _d(self.k),
-                        float(m.hbar))
+                        float(m.hbar), self.degree, _d(self.a) if self.a is not None else None)
 
     @property
     def ref(self):
@@ -168,10 +171,14 @@ def mean_force(m, q, U, a, b):
     return F
 
 
-def velocity_nac(m, p, E, U):
+def velocity_nac(m, p, E, U, q=None):
+    """v.d for all pairs; q is needed when the model has powers above 1."""
     mm = _model(m)
     vd = np.zeros((mm.n, mm.n))
-    lib().or_velocity_nac(mm.ref, _d(np.ascontiguousarray(p, np.float64)),
+    if q is None and mm.degree > 1:
+        raise ValueError("velocity_nac of a model with higher powers needs q")
+    qp = _d(np.ascontiguousarray(q, np.float64)) if q is not None else None
+    lib().or_velocity_nac(mm.ref, qp, _d(np.ascontiguousarray(p, np.float64)),
                           _d(np.ascontiguousarray(E, np.float64)),
                           _d(np.ascontiguousarray(U, np.float64)), _d(vd))
     return vd

@@ -31,6 +31,11 @@
  *     each column kept continuous by overlap with the previous step;
  *   - observables normalised by the number of walkers.
  *
+ * Beyond the linear-vibronic form V(q) = V0 + sum_j q_j K_j, a model may
+ * carry higher separable powers sum_{k=2..4} q_j^k A_jk (state-dependent
+ * frequencies and anharmonicity); forces and couplings then use
+ * dV/dq_j = K_j + sum_k k q_j^(k-1) A_jk, evaluated directly.
+ *
  * Floating point: IEEE binary64, compiled without fast-math and without
  * FMA contraction.
  */
@@ -54,6 +59,8 @@ typedef struct {
     const double *v0;     /* [N][N] */
     const double *k;      /* [M][N][N] */
     double hbar;
+    int32_t degree;       /* highest power of q_j in V(q): 1 (linear) .. 4 */
+    const double *a;      /* [M][degree-1][N][N]: A_jk for k = 2..degree, or NULL */
 } or_model;
 
 /* ------------------------------------------------------------------ */
@@ -203,15 +210,43 @@ void or_gauge(int n, const double *Uprev, double *U)
     }
 }
 
-/* Electronic Hamiltonian V(q) = V0 + sum_j q_j K_j. */
+/* Entry i of A_jk (k >= 2) of a model with higher powers. */
+static double poly_entry(const or_model *m, int j, int k, int i)
+{
+    int n = m->n_states;
+    return m->a[((size_t)j * (m->degree - 1) + (k - 2)) * n * n + i];
+}
+
+/* Electronic Hamiltonian V(q) = V0 + sum_j [q_j K_j + sum_{k=2..D} q_j^k A_jk]. */
 void or_potential(const or_model *m, const double *q, double *V)
 {
     int n = m->n_states, M = m->n_modes;
     for (int i = 0; i < n * n; ++i) {
         double v = m->v0[i];
-        for (int j = 0; j < M; ++j)
+        for (int j = 0; j < M; ++j) {
             v += q[j] * m->k[j * n * n + i];
+            double qk = q[j];
+            for (int k = 2; k <= m->degree; ++k) {
+                qk *= q[j];
+                v += qk * poly_entry(m, j, k, i);
+            }
+        }
         V[i] = v;
+    }
+}
+
+/* dV/dq_j = K_j + sum_{k=2..D} k q_j^(k-1) A_jk, an N x N matrix. */
+static void mode_gradient(const or_model *m, int j, double qj, double *Gj)
+{
+    int n = m->n_states;
+    for (int i = 0; i < n * n; ++i) {
+        double g = m->k[(size_t)j * n * n + i];
+        double qk = 1.0;
+        for (int k = 2; k <= m->degree; ++k) {
+            qk *= qj;
+            g += k * qk * poly_entry(m, j, k, i);
+        }
+        Gj[i] = g;
     }
 }
 
@@ -245,30 +280,34 @@ static void rotate_to_adiabatic(int n, const double *U, const double *Amat, doub
 }
 
 /* Mean classical force on element (a,b):
- * F_j = -m_j w_j^2 q_j - [ (U^T K_j U)_aa + (U^T K_j U)_bb ] / 2,
+ * F_j = -m_j w_j^2 q_j - [ (U^T dV/dq_j U)_aa + (U^T dV/dq_j U)_bb ] / 2,
  * i.e. (F_a + F_b)/2 with Hellmann-Feynman F_alpha (Eq. 1, last term). */
 void or_mean_force(const or_model *m, const double *q, const double *U, int a, int b, double *F)
 {
     int n = m->n_states;
-    double G[OR_MAXN * OR_MAXN];
+    double G[OR_MAXN * OR_MAXN], Gj[OR_MAXN * OR_MAXN];
     for (int j = 0; j < m->n_modes; ++j) {
-        rotate_to_adiabatic(n, U, m->k + (size_t)j * n * n, G);
+        mode_gradient(m, j, q[j], Gj);
+        rotate_to_adiabatic(n, U, Gj, G);
         F[j] = -m->mass[j] * m->omega[j] * m->omega[j] * q[j]
                - 0.5 * (G[a * n + a] + G[b * n + b]);
     }
 }
 
-/* (P/M).d_ab for all pairs: D = U^T (sum_j v_j K_j) U, v.d_ab = D_ab/(E_b - E_a)
- * for a != b and 0 on the diagonal.  Output vd [N][N]. */
-void or_velocity_nac(const or_model *m, const double *p, const double *E, const double *U, double *vd)
+/* (P/M).d_ab for all pairs: D = U^T (sum_j v_j dV/dq_j) U, v.d_ab =
+ * D_ab/(E_b - E_a) for a != b and 0 on the diagonal.  Output vd [N][N].
+ * q may be NULL for a linear model (dV/dq_j = K_j does not depend on it). */
+void or_velocity_nac(const or_model *m, const double *q, const double *p, const double *E, const double *U,
+                     double *vd)
 {
     int n = m->n_states;
-    double Kv[OR_MAXN * OR_MAXN], D[OR_MAXN * OR_MAXN];
-    for (int i = 0; i < n * n; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < m->n_modes; ++j)
-            s += (p[j] / m->mass[j]) * m->k[(size_t)j * n * n + i];
-        Kv[i] = s;
+    double Kv[OR_MAXN * OR_MAXN], D[OR_MAXN * OR_MAXN], Gj[OR_MAXN * OR_MAXN];
+    for (int i = 0; i < n * n; ++i)
+        Kv[i] = 0.0;
+    for (int j = 0; j < m->n_modes; ++j) {
+        mode_gradient(m, j, q ? q[j] : 0.0, Gj);
+        for (int i = 0; i < n * n; ++i)
+            Kv[i] += (p[j] / m->mass[j]) * Gj[i];
     }
     rotate_to_adiabatic(n, U, Kv, D);
     for (int a = 0; a < n; ++a)
@@ -496,7 +535,7 @@ static void propagate_one(const or_model *m, uint64_t gid, int64_t step0, int n_
         for (int i = 0; i + 1 < n; ++i)
             if (!(E[i + 1] - E[i] > 2.2250738585072014e-308))
                 *flag |= OR_FLAG_DEGENERATE;
-        or_velocity_nac(m, p, E, U, vd);
+        or_velocity_nac(m, q, p, E, U, vd);
         uint32_t x[4];
         philox_block(seed, gid, (uint32_t)(step >> 2), 0u, x);
         double u = or_uniform24(x[step & 3]);

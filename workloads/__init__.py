@@ -11,6 +11,12 @@ Model family (Sec. II.A, Eq. 1 symbols R, P, M; Sec. II.C models):
     H = sum_j p_j^2/(2 m_j) + sum_j m_j w_j^2 q_j^2 / 2 + V(q),
     V(q) = V0 + sum_j q_j K_j           (V0, K_j real symmetric N x N)
 
+optionally with separable higher powers of each mode (``poly``):
+
+    V(q) += sum_j sum_{k=2..D} q_j^k A_jk   (A_jk real symmetric, D <= 4)
+
+which adds state-dependent frequencies (k = 2) and anharmonicity (k = 3, 4).
+
 Workloads (sizes from the headline configurations; parameters of the
 paper's 3-D spin-boson model live in its cited references and are replaced
 by an Ohmic discretisation here; the pyrazine-like model uses the
@@ -47,12 +53,20 @@ class LVCModel:
     k: np.ndarray      # [M, N, N] each symmetric
     hbar: float = 1.0
     time_unit_fs: Optional[float] = None  # fs per internal time unit (eV models)
+    poly: Optional[np.ndarray] = None  # [M, D-1, N, N]: A_jk for k = 2..D (D <= 4), each symmetric
 
     def __post_init__(self):
         self.mass = np.ascontiguousarray(self.mass, dtype=np.float64)
         self.omega = np.ascontiguousarray(self.omega, dtype=np.float64)
         self.v0 = np.ascontiguousarray(self.v0, dtype=np.float64)
         self.k = np.ascontiguousarray(self.k, dtype=np.float64)
+        if self.poly is not None:
+            self.poly = np.ascontiguousarray(self.poly, dtype=np.float64)
+
+    @property
+    def degree(self) -> int:
+        """Highest power of q_j in V(q): 1 for an LVC model."""
+        return 1 if self.poly is None else int(self.poly.shape[1]) + 1
 
     @property
     def n_states(self) -> int:
@@ -219,6 +233,58 @@ def random_lvc(index: int, key: int = 4, n_modes: Optional[int] = None,
     init = InitSpec(kT=kT, q0=state1_minimum(model), state=0)
     seed = (key << 32) | (index & 0xFFFFFFFF)
     return Workload(model, init, RunSpec(T, S, dt, cadence, seed))
+
+
+def pyrazine_qvc(n_traj: int = 1_000_000, n_steps: int = 200, dt_fs: float = 0.5,
+                 cadence: int = 2, seed: int = 7) -> Workload:
+    """The pyrazine-like model with state-dependent frequencies and a
+    quartic tuning mode: V(q) gains sum_j (gamma_j/2) q_j^2 diag(-1, +1) on
+    the two totally symmetric modes (the upper state softer along nu6a,
+    stiffer along nu1) and (lambda/24) q^4 I on nu6a (energies in eV,
+    dimensionless coordinates, as ``pyrazine_ci``)."""
+    base = pyrazine_ci(n_traj=n_traj, n_steps=n_steps, dt_fs=dt_fs, cadence=cadence, seed=seed)
+    m = base.model
+    poly = np.zeros((3, 3, 2, 2))  # powers 2, 3, 4
+    poly[0, 0] = 0.5 * 0.012 * np.diag([-1.0, 1.0])   # nu1: gamma = 0.012 eV
+    poly[1, 0] = 0.5 * -0.018 * np.diag([-1.0, 1.0])  # nu6a: gamma = -0.018 eV
+    poly[1, 2] = (0.004 / 24.0) * np.eye(2)           # nu6a: lambda = 0.004 eV
+    model = LVCModel(name="pyrazine_qvc", mass=m.mass, omega=m.omega, v0=m.v0, k=m.k, hbar=m.hbar,
+                     time_unit_fs=m.time_unit_fs, poly=poly)
+    return Workload(model, base.init, base.run)
+
+
+def random_poly(index: int, n_states: int = 3, n_modes: int = 5, degree: int = 4, key: int = 6,
+                n_traj: int = 2000, n_steps: int = 100, dt: float = 0.05, cadence: int = 10,
+                rank_full: bool = True) -> Workload:
+    """An N-state model with every power up to ``degree`` in every mode,
+    drawn from (key, index).  Linear and higher couplings are dense random
+    symmetric matrices (so the coupling space has full rank when
+    ``rank_full``), cubic terms are small, and each quartic term is a
+    positive multiple of the identity plus a smaller symmetric part, so every
+    adiabatic surface is confining."""
+    rng = np.random.Generator(np.random.Philox(key=[key, index]))
+    N, M = int(n_states), int(n_modes)
+
+    def sym(scale):
+        a = rng.uniform(-scale, scale, size=(N, N))
+        return 0.5 * (a + a.T)
+
+    bias = np.linspace(-0.4, 0.4, N)
+    v0 = np.diag(bias) + sym(0.1) * (1.0 - np.eye(N))
+    omega = rng.uniform(0.5, 1.5, size=M)
+    mass = rng.uniform(0.7, 1.4, size=M)
+    k = np.stack([sym(0.3) if rank_full else 0.3 * rng.uniform(-1, 1) * _z_diag(N) for _ in range(M)])
+    poly = np.zeros((M, degree - 1, N, N))
+    for j in range(M):
+        poly[j, 0] = sym(0.1 * mass[j] * omega[j] ** 2)
+        if degree >= 3:
+            poly[j, 1] = sym(0.02)
+        if degree >= 4:
+            poly[j, 2] = 0.05 * np.eye(N) + sym(0.01)
+    model = LVCModel(name=f"random_poly_{key}_{index}", mass=mass, omega=omega, v0=v0, k=k, poly=poly)
+    init = InitSpec(kT=0.3, q0=np.zeros(M), state=N - 1)
+    seed = (key << 32) | (index & 0xFFFFFFFF)
+    return Workload(model, init, RunSpec(n_traj, n_steps, dt, cadence, seed))
 
 
 def batched_instances(n_instances: int = 256, key: int = 4, **kw) -> List[Workload]:
