@@ -21,7 +21,9 @@ two.  Two further legs are reported in the same line:
   spin_boson  the 3-mode Ohmic spin-boson runs (1e6 walkers, 2000 steps,
            kT 0.2 and 1.0) in both precisions with their population difference;
   convergence  the pyrazine-like and spin-boson (kT 0.2) models at 1e6, 1e7
-           and 1e8 walkers: horizons of agreement and the decay rate.
+           and 1e8 walkers: horizons of agreement and the decay rate;
+  poly     models with higher powers of each mode (state-dependent
+           frequencies, anharmonicity) on the general kernels.
 
 Prints one JSON line.
 
@@ -86,7 +88,8 @@ def time_path(P, torch, model, wl, prec, n_traj, steps, warmup):
     r = wl.run
     ens = P.Ensemble(model, n_traj, prec)
     part = P.Partials(model, n_traj, r.n_out)
-    out = torch.empty((r.n_out, 2, 2, 2, 4), dtype=torch.float64, device="cuda")
+    n = model.n_states
+    out = torch.empty((r.n_out, 2, n, n, 4), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
 
@@ -199,6 +202,32 @@ def spin_boson_leg(P, torch):
                     "fp64": {"value": r.n_traj * r.n_steps / (res["fp64"][0] / 1e3), "ms": res["fp64"][0]},
                     "fp32_vs_fp64_max_abs_population_diff": dpop, "resolved_bins": n_res, "bins": len(se)})
         torch.cuda.empty_cache()
+    return out
+
+
+def poly_leg(P, torch):
+    """Models with higher powers of each mode (general kernels, every
+    coupling direction kept): the pyrazine-like model with state-dependent
+    frequencies and a quartic tuning mode (1e7 walkers, 200 steps of 0.5 fs)
+    and a 3-state, 16-mode quartic model (1e6 walkers, 200 steps), both
+    precisions; walker-steps/s of sample + propagate + reduce and the
+    propagate kernel's own time."""
+    import workloads as W
+    cases = (("pyrazine_qvc", W.pyrazine_qvc(n_traj=10_000_000, n_steps=200, cadence=10)),
+             ("poly_n3_m16_d4", W.random_poly(20, n_states=3, n_modes=16, degree=4, n_traj=1_000_000,
+                                               n_steps=200, cadence=10, dt=0.02)))
+    out = []
+    for name, wl in cases:
+        r = wl.run
+        model = P.Model(wl.model)
+        row = {"model": name, "n_states": model.n_states, "n_modes": model.n_modes, "degree": model.degree,
+               "rank": model.rank, "n_traj": r.n_traj, "n_steps": r.n_steps}
+        for prec in ("fp32", "fp64"):
+            ms_step, ms_prop, _ = time_path(P, torch, model, wl, prec, r.n_traj, 3, 1)
+            row[prec] = {"value": r.n_traj * r.n_steps / (ms_step / 1e3), "ms": ms_step, "propagate_ms": ms_prop,
+                         "flags": dict(time_path.flag_counts)}
+            torch.cuda.empty_cache()
+        out.append(row)
     return out
 
 
@@ -335,7 +364,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling,convergence",
+    ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling,convergence,poly",
                     help="comma-separated subset of headline,spin_boson,batched,served,scaling")
     ap.add_argument("--served-jobs", type=int, default=200)
     ap.add_argument("--served-quantum-work", type=float, default=2e8,
@@ -458,6 +487,10 @@ def main():
         line["scaling_sweep"] = scaling_leg(P, torch, wl)
         print(f"[bench] scaling sweep: " + ", ".join(f"{x['prec']} {x['n_traj']:.0e}: {x['ms']:.1f} ms"
                                                     for x in line["scaling_sweep"]), file=sys.stderr, flush=True)
+    if "poly" in legs:
+        line["poly"] = poly_leg(P, torch)
+        print("[bench] poly: " + "; ".join(f"{x['model']} fp32 {x['fp32']['value']:.3e}, fp64 {x['fp64']['value']:.3e}"
+                                           for x in line["poly"]), file=sys.stderr, flush=True)
     if "convergence" in legs:
         line["convergence"] = convergence_leg(P, torch)
         for key, v in line["convergence"].items():

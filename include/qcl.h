@@ -167,6 +167,33 @@ typedef struct {
  * <= 0, asymmetry), OUT_OF_MEMORY, DEVICE. */
 qcl_status qcl_create_model(const qcl_model_desc *desc, qcl_model *out);
 
+/* Higher separable powers of each mode (beyond the linear-vibronic form;
+ * Eq. 1 holds for any V(R), and the paper's closing section names general
+ * potentials as the next step): the model's potential becomes
+ *   V(q) = V0 + sum_j [ q_j K_j + sum_{k=2..degree} q_j^k A_jk ],
+ * so the adiabatic forces and couplings use
+ *   dV/dq_j = K_j + sum_k k q_j^(k-1) A_jk.
+ * k = 2 gives state-dependent frequencies, k = 3, 4 anharmonicity.  The
+ * Wigner initial state stays that of the harmonic wells (m_j, w_j). */
+typedef struct {
+    int32_t degree;       /* highest power, 2 .. 4 */
+    int32_t reserved;
+    const double *a;      /* host [M][degree-1][N][N] row-major: A_jk for
+                             k = 2..degree, each symmetric to 1e-12 */
+} qcl_poly_desc;
+
+/* As qcl_create_model, with the higher powers of poly (read during the
+ * call only).  Such a model always runs on the general-N kernels (also for
+ * N = 2), with every coupling direction kept (rank padded to N(N+1)/2) and
+ * the default register budget (qcl_prop_desc.occupancy is ignored).
+ * Errors: as qcl_create_model; INVALID_ARG also for degree outside [2, 4],
+ * a NULL poly->a, non-finite or asymmetric A_jk. */
+qcl_status qcl_create_model_poly(const qcl_model_desc *desc, const qcl_poly_desc *poly, qcl_model *out);
+
+/* Highest power of q_j in the model's potential: 1 for a linear-vibronic
+ * model, 2..4 for one built by qcl_create_model_poly, 0 for NULL. */
+int32_t qcl_model_degree(qcl_model model);
+
 /* Frees a model (NULL is accepted).  Work that uses it must be complete. */
 qcl_status qcl_destroy_model(qcl_model model);
 

@@ -1,0 +1,5 @@
+// General-N kernels instantiated for N = 4 states, models with higher
+// separable powers of each mode.
+#define QCL_GEN_N 4
+#define QCL_GEN_POLY 1
+#include "kernels_general.inc"

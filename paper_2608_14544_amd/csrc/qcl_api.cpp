@@ -270,7 +270,7 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
             continue;
         const qcl_model_s &m = *it.model;
         // general kernels are specialised on padded modes and rank bucket
-        const int modes = m.fast2 ? m.m : qcl::padded_modes(m.m) * 64 + m.rank_pad;
+        const int modes = m.fast2 ? m.m : qcl::padded_modes(m.m) * 64 + m.rank_pad + (m.degree > 1 ? 32 : 0);
         BatchClass *c = nullptr;
         const int occ = qcl::occupancy_variant(m, it.ens->prec, it.prop.occupancy);
         for (BatchClass &k : plan.classes)
@@ -322,13 +322,9 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
     return QCL_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *qcl_last_error(void) { return g_last_error.c_str(); }
-
-qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out)
+// Builds a model (linear when poly is NULL); see qcl_create_model and
+// qcl_create_model_poly.
+qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_model *out)
 {
     if (!d || !out)
         return fail(QCL_ERR_INVALID_ARG, "NULL argument");
@@ -353,6 +349,19 @@ qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out)
     for (int j = 0; j < M; ++j)
         if (!symmetric(d->k + (size_t)j * n * n, n))
             return fail(QCL_ERR_INVALID_ARG, "K_%d is not symmetric", j);
+    const int D = poly ? poly->degree : 1;
+    if (poly) {
+        if (D < 2 || D > 4)
+            return fail(QCL_ERR_INVALID_ARG, "poly degree %d outside [2, 4]", D);
+        if (!poly->a)
+            return fail(QCL_ERR_INVALID_ARG, "poly->a is NULL");
+        if (!finite_all(poly->a, (int64_t)M * (D - 1) * n * n))
+            return fail(QCL_ERR_INVALID_ARG, "non-finite higher-power coefficient");
+        for (int j = 0; j < M; ++j)
+            for (int k = 2; k <= D; ++k)
+                if (!symmetric(poly->a + ((size_t)j * (D - 1) + (k - 2)) * n * n, n))
+                    return fail(QCL_ERR_INVALID_ARG, "A_%d,%d is not symmetric", j, k);
+    }
 
     qcl_model_s *m = new (std::nothrow) qcl_model_s();
     if (!m)
@@ -364,16 +373,28 @@ qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out)
     m->omega.assign(d->omega, d->omega + M);
     m->v0.assign(d->v0, d->v0 + n * n);
     m->k.assign(d->k, d->k + (size_t)M * n * n);
-    m->fast2 = (n == 2 && M <= qcl::kMaxFastModes);
+    m->degree = D;
+    if (poly)
+        m->poly.assign(poly->a, poly->a + (size_t)M * (D - 1) * n * n);
+    m->fast2 = (n == 2 && M <= qcl::kMaxFastModes && D == 1);
     // energy scale: |V0| plus each mode's coupling over its zero-point-ish length
     double scale = 0.0;
     for (int i = 0; i < n * n; ++i)
         scale += std::fabs(m->v0[i]);
     for (int j = 0; j < M; ++j) {
+        const double len = 1.0 / (m->omega[j] * std::sqrt(m->mass[j]));
         double kj = 0.0;
         for (int i = 0; i < n * n; ++i)
             kj += std::fabs(m->k[(size_t)j * n * n + i]);
-        scale += kj / (m->omega[j] * std::sqrt(m->mass[j]));
+        scale += kj * len;
+        double lk = len;
+        for (int k = 2; k <= D; ++k) {
+            lk *= len;
+            double ak = 0.0;
+            for (int i = 0; i < n * n; ++i)
+                ak += std::fabs(m->poly[((size_t)j * (D - 1) + (k - 2)) * n * n + i]);
+            scale += ak * lk;
+        }
     }
     m->energy_scale = scale > 0.0 ? scale : 1.0;
     // two-state constants (closed-form kernels)
@@ -411,29 +432,62 @@ qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out)
     }
     // general-N tables (factored couplings), binary64 then binary32
     const int T = n * (n + 1) / 2;
-    std::vector<double> kmat((size_t)M * T), basis, coef;
-    for (int j = 0; j < M; ++j)
-        for (int k = 0, s = 0; k < n; ++k)
-            for (int l = k; l < n; ++l, ++s)
-                kmat[(size_t)j * T + s] = m->k[(size_t)j * n * n + k * n + l];
-    m->rank = factor_couplings(M, T, kmat, basis, coef);
-    m->rank_pad = qcl::rank_bucket(m->rank, n);
-    const int RB = m->rank_pad;
-    std::vector<double> gen;
+    std::vector<double> basis, coef, gen;
     for (int k = 0; k < n; ++k)
         for (int l = k; l < n; ++l)
             gen.push_back(m->v0[k * n + l]);
-    for (int r = 0; r < RB; ++r)
-        for (int s = 0; s < T; ++s)
-            gen.push_back(r < m->rank ? basis[(size_t)r * T + s] : 0.0);
-    for (int j = 0; j < qcl::kMaxModesPad; ++j) {
-        const bool real = j < M;
-        gen.push_back(real ? m->mass[j] * m->omega[j] * m->omega[j] : 0.0);
-        gen.push_back(real ? 1.0 / m->mass[j] : 0.0);
+    if (D == 1) {
+        std::vector<double> kmat((size_t)M * T);
+        for (int j = 0; j < M; ++j)
+            for (int k = 0, s = 0; k < n; ++k)
+                for (int l = k; l < n; ++l, ++s)
+                    kmat[(size_t)j * T + s] = m->k[(size_t)j * n * n + k * n + l];
+        m->rank = factor_couplings(M, T, kmat, basis, coef);
+        m->rank_pad = qcl::rank_bucket(m->rank, n);
+        const int RB = m->rank_pad;
         for (int r = 0; r < RB; ++r)
-            gen.push_back(real && r < m->rank ? coef[(size_t)j * m->rank + r] : 0.0);
+            for (int s = 0; s < T; ++s)
+                gen.push_back(r < m->rank ? basis[(size_t)r * T + s] : 0.0);
+        for (int j = 0; j < qcl::kMaxModesPad; ++j) {
+            const bool real = j < M;
+            gen.push_back(real ? m->mass[j] * m->omega[j] * m->omega[j] : 0.0);
+            gen.push_back(real ? 1.0 / m->mass[j] : 0.0);
+            for (int r = 0; r < RB; ++r)
+                gen.push_back(real && r < m->rank ? coef[(size_t)j * m->rank + r] : 0.0);
+            for (int r = 0; r < RB; ++r)
+                gen.push_back(real && r < m->rank ? coef[(size_t)j * m->rank + r] / m->mass[j] : 0.0);
+        }
+    } else {
+        // rows (j, k), k = 1..4: A_j1 = K_j, A_jk from poly, zero past the degree
+        std::vector<double> amat((size_t)M * 4 * T, 0.0);
+        for (int j = 0; j < M; ++j)
+            for (int k = 1; k <= D; ++k) {
+                const double *A = k == 1 ? &m->k[(size_t)j * n * n]
+                                         : &m->poly[((size_t)j * (D - 1) + (k - 2)) * n * n];
+                for (int a = 0, s = 0; a < n; ++a)
+                    for (int b = a; b < n; ++b, ++s)
+                        amat[((size_t)j * 4 + (k - 1)) * T + s] = A[a * n + b];
+            }
+        m->rank = factor_couplings(M * 4, T, amat, basis, coef);
+        m->rank_pad = T;
+        const int RB = T;
         for (int r = 0; r < RB; ++r)
-            gen.push_back(real && r < m->rank ? coef[(size_t)j * m->rank + r] / m->mass[j] : 0.0);
+            for (int s = 0; s < T; ++s)
+                gen.push_back(r < m->rank ? basis[(size_t)r * T + s] : 0.0);
+        for (int j = 0; j < qcl::kMaxModesPad; ++j) {
+            const bool real = j < M;
+            gen.push_back(real ? m->mass[j] * m->omega[j] * m->omega[j] : 0.0);
+            gen.push_back(real ? 1.0 / m->mass[j] : 0.0);
+            for (int r = 0; r < RB; ++r) {
+                double c[4];
+                for (int k = 0; k < 4; ++k)
+                    c[k] = real && r < m->rank ? coef[((size_t)j * 4 + k) * m->rank + r] : 0.0;
+                for (int k = 0; k < 4; ++k)
+                    gen.push_back(c[k]);
+                for (int k = 0; k < 4; ++k)
+                    gen.push_back((k + 1) * c[k]);
+            }
+        }
     }
     while (packed.size() % 32)
         packed.push_back(0.0);
@@ -463,6 +517,26 @@ qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out)
     *out = m;
     return QCL_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+const char *qcl_last_error(void) { return g_last_error.c_str(); }
+
+qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out) { return create_model(d, nullptr, out); }
+
+qcl_status qcl_create_model_poly(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_model *out)
+{
+    if (!poly) {
+        if (out)
+            *out = nullptr;
+        return fail(QCL_ERR_INVALID_ARG, "poly is NULL");
+    }
+    return create_model(d, poly, out);
+}
+
+int32_t qcl_model_degree(qcl_model m) { return m ? m->degree : 0; }
 
 qcl_status qcl_destroy_model(qcl_model m)
 {

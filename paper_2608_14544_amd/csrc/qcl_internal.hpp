@@ -53,6 +53,12 @@ struct N2Const {
 //   basis [RB][T]                    B_r
 //   modes [kMaxModesPad][2 + 2 RB]   m w^2, 1/m, C_j0..C_j(RB-1), C_jr/m_j
 // zero-padded past the model's modes so that padded modes stay at rest.
+// A model with higher powers (V(q) = V0 + sum_j sum_{k=1..4} q_j^k A_jk,
+// A_j1 = K_j) factors all its A_jk over one basis, A_jk = sum_r C_jkr B_r,
+// with RB = T, and its mode rows hold per direction r the coefficients of
+// phi_jr(x) = sum_k C_jkr x^k and of its derivative:
+//   modes [kMaxModesPad][2 + 8 RB]   m w^2, 1/m, then per r:
+//                                    C_j1r..C_j4r, 1 C_j1r, 2 C_j2r, 3 C_j3r, 4 C_j4r
 constexpr int kMaxModesPad = 128;
 
 template <typename R>
@@ -148,7 +154,9 @@ struct qcl_model_s {
     size_t gen32_byte_offset = 0;  // byte offset of the general-N binary32 constants
     int32_t rank = 0;           // rank of the mode couplings (general-N factorisation)
     int32_t rank_pad = 1;       // rank bucket RB the general kernels are specialised on
-    bool fast2 = false;         // two-state closed-form kernels apply (N = 2, M <= 8)
+    int32_t degree = 1;         // highest power of q_j in V(q) (> 1: kernels_poly{N}.hip)
+    std::vector<double> poly;   // [M][degree-1][N][N] higher-power matrices A_jk (k >= 2)
+    bool fast2 = false;         // two-state closed-form kernels apply (N = 2, M <= 8, linear)
 };
 
 namespace qcl {
@@ -158,33 +166,48 @@ hipError_t launch_sample_n2(const qcl_model_s &m, const SampleArgs &sa, const qc
 hipError_t launch_propagate_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
                                double *partials, hipStream_t stream);
 template <int K>
-struct int_ {};
-// one definition per state count (kernels_gen{2,3,4}.hip)
-hipError_t launch_sample_general_n(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,
-                                   double *partials, int32_t n_out, hipStream_t s, int_<2>);
-hipError_t launch_sample_general_n(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,
-                                   double *partials, int32_t n_out, hipStream_t s, int_<3>);
-hipError_t launch_sample_general_n(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,
-                                   double *partials, int32_t n_out, hipStream_t s, int_<4>);
-hipError_t launch_propagate_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
-                                      double *partials, hipStream_t s, int_<2>);
-hipError_t launch_propagate_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
-                                      double *partials, hipStream_t s, int_<3>);
-hipError_t launch_propagate_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
-                                      double *partials, hipStream_t s, int_<4>);
+struct int_ {};  // general kernels of K states, linear couplings (kernels_gen{K}.hip)
+template <int K>
+struct poly_ {};  // general kernels of K states, higher powers (kernels_poly{K}.hip)
 
-size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
-                            double *partials, int64_t tile_begin, void *out, int_<2>);
-size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
-                            double *partials, int64_t tile_begin, void *out, int_<3>);
-size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
-                            double *partials, int64_t tile_begin, void *out, int_<4>);
-hipError_t launch_batch_general_n(int mp, int rb, int prec, int occ, const void *items, int32_t n_items,
-                                  int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<2>);
-hipError_t launch_batch_general_n(int mp, int rb, int prec, int occ, const void *items, int32_t n_items,
-                                  int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<3>);
-hipError_t launch_batch_general_n(int mp, int rb, int prec, int occ, const void *items, int32_t n_items,
-                                  int64_t total_tiles, unsigned long long *counter, hipStream_t s, int_<4>);
+#define QCL_DECLARE_GENERAL(TAG)                                                                              \
+    hipError_t launch_sample_general_n(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,   \
+                                       double *partials, int32_t n_out, hipStream_t s, TAG);                 \
+    hipError_t launch_propagate_general_n(const qcl_model_s &m, const qcl_ensemble &ens,                     \
+                                          const qcl_prop_desc &pd, double *partials, hipStream_t s, TAG);    \
+    size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,      \
+                                double *partials, int64_t tile_begin, void *out, TAG);                       \
+    hipError_t launch_batch_general_n(int mp, int rb, int prec, int occ, const void *items, int32_t n_items, \
+                                      int64_t total_tiles, unsigned long long *counter, hipStream_t s, TAG);
+QCL_DECLARE_GENERAL(int_<2>)
+QCL_DECLARE_GENERAL(int_<3>)
+QCL_DECLARE_GENERAL(int_<4>)
+QCL_DECLARE_GENERAL(poly_<2>)
+QCL_DECLARE_GENERAL(poly_<3>)
+QCL_DECLARE_GENERAL(poly_<4>)
+#undef QCL_DECLARE_GENERAL
+
+// Calls fn with the tag of the general kernels a model runs on; `none` when
+// the state count has none (never, for a validated model).
+template <typename Ret, typename F>
+inline Ret with_general(const qcl_model_s &m, Ret none, F &&fn)
+{
+    if (m.degree > 1) {
+        switch (m.n) {
+        case 2: return fn(poly_<2>{});
+        case 3: return fn(poly_<3>{});
+        case 4: return fn(poly_<4>{});
+        default: return none;
+        }
+    }
+    switch (m.n) {
+    case 2: return fn(int_<2>{});
+    case 3: return fn(int_<3>{});
+    case 4: return fn(int_<4>{});
+    default: return none;
+    }
+}
+
 size_t batch_item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
                      int64_t tile_begin, void *out);
 hipError_t launch_batch_n2(int modes, int prec, int scheme, const void *items, int32_t n_items, int64_t total_tiles,
@@ -198,20 +221,17 @@ inline size_t batch_item(const qcl_model_s &m, const qcl_ensemble &ens, const qc
 {
     if (m.fast2)
         return batch_item_n2(m, ens, pd, partials, tile_begin, out);
-    switch (m.n) {
-    case 2: return batch_item_general_n(m, ens, pd, partials, tile_begin, out, int_<2>{});
-    case 3: return batch_item_general_n(m, ens, pd, partials, tile_begin, out, int_<3>{});
-    case 4: return batch_item_general_n(m, ens, pd, partials, tile_begin, out, int_<4>{});
-    default: return 0;
-    }
+    return with_general(m, size_t(0),
+                        [&](auto tag) { return batch_item_general_n(m, ens, pd, partials, tile_begin, out, tag); });
 }
 
 // The register-budget variant a call runs: 3 where such kernels exist
-// (binary32, general kernels, at most 32 padded modes) and it was asked
-// for, else 0.
+// (binary32, general kernels of a linear model, at most 32 padded modes)
+// and it was asked for, else 0.
 inline int occupancy_variant(const qcl_model_s &m, int prec, int requested)
 {
-    return (requested == 3 && !m.fast2 && prec == QCL_FP32_ACC64 && padded_modes(m.m) <= 32) ? 3 : 0;
+    return (requested == 3 && !m.fast2 && m.degree == 1 && prec == QCL_FP32_ACC64 && padded_modes(m.m) <= 32) ? 3
+                                                                                                              : 0;
 }
 
 inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, int occ, const void *items,
@@ -220,34 +240,23 @@ inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, int o
     if (m.fast2)  // the transition rule is a template parameter of the two-state kernels
         return launch_batch_n2(m.m, prec, scheme, items, n_items, total_tiles, counter, s);
     const int mp = padded_modes(m.m), rb = m.rank_pad;
-    switch (m.n) {
-    case 2: return launch_batch_general_n(mp, rb, prec, occ, items, n_items, total_tiles, counter, s, int_<2>{});
-    case 3: return launch_batch_general_n(mp, rb, prec, occ, items, n_items, total_tiles, counter, s, int_<3>{});
-    case 4: return launch_batch_general_n(mp, rb, prec, occ, items, n_items, total_tiles, counter, s, int_<4>{});
-    default: return hipErrorNotSupported;
-    }
+    return with_general(m, hipErrorNotSupported, [&](auto tag) {
+        return launch_batch_general_n(mp, rb, prec, occ, items, n_items, total_tiles, counter, s, tag);
+    });
 }
 
 inline hipError_t launch_sample_general(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,
                                         double *partials, int32_t n_out, hipStream_t s)
 {
-    switch (m.n) {
-    case 2: return launch_sample_general_n(m, sa, ens, partials, n_out, s, int_<2>{});
-    case 3: return launch_sample_general_n(m, sa, ens, partials, n_out, s, int_<3>{});
-    case 4: return launch_sample_general_n(m, sa, ens, partials, n_out, s, int_<4>{});
-    default: return hipErrorNotSupported;
-    }
+    return with_general(m, hipErrorNotSupported,
+                        [&](auto tag) { return launch_sample_general_n(m, sa, ens, partials, n_out, s, tag); });
 }
 
 inline hipError_t launch_propagate_general(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
                                            double *partials, hipStream_t s)
 {
-    switch (m.n) {
-    case 2: return launch_propagate_general_n(m, ens, pd, partials, s, int_<2>{});
-    case 3: return launch_propagate_general_n(m, ens, pd, partials, s, int_<3>{});
-    case 4: return launch_propagate_general_n(m, ens, pd, partials, s, int_<4>{});
-    default: return hipErrorNotSupported;
-    }
+    return with_general(m, hipErrorNotSupported,
+                        [&](auto tag) { return launch_propagate_general_n(m, ens, pd, partials, s, tag); });
 }
 hipError_t launch_reduce(int n_states, double *partials, int64_t n_traj, int32_t n_out, double *out,
                          hipStream_t stream);

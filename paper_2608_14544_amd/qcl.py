@@ -52,6 +52,10 @@ class qcl_model_desc(C.Structure):
                 ("hbar", C.c_double)]
 
 
+class qcl_poly_desc(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("reserved", C.c_int32), ("a", C.POINTER(C.c_double))]
+
+
 class qcl_init_desc(C.Structure):
     _fields_ = [("kT", C.c_double), ("q0", C.POINTER(C.c_double)),
                 ("state", C.c_int32), ("basis", C.c_int32)]
@@ -76,7 +80,8 @@ class qcl_batch_item(C.Structure):
                 ("partials", C.c_void_p)]
 
 
-EXPORTS = ("qcl_create_model", "qcl_destroy_model", "qcl_model_states", "qcl_model_modes", "qcl_model_rank",
+EXPORTS = ("qcl_create_model", "qcl_create_model_poly", "qcl_destroy_model", "qcl_model_states",
+           "qcl_model_modes", "qcl_model_rank", "qcl_model_degree",
            "qcl_ensemble_bytes", "qcl_ensemble_bind", "qcl_partials_bytes",
            "qcl_sample_initial", "qcl_propagate", "qcl_batch_workspace_bytes", "qcl_propagate_batch",
            "qcl_reduce_observables", "qcl_last_error")
@@ -96,6 +101,9 @@ def load_library(path: str = LIB_PATH):
         L = C.CDLL(path)
         vp, i32, i64, u64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
         L.qcl_create_model.argtypes = [C.POINTER(qcl_model_desc), C.POINTER(vp)]
+        L.qcl_create_model_poly.argtypes = [C.POINTER(qcl_model_desc), C.POINTER(qcl_poly_desc), C.POINTER(vp)]
+        L.qcl_model_degree.argtypes = [vp]
+        L.qcl_model_degree.restype = i32
         L.qcl_destroy_model.argtypes = [vp]
         L.qcl_model_states.argtypes = [vp]
         L.qcl_model_states.restype = i32
@@ -155,11 +163,19 @@ class Model:
         desc = qcl_model_desc(int(v0.shape[0]), int(mass.shape[0]), _dptr(mass), _dptr(omega),
                               _dptr(v0), _dptr(k), float(lvc.hbar))
         h = C.c_void_p()
-        _check(L.qcl_create_model(C.byref(desc), C.byref(h)))
+        poly = getattr(lvc, "poly", None)
+        if poly is None:
+            _check(L.qcl_create_model(C.byref(desc), C.byref(h)))
+        else:
+            a = np.ascontiguousarray(poly, np.float64)
+            self._arrays.append(a)
+            pd = qcl_poly_desc(int(a.shape[1]) + 1, 0, _dptr(a))
+            _check(L.qcl_create_model_poly(C.byref(desc), C.byref(pd), C.byref(h)))
         self.handle = h
         self.n_states = int(L.qcl_model_states(h))
         self.n_modes = int(L.qcl_model_modes(h))
         self.rank = int(L.qcl_model_rank(h))
+        self.degree = int(L.qcl_model_degree(h))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -59,6 +59,8 @@ class TuningTable:
             self.load(path)
 
     def key(self, model: "Q.Model", prec: str) -> Optional[Key]:
+        if getattr(model, "degree", 1) > 1:  # one build only for models with higher powers
+            return None
         return kernel_class(model.n_states, model.n_modes, model.rank, prec)
 
     def occupancy(self, model: "Q.Model", prec: str) -> int:

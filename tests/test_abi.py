@@ -69,6 +69,28 @@ def test_create_model_rejects_invalid(case):
     assert L.qcl_last_error()
 
 
+@pytest.mark.parametrize("degree,patch", [
+    (1, None), (5, None), (2, "asym"), (3, "nan"), (2, "null"),
+])
+def test_create_model_poly_rejects_invalid(degree, patch):
+    qcl, L = _lib()
+    lvc = W.pyrazine_qvc().model
+    d, keep = _desc(qcl, lvc)
+    a = np.zeros((lvc.n_modes, max(degree, 2) - 1, 2, 2))
+    if patch == "asym":
+        a[1, 0, 0, 1] = 0.1
+    if patch == "nan":
+        a[2, 1, 1, 1] = np.nan
+    pd = qcl.qcl_poly_desc(degree, 0, None if patch == "null" else a.ctypes.data_as(C.POINTER(C.c_double)))
+    h = C.c_void_p()
+    st = L.qcl_create_model_poly(C.byref(d), C.byref(pd), C.byref(h))
+    assert st == qcl.QCL_ERR_INVALID_ARG, (degree, patch, st, L.qcl_last_error())
+    assert not h.value
+    assert L.qcl_last_error()
+    assert L.qcl_create_model_poly(C.byref(d), None, C.byref(h)) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_model_degree(None) == 0
+
+
 def test_null_arguments_rejected():
     qcl, L = _lib()
     assert L.qcl_create_model(None, None) == qcl.QCL_ERR_INVALID_ARG

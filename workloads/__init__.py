@@ -273,10 +273,10 @@ def random_poly(index: int, n_states: int = 3, n_modes: int = 5, degree: int = 4
     v0 = np.diag(bias) + sym(0.1) * (1.0 - np.eye(N))
     omega = rng.uniform(0.5, 1.5, size=M)
     mass = rng.uniform(0.7, 1.4, size=M)
-    k = np.stack([sym(0.3) if rank_full else 0.3 * rng.uniform(-1, 1) * _z_diag(N) for _ in range(M)])
+    k = np.stack([sym(0.15) if rank_full else 0.15 * rng.uniform(-1, 1) * _z_diag(N) for _ in range(M)])
     poly = np.zeros((M, degree - 1, N, N))
     for j in range(M):
-        poly[j, 0] = sym(0.1 * mass[j] * omega[j] ** 2)
+        poly[j, 0] = sym(0.05 * mass[j] * omega[j] ** 2)
         if degree >= 3:
             poly[j, 1] = sym(0.02)
         if degree >= 4:
