@@ -266,7 +266,7 @@ def batched_leg(P, torch, n_instances=256):
             "value": tot / (ms / 1e3), "unit": "trajectory-steps/s", "walker_steps": tot,
             "ms": ms, "wall_ms": wall * 1e3,
             "autotune": {"classes": len(table.choice), "capped_register_budget": sum(
-                1 for v in table.choice.values() if v == 3), "seconds": tune_s}}, table
+                1 for v in table.choice.values() if v != 0), "seconds": tune_s}}, table
 
 
 def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=None, quantum_work=2e8):

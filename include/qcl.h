@@ -153,8 +153,10 @@ typedef struct {
     int32_t occupancy;    /* register budget of the general kernels: 0 = the
                              compiler's choice; 3 = at most a third of the
                              register file per wave (3 waves per SIMD), for
-                             binary32 ensembles of models with N > 2 or M > 8
-                             and at most 32 modes (other models ignore it).
+                             binary32 ensembles of linear models with N > 2
+                             or M > 8 and at most 32 modes; 2 = at most half
+                             of it (2 waves per SIMD) for such models with
+                             33..64 modes (other models ignore both).
                              The result is bitwise the same either way; the
                              faster choice depends on the model (see the
                              tuner in the Python package). */

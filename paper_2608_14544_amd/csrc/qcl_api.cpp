@@ -181,8 +181,8 @@ qcl_status check_propagate(qcl_model m, const qcl_ensemble *ens, const qcl_prop_
         return fail(QCL_ERR_INVALID_ARG, "n_steps >= 0, cadence >= 1 and n_out >= 1 required");
     if (pd->scheme != QCL_TRANS_NORMALIZED && pd->scheme != QCL_TRANS_LINEAR)
         return fail(QCL_ERR_INVALID_ARG, "unknown transition scheme %d", pd->scheme);
-    if (pd->occupancy != 0 && pd->occupancy != 3)
-        return fail(QCL_ERR_INVALID_ARG, "occupancy must be 0 or 3");
+    if (pd->occupancy != 0 && pd->occupancy != 2 && pd->occupancy != 3)
+        return fail(QCL_ERR_INVALID_ARG, "occupancy must be 0, 2 or 3");
     const int64_t last_bin = (ens->step + pd->n_steps) / pd->cadence;
     if (last_bin >= pd->n_out)
         return fail(QCL_ERR_INVALID_ARG, "bin %lld would be written but n_out is %d", (long long)last_bin,

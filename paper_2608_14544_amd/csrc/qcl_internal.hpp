@@ -225,13 +225,19 @@ inline size_t batch_item(const qcl_model_s &m, const qcl_ensemble &ens, const qc
                         [&](auto tag) { return batch_item_general_n(m, ens, pd, partials, tile_begin, out, tag); });
 }
 
-// The register-budget variant a call runs: 3 where such kernels exist
-// (binary32, general kernels of a linear model, at most 32 padded modes)
-// and it was asked for, else 0.
+// The register-budget variant a call runs: the one asked for where such
+// kernels exist (binary32, general kernels of a linear model; 3 with at most
+// 32 padded modes, 2 with 64), else 0.
 inline int occupancy_variant(const qcl_model_s &m, int prec, int requested)
 {
-    return (requested == 3 && !m.fast2 && m.degree == 1 && prec == QCL_FP32_ACC64 && padded_modes(m.m) <= 32) ? 3
-                                                                                                              : 0;
+    if (m.fast2 || m.degree != 1 || prec != QCL_FP32_ACC64)
+        return 0;
+    const int mp = padded_modes(m.m);
+    if (requested == 3 && mp <= 32)
+        return 3;
+    if (requested == 2 && mp == 64)
+        return 2;
+    return 0;
 }
 
 inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, int occ, const void *items,

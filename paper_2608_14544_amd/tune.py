@@ -1,10 +1,11 @@
 """Autotuner for the general kernels' register budget.
 
-The general kernels (N > 2, or N = 2 with M > 8) exist in binary32 for at
-most 32 padded modes in two builds of the same code: one where the compiler
-chooses the register count (often 150-240 registers, two or three waves per
-SIMD) and one limited to a third of the register file (three waves per
-SIMD, some values kept in the accumulation registers instead).  Which one is
+The general kernels of linear models (N > 2, or N = 2 with M > 8) exist in
+binary32 in two builds of the same code: one where the compiler chooses
+the register count (often 150-240 registers, two or three waves per SIMD;
+at 64 modes all 256 and some accumulation registers, one wave), and one
+with a register budget: a third of the register file (three waves per
+SIMD) up to 32 padded modes, half of it (two waves) at 64.  Which one is
 faster depends on the kernel class -- more resident waves hide the step's
 long dependency chains, the cap can force spills -- so it is measured.  The
 arithmetic is identical: the choice never changes a result bit.
@@ -25,7 +26,12 @@ from typing import Dict, Iterable, Optional, Tuple
 from . import qcl as Q
 
 Key = Tuple[int, int, int, str]
-VARIANTS = (0, 3)
+VARIANTS = (0, 2, 3)
+
+
+def budget_variant(mp: int) -> int:
+    """The register-budget build that exists for ``mp`` padded modes."""
+    return 3 if mp <= 32 else 2
 
 
 def padded_modes(m: int) -> int:
@@ -42,11 +48,11 @@ def rank_bucket(rank: int, n: int) -> int:
 
 def kernel_class(n_states: int, n_modes: int, rank: int, prec: str) -> Optional[Key]:
     """The tunable kernel class of a model, or None when only one build
-    exists (two-state closed form, binary64, more than 32 padded modes)."""
+    exists (two-state closed form, binary64, more than 64 padded modes)."""
     if n_states == 2 and n_modes <= 8:
         return None
     mp = padded_modes(n_modes)
-    if prec != "fp32" or mp > 32:
+    if prec != "fp32" or mp > 64:
         return None
     return (n_states, mp, rank_bucket(rank, n_states), prec)
 
@@ -98,16 +104,17 @@ class TuningTable:
         ens = Q.Ensemble(model, n_traj, prec, zero=False)
         part = Q.Partials(model, n_traj, 2 * (n_steps // r.cadence) + 4)
         Q.qcl_sample_initial(model, workload.init, r.seed, ens, part)
+        alt = budget_variant(k[1])
         times = {}
-        for occ in VARIANTS:  # warm both builds first
+        for occ in (0, alt):  # warm both builds first
             Q.qcl_propagate(model, ens, r.dt, r.cadence, r.cadence, r.seed, part, occupancy=occ)
         torch.cuda.synchronize()
-        for occ in VARIANTS:
+        for occ in (0, alt):
             t0 = time.perf_counter()
             Q.qcl_propagate(model, ens, r.dt, n_steps // 2, r.cadence, r.seed, part, occupancy=occ)
             torch.cuda.synchronize()
             times[occ] = (time.perf_counter() - t0) * 1e3
-        best = 3 if times[3] < (1.0 - min_gain) * times[0] else 0
+        best = alt if times[alt] < (1.0 - min_gain) * times[0] else 0
         self.choice[k] = best
         self.timings[k] = times
         del ens, part

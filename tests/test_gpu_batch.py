@@ -120,27 +120,30 @@ def test_batch_rejects_shared_ensemble(P):
     assert ens.step == 0
 
 
-def test_register_budget_variants_bitwise(P):
-    """The capped-register build of a general kernel gives the same bits,
-    alone and batched; the tuner picks one of the two builds."""
+@pytest.mark.parametrize("n_states,n_modes,budget", [(3, 20, 3), (4, 50, 2), (2, 40, 2)])
+def test_register_budget_variants_bitwise(P, n_states, n_modes, budget):
+    """The register-budget build of a general kernel (3 waves per SIMD up to
+    32 padded modes, 2 at 64) gives the same bits, alone and batched; the
+    tuner picks one of the two builds."""
     import torch
     from paper_2608_14544_amd.tune import TuningTable
-    wl = W.random_lvc(12, n_states=3, n_modes=20, n_traj=1500, n_steps=60, cadence=20)
+    wl = W.random_lvc(12 + n_modes, n_states=n_states, n_modes=n_modes, n_traj=1500, n_steps=60, cadence=20)
     r = wl.run
     outs = []
-    for occ in (0, 3):
+    for occ in (0, budget):
         model, ens, part = _setup(P, wl, "fp32", r.n_traj)
         P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part, occupancy=occ)
         outs.append((P.qcl_reduce_observables(model, part, r.n_traj).cpu().numpy(), ens.to_numpy()))
     model, ens, part = _setup(P, wl, "fp32", r.n_traj)
-    P.qcl_propagate_batch([P.BatchJob(model, ens, part, r.dt, r.n_steps, r.cadence, r.seed, occupancy=3)])
+    P.qcl_propagate_batch([P.BatchJob(model, ens, part, r.dt, r.n_steps, r.cadence, r.seed, occupancy=budget)])
     outs.append((P.qcl_reduce_observables(model, part, r.n_traj).cpu().numpy(), ens.to_numpy()))
     torch.cuda.synchronize()
-    _assert_same(outs[0], outs[1], "occupancy 3")
-    _assert_same(outs[0], outs[2], "batched occupancy 3")
+    _assert_same(outs[0], outs[1], f"occupancy {budget}")
+    _assert_same(outs[0], outs[2], f"batched occupancy {budget}")
     t = TuningTable()
     choice = t.tune(wl, "fp32", n_traj=1 << 16, n_steps=20)
-    assert choice in (0, 3) and t.occupancy(P.Model(wl.model), "fp32") == choice
+    print("tuned", n_states, n_modes, t.timings, flush=True)
+    assert choice in (0, budget) and t.occupancy(P.Model(wl.model), "fp32") == choice
 
 
 def test_batched_workload_full_size():

@@ -122,12 +122,14 @@ def test_tuning_classes_and_table_roundtrip(tmp_path):
     assert padded_modes(1) == 8 and padded_modes(9) == 16 and padded_modes(33) == 64 and padded_modes(100) == 128
     assert rank_bucket(0, 3) == 1 and rank_bucket(2, 3) == 3 and rank_bucket(4, 3) == 6
     assert kernel_class(2, 8, 3, "fp32") is None           # closed-form two-state kernels
-    assert kernel_class(3, 40, 1, "fp32") is None          # no capped build above 32 modes
+    assert kernel_class(3, 40, 1, "fp32") == (3, 64, 1, "fp32")  # two-wave budget at 64 modes
+    assert kernel_class(3, 100, 1, "fp32") is None         # no budget build above 64 modes
     assert kernel_class(4, 20, 1, "fp64") is None          # binary32 only
     assert kernel_class(4, 20, 2, "fp32") == (4, 32, 4, "fp32")
     t = TuningTable()
     t.choice[(4, 32, 4, "fp32")] = 3
     t.choice[(3, 16, 1, "fp32")] = 0
+    t.choice[(2, 64, 1, "fp32")] = 2
     path = str(tmp_path / "tuning.json")
     t.save(path)
     u = TuningTable(path)
