@@ -106,3 +106,47 @@ def test_poly_large_mode_buckets(P, n_states, n_modes):
     nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.01, label=f"poly N{n_states} M{n_modes}")
     if nflip == 0:
         assert ensemble_close(out_g, out_o, wl.run.n_traj)
+
+
+def test_poly_bench_configuration_full_size(P):
+    """The bench's polynomial workload at full size (pyrazine_qvc, 1e7
+    walkers, 200 steps, one launch): binary64 walkers sampled across the
+    ensemble recomputed one by one by the oracle, and the binary32 run's
+    populations within 2e-3 of the binary64 run's while resolved."""
+    import torch
+    import oracle.core as oc
+    from test_gpu_parity import _oracle_state
+    wl = W.pyrazine_qvc(n_traj=10_000_000, n_steps=200, cadence=10)
+    r = wl.run
+    model = P.Model(wl.model)
+    outs = {}
+    for prec in ("fp64", "fp32"):
+        ens = P.Ensemble(model, r.n_traj, prec, zero=False)
+        part = P.Partials(model, r.n_traj, r.n_out)
+        P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
+        P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part)
+        outs[prec] = P.qcl_reduce_observables(model, part, r.n_traj).cpu().numpy()
+        if prec == "fp64":
+            t = ens.tensors()
+            ids = np.array([0, 255, 256, 1 << 20, 5_555_555, r.n_traj - 1])
+            g = {"q": t["q"][:, ids].cpu().numpy().T, "p": t["p"][:, ids].cpu().numpy().T,
+                 "U": t["u"][:, ids].cpu().numpy().T.reshape(-1, 2, 2), "w": t["w"][ids].cpu().numpy(),
+                 "phase": t["phase"][ids].cpu().numpy(), "a": t["a"][ids].cpu().numpy().astype(np.int32),
+                 "b": t["b"][ids].cpu().numpy().astype(np.int32)}
+        del ens, part
+        torch.cuda.empty_cache()
+    m = oc.Model(wl.model)
+    o = {k: [] for k in g}
+    for i in ids:
+        st, _ = oc.sample(m, wl.init, r.seed, 1, traj_offset=int(i))
+        oc.propagate(m, st, r.dt, r.n_steps, r.cadence, r.seed, r.n_out)
+        for k, v in _oracle_state(st).items():
+            o[k].append(v[0])
+    o = {k: np.array(v) for k, v in o.items()}
+    compare_walkers(g, o, rtol=1e-8, max_flip_frac=0.2, label="pyrazine_qvc 1e7 sampled")
+    o64, o32 = outs["fp64"], outs["fp32"]
+    se = np.max(np.stack([o64[:, 0, i, i, 2] for i in range(2)]), axis=0)
+    res = int(np.argmax(~(se < 0.01))) if np.any(~(se < 0.01)) else len(se)
+    d = max(float(np.abs(o32[:res, 0, i, i, 0] - o64[:res, 0, i, i, 0]).max()) for i in range(2))
+    print("fp32 vs fp64 population diff", d, "over", res, "resolved bins", flush=True)
+    assert res >= 3 and d <= 2e-3
