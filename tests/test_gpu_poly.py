@@ -150,3 +150,29 @@ def test_poly_bench_configuration_full_size(P):
     d = max(float(np.abs(o32[:res, 0, i, i, 0] - o64[:res, 0, i, i, 0]).max()) for i in range(2))
     print("fp32 vs fp64 population diff", d, "over", res, "resolved bins", flush=True)
     assert res >= 3 and d <= 2e-3
+
+
+@pytest.mark.parametrize("T", [0, 1, 255, 257])
+def test_poly_empty_and_ragged(P, T):
+    wl = W.random_poly(30, n_states=3, n_modes=5, degree=4, n_traj=T, n_steps=40, cadence=7)
+    out_g, st_g, _, _ = gpu_run(P, wl)
+    if T == 0:
+        assert out_g is None and st_g["w"].size == 0
+        return
+    out_o, st_o, _, _ = oracle_run(wl)
+    compare_walkers(st_g, st_o, rtol=1e-9, label=f"poly T={T}")
+    assert ensemble_close(out_g, out_o, T)
+
+
+def test_poly_largest_bucket_n4_m128(P):
+    """Four states, 128 modes, quartic: the largest polynomial class (its
+    binary64 build spills to scratch), against the oracle, both precisions."""
+    wl = W.random_poly(31, n_states=4, n_modes=128, degree=4, n_traj=256, n_steps=20, cadence=10,
+                       rank_full=False)
+    out_g, st_g, _, _ = gpu_run(P, wl)
+    out_o, st_o, _, _ = oracle_run(wl)
+    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.02, label="poly N4 M128")
+    if nflip == 0:
+        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    out32, st32, _, _ = gpu_run(P, wl, prec="fp32")
+    assert np.all(np.isfinite(st32["w"])) and np.all(np.isfinite(out32))
