@@ -47,7 +47,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define OR_MAXN 4
+#define OR_MAXN 8
 #define OR_MAXM 128
 #define OR_CHUNK 1024
 

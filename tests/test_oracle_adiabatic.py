@@ -14,7 +14,7 @@ import scipy.linalg as sl
 import workloads as W
 
 
-@pytest.mark.parametrize("n", [2, 3, 4])
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7, 8])
 def test_jacobi_vs_lapack(oracle_lib, n):
     oc = oracle_lib
     rng = np.random.default_rng(n)
@@ -57,7 +57,8 @@ def test_gauge_conventions(oracle_lib):
 
 
 @pytest.mark.parametrize("wl", [W.pyrazine_ci(), W.spin_boson_ohmic(), W.random_lvc(3, n_states=3, n_modes=4),
-                                W.random_lvc(7, n_states=4, n_modes=5)])
+                                W.random_lvc(7, n_states=4, n_modes=5), W.random_lvc(8, n_states=6, n_modes=4),
+                                W.random_lvc(9, n_states=8, n_modes=3)])
 def test_force_and_nac_vs_finite_differences(oracle_lib, wl):
     oc = oracle_lib
     model = wl.model

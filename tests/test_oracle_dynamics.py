@@ -250,21 +250,23 @@ def test_all_branches_enumeration(oracle_lib, scheme, start):
     assert np.all(np.abs(mc.imag - ex.imag) <= 4.5 * se_i + grain)
 
 
-def test_three_state_enumeration(oracle_lib):
+@pytest.mark.parametrize("n_states,k", [(3, 3), (5, 2), (8, 2)])
+def test_many_state_enumeration(oracle_lib, n_states, k):
     oc = oracle_lib
-    wl = W.random_lvc(1, n_states=3, n_modes=1)
+    wl = W.random_lvc(1, n_states=n_states, n_modes=1)
     mm = oc.Model(wl.model)
     rng = np.random.default_rng(0)
     q0 = wl.init.q0 + 0.3 * rng.normal(size=1)
     p0 = np.array([1.5])
     _, U0 = oc.adiabatic(mm, q0)
-    k, dt, T = 3, 0.2, 200_000
-    ex = Enumerator(wl.model).expectation(q0, p0, 1, 1, U0, dt, k)
-    st = oc.State(T, 3, 1)
+    dt, T = 0.2, 200_000
+    s0 = n_states // 2
+    ex = Enumerator(wl.model).expectation(q0, p0, s0, s0, U0, dt, k)
+    st = oc.State(T, n_states, 1)
     st.q[:] = q0
     st.p[:] = p0
-    st.a[:] = 1
-    st.b[:] = 1
+    st.a[:] = s0
+    st.b[:] = s0
     st.w[:] = 1.0
     st.U[:] = U0
     sums, _ = oc.propagate(mm, st, dt, k, 1, 17, k + 1)
