@@ -46,8 +46,9 @@
 extern "C" {
 #endif
 
-#define QCL_MAX_STATES 4
+#define QCL_MAX_STATES 8
 #define QCL_MAX_MODES 128
+#define QCL_MAX_MODES_MANY 32  /* mode limit of models with more than 4 states */
 /* Walkers per reduction tile: the partial sums are kept per tile of this
  * many consecutive walkers. */
 #define QCL_TILE 256
@@ -94,7 +95,8 @@ typedef struct qcl_model_s *qcl_model; /* opaque, library-owned, immutable */
 
 /* Model description (host pointers, read during qcl_create_model only). */
 typedef struct {
-    int32_t n_states;     /* N, 2 .. QCL_MAX_STATES */
+    int32_t n_states;     /* N, 2 .. QCL_MAX_STATES (N > 4: linear models
+                             with at most QCL_MAX_MODES_MANY modes) */
     int32_t n_modes;      /* M, 1 .. QCL_MAX_MODES */
     const double *mass;   /* [M], > 0 */
     const double *omega;  /* [M], > 0 */

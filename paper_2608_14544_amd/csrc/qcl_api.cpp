@@ -350,6 +350,11 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
         if (!symmetric(d->k + (size_t)j * n * n, n))
             return fail(QCL_ERR_INVALID_ARG, "K_%d is not symmetric", j);
     const int D = poly ? poly->degree : 1;
+    if (n > 4 && M > QCL_MAX_MODES_MANY)
+        return fail(QCL_ERR_UNSUPPORTED, "models with %d states support at most %d modes (got %d)", n,
+                    QCL_MAX_MODES_MANY, M);
+    if (n > 4 && poly)
+        return fail(QCL_ERR_UNSUPPORTED, "higher powers need at most 4 states (got %d)", n);
     if (poly) {
         if (D < 2 || D > 4)
             return fail(QCL_ERR_INVALID_ARG, "poly degree %d outside [2, 4]", D);

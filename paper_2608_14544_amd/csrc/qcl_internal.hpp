@@ -77,7 +77,11 @@ inline int padded_modes(int m)
     return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 128;
 }
 
-inline int rank_bucket(int rank, int n) { return rank <= 1 ? 1 : rank <= n ? n : n * (n + 1) / 2; }
+// rank bucket: 1, N or T = N(N+1)/2 (for more than 4 states only 1 or T)
+inline int rank_bucket(int rank, int n)
+{
+    return rank <= 1 ? 1 : (rank <= n && n <= 4) ? n : n * (n + 1) / 2;
+}
 
 template <typename R>
 struct EnsDev {
@@ -182,6 +186,10 @@ struct poly_ {};  // general kernels of K states, higher powers (kernels_poly{K}
 QCL_DECLARE_GENERAL(int_<2>)
 QCL_DECLARE_GENERAL(int_<3>)
 QCL_DECLARE_GENERAL(int_<4>)
+QCL_DECLARE_GENERAL(int_<5>)
+QCL_DECLARE_GENERAL(int_<6>)
+QCL_DECLARE_GENERAL(int_<7>)
+QCL_DECLARE_GENERAL(int_<8>)
 QCL_DECLARE_GENERAL(poly_<2>)
 QCL_DECLARE_GENERAL(poly_<3>)
 QCL_DECLARE_GENERAL(poly_<4>)
@@ -204,6 +212,10 @@ inline Ret with_general(const qcl_model_s &m, Ret none, F &&fn)
     case 2: return fn(int_<2>{});
     case 3: return fn(int_<3>{});
     case 4: return fn(int_<4>{});
+    case 5: return fn(int_<5>{});
+    case 6: return fn(int_<6>{});
+    case 7: return fn(int_<7>{});
+    case 8: return fn(int_<8>{});
     default: return none;
     }
 }
@@ -230,7 +242,7 @@ inline size_t batch_item(const qcl_model_s &m, const qcl_ensemble &ens, const qc
 // 32 padded modes, 2 with 64), else 0.
 inline int occupancy_variant(const qcl_model_s &m, int prec, int requested)
 {
-    if (m.fast2 || m.degree != 1 || prec != QCL_FP32_ACC64)
+    if (m.fast2 || m.degree != 1 || m.n > 4 || prec != QCL_FP32_ACC64)
         return 0;
     const int mp = padded_modes(m.m);
     if (requested == 3 && mp <= 32)

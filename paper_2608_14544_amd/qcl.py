@@ -368,8 +368,12 @@ def qcl_reduce_observables(model: Model, partials: Partials, n_traj: int, out=No
     """Returns a device tensor [n_out, 2, N, N, 4]: mean Re, mean Im, SE Re, SE Im."""
     torch = _torch()
     N = model.n_states
+    shape = (partials.n_out, 2, N, N, 4)
     if out is None:
-        out = torch.empty((partials.n_out, 2, N, N, 4), dtype=torch.float64, device=partials.tensor.device)
+        out = torch.empty(shape, dtype=torch.float64, device=partials.tensor.device)
+    elif tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous() \
+            or out.device != partials.tensor.device:
+        raise ValueError(f"out must be a contiguous float64 tensor of shape {shape} on {partials.tensor.device}")
     _check(load_library().qcl_reduce_observables(model.handle, partials.ptr, int(n_traj), partials.n_out,
                                                  C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(stream))))
     return out

@@ -43,13 +43,14 @@ def padded_modes(m: int) -> int:
 
 
 def rank_bucket(rank: int, n: int) -> int:
-    return 1 if rank <= 1 else n if rank <= n else n * (n + 1) // 2
+    return 1 if rank <= 1 else n if (rank <= n and n <= 4) else n * (n + 1) // 2
 
 
 def kernel_class(n_states: int, n_modes: int, rank: int, prec: str) -> Optional[Key]:
     """The tunable kernel class of a model, or None when only one build
-    exists (two-state closed form, binary64, more than 64 padded modes)."""
-    if n_states == 2 and n_modes <= 8:
+    exists (two-state closed form, more than 4 states, binary64, more than
+    64 padded modes)."""
+    if (n_states == 2 and n_modes <= 8) or n_states > 4:
         return None
     mp = padded_modes(n_modes)
     if prec != "fp32" or mp > 64:

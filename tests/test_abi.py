@@ -53,7 +53,7 @@ def _desc(qcl, lvc, **over):
 
 
 @pytest.mark.parametrize("case", [
-    dict(n_states=1), dict(n_states=5), dict(n_modes=0), dict(n_modes=129), dict(hbar=0.0),
+    dict(n_states=1), dict(n_states=9), dict(n_modes=0), dict(n_modes=129), dict(hbar=0.0),
     dict(hbar=float("nan")), dict(mass=[-1.0, 1.0, 1.0]), dict(omega=[1.0, 0.0, 1.0]),
     dict(v0=[[0.0, 0.1], [0.2, 0.0]]), dict(k=np.array([[[0, 1], [0, 0]]] * 3, float)),
     dict(v0=[[np.inf, 0.0], [0.0, 0.0]]),
@@ -89,6 +89,22 @@ def test_create_model_poly_rejects_invalid(degree, patch):
     assert L.qcl_last_error()
     assert L.qcl_create_model_poly(C.byref(d), None, C.byref(h)) == qcl.QCL_ERR_INVALID_ARG
     assert L.qcl_model_degree(None) == 0
+
+
+def test_many_state_limits_on_host():
+    """More than 4 states: at most 32 modes and no higher powers
+    (QCL_ERR_UNSUPPORTED, before any device work)."""
+    qcl, L = _lib()
+    big = W.random_lvc(50, n_states=5, n_modes=33).model
+    d, keep = _desc(qcl, big)
+    h = C.c_void_p()
+    assert L.qcl_create_model(C.byref(d), C.byref(h)) == qcl.QCL_ERR_UNSUPPORTED and not h.value
+    assert b"32 modes" in L.qcl_last_error()
+    six = W.random_lvc(51, n_states=6, n_modes=3).model
+    d, keep = _desc(qcl, six)
+    a = np.zeros((3, 1, 6, 6))
+    pd = qcl.qcl_poly_desc(2, 0, a.ctypes.data_as(C.POINTER(C.c_double)))
+    assert L.qcl_create_model_poly(C.byref(d), C.byref(pd), C.byref(h)) == qcl.QCL_ERR_UNSUPPORTED
 
 
 def test_null_arguments_rejected():
