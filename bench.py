@@ -23,7 +23,8 @@ two.  Two further legs are reported in the same line:
   convergence  the pyrazine-like and spin-boson (kT 0.2) models at 1e6, 1e7
            and 1e8 walkers: horizons of agreement and the decay rate;
   poly     models with higher powers of each mode (state-dependent
-           frequencies, anharmonicity) on the general kernels.
+           frequencies, anharmonicity) on the general kernels;
+  many_states  6- and 8-state models on the general kernels.
 
 Prints one JSON line.
 
@@ -216,6 +217,31 @@ def poly_leg(P, torch):
     cases = (("pyrazine_qvc", W.pyrazine_qvc(n_traj=10_000_000, n_steps=200, cadence=10)),
              ("poly_n3_m16_d4", W.random_poly(20, n_states=3, n_modes=16, degree=4, n_traj=1_000_000,
                                                n_steps=200, cadence=10, dt=0.02)))
+    return _model_runs(P, torch, cases)
+
+
+def many_states_leg(P, torch):
+    """Models with 6 and 8 electronic states (general kernels, odd-even
+    transposition sort): a 6-state, 8-mode model with rank-1 couplings and an
+    8-state, 8-mode model whose couplings span 8 directions (all 36 kept),
+    1e6 walkers x 200 steps, both precisions."""
+    import numpy as np
+    import workloads as W
+    dense = W.random_lvc(61, n_states=8, n_modes=8, n_traj=1_000_000, n_steps=200, cadence=10)
+    rng = np.random.Generator(np.random.Philox(key=[9, 61]))
+    k = dense.model.k.copy()
+    for j in range(8):
+        a = rng.uniform(-0.05, 0.05, size=(8, 8))
+        k[j] += 0.5 * (a + a.T)
+    dense.model = W.LVCModel(name="random_lvc_n8_dense", mass=dense.model.mass, omega=dense.model.omega,
+                             v0=dense.model.v0, k=k)
+    cases = (("lvc_n6_m8_rank1", W.random_lvc(60, n_states=6, n_modes=8, n_traj=1_000_000, n_steps=200,
+                                              cadence=10)),
+             ("lvc_n8_m8_dense", dense))
+    return _model_runs(P, torch, cases)
+
+
+def _model_runs(P, torch, cases):
     out = []
     for name, wl in cases:
         r = wl.run
@@ -364,7 +390,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling,convergence,poly",
+    ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling,convergence,poly,many_states",
                     help="comma-separated subset of headline,spin_boson,batched,served,scaling")
     ap.add_argument("--served-jobs", type=int, default=200)
     ap.add_argument("--served-quantum-work", type=float, default=2e8,
@@ -491,6 +517,11 @@ def main():
         line["poly"] = poly_leg(P, torch)
         print("[bench] poly: " + "; ".join(f"{x['model']} fp32 {x['fp32']['value']:.3e}, fp64 {x['fp64']['value']:.3e}"
                                            for x in line["poly"]), file=sys.stderr, flush=True)
+    if "many_states" in legs:
+        line["many_states"] = many_states_leg(P, torch)
+        print("[bench] many states: " + "; ".join(
+            f"{x['model']} fp32 {x['fp32']['value']:.3e}, fp64 {x['fp64']['value']:.3e}"
+            for x in line["many_states"]), file=sys.stderr, flush=True)
     if "convergence" in legs:
         line["convergence"] = convergence_leg(P, torch)
         for key, v in line["convergence"].items():

@@ -450,17 +450,26 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
         m->rank = factor_couplings(M, T, kmat, basis, coef);
         m->rank_pad = qcl::rank_bucket(m->rank, n);
         const int RB = m->rank_pad;
+        // every direction kept: the slot basis (unit matrices), coefficients
+        // the slot values themselves; the kernels skip its contractions
+        const bool slots = RB == T;
+        auto basis_rs = [&](int r, int s) {
+            return slots ? (r == s ? 1.0 : 0.0) : (r < m->rank ? basis[(size_t)r * T + s] : 0.0);
+        };
+        auto coef_jr = [&](int j, int r) {
+            return slots ? kmat[(size_t)j * T + r] : (r < m->rank ? coef[(size_t)j * m->rank + r] : 0.0);
+        };
         for (int r = 0; r < RB; ++r)
             for (int s = 0; s < T; ++s)
-                gen.push_back(r < m->rank ? basis[(size_t)r * T + s] : 0.0);
+                gen.push_back(basis_rs(r, s));
         for (int j = 0; j < qcl::kMaxModesPad; ++j) {
             const bool real = j < M;
             gen.push_back(real ? m->mass[j] * m->omega[j] * m->omega[j] : 0.0);
             gen.push_back(real ? 1.0 / m->mass[j] : 0.0);
             for (int r = 0; r < RB; ++r)
-                gen.push_back(real && r < m->rank ? coef[(size_t)j * m->rank + r] : 0.0);
+                gen.push_back(real ? coef_jr(j, r) : 0.0);
             for (int r = 0; r < RB; ++r)
-                gen.push_back(real && r < m->rank ? coef[(size_t)j * m->rank + r] / m->mass[j] : 0.0);
+                gen.push_back(real ? coef_jr(j, r) / m->mass[j] : 0.0);
         }
     } else {
         // rows (j, k), k = 1..4: A_j1 = K_j, A_jk from poly, zero past the degree
@@ -475,10 +484,10 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
             }
         m->rank = factor_couplings(M * 4, T, amat, basis, coef);
         m->rank_pad = T;
-        const int RB = T;
+        const int RB = T;  // slot basis: the coefficients are the slot values
         for (int r = 0; r < RB; ++r)
             for (int s = 0; s < T; ++s)
-                gen.push_back(r < m->rank ? basis[(size_t)r * T + s] : 0.0);
+                gen.push_back(r == s ? 1.0 : 0.0);
         for (int j = 0; j < qcl::kMaxModesPad; ++j) {
             const bool real = j < M;
             gen.push_back(real ? m->mass[j] * m->omega[j] * m->omega[j] : 0.0);
@@ -486,7 +495,7 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
             for (int r = 0; r < RB; ++r) {
                 double c[4];
                 for (int k = 0; k < 4; ++k)
-                    c[k] = real && r < m->rank ? coef[((size_t)j * 4 + k) * m->rank + r] : 0.0;
+                    c[k] = real ? amat[((size_t)j * 4 + k) * T + r] : 0.0;
                 for (int k = 0; k < 4; ++k)
                     gen.push_back(c[k]);
                 for (int k = 0; k < 4; ++k)

@@ -53,6 +53,9 @@ struct N2Const {
 //   basis [RB][T]                    B_r
 //   modes [kMaxModesPad][2 + 2 RB]   m w^2, 1/m, C_j0..C_j(RB-1), C_jr/m_j
 // zero-padded past the model's modes so that padded modes stay at rest.
+// When every direction is kept (RB = T) the basis is the slot basis (B_r
+// the unit matrix of slot r) and C_jr the slot values of K_j; the kernels
+// then skip the contractions with it.
 // A model with higher powers (V(q) = V0 + sum_j sum_{k=1..4} q_j^k A_jk,
 // A_j1 = K_j) factors all its A_jk over one basis, A_jk = sum_r C_jkr B_r,
 // with RB = T, and its mode rows hold per direction r the coefficients of
