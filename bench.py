@@ -403,7 +403,8 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the walker ensemble would shard by trajectory id; see DESIGN.md)", file=sys.stderr)
+              "(the walker ensemble would shard by global walker id, each GPU reducing its own "
+              "tiles, with one gather of the per-GPU partial sums at the end)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
