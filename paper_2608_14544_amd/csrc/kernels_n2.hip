@@ -22,6 +22,12 @@
 //     x_old . x_new < 0, so s0 s1 is constant along a walker.
 // Normalised eigenvectors are formed only for output bins and for the
 // frame stored at the end of a call.
+//
+// Models with higher powers of each mode (POLY) keep the closed form: dl,
+// cc and Vbar become sums of per-mode polynomials, evaluated by Horner's
+// rule, and the constants dlt_j, cpl_j, kbar_j above become the slopes of
+// those polynomials at q_j, computed once per point and kept in registers
+// for the coupling and the two kicks that use them.
 #include <algorithm>
 #include <cstring>
 
@@ -82,6 +88,43 @@ __device__ __forceinline__ void coupling_coords(const N2Const<M, R> &C, const R 
     }
 }
 
+__device__ __forceinline__ float fma2(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma2(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// c1 + x (c2 + x (c3 + x c4)): phi(x) = x times this for value coefficients,
+// phi'(x) itself for slope coefficients
+template <typename R>
+__device__ __forceinline__ R horner4(const R *c, R x)
+{
+    return fma2(x, fma2(x, fma2(x, c[3], c[2]), c[1]), c[0]);
+}
+
+template <int M, typename R>
+__device__ __forceinline__ void poly_coords(const N2Const<M, R> &C, const N2Poly<M, R> &Q, const R (&q)[M], R &dl,
+                                            R &cc)
+{
+    dl = C.dlt0;
+    cc = C.c0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        dl = fma2(q[j], horner4<R>(Q.dv[j], q[j]), dl);
+        cc = fma2(q[j], horner4<R>(Q.cv[j], q[j]), cc);
+    }
+}
+
+// slopes of the dl, cc and Vbar polynomials of every mode at q
+template <int M, typename R>
+__device__ __forceinline__ void poly_slopes(const N2Poly<M, R> &Q, const R (&q)[M], R (&SD)[M], R (&SC)[M],
+                                            R (&SB)[M])
+{
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        SD[j] = horner4<R>(Q.ds[j], q[j]);
+        SC[j] = horner4<R>(Q.cs[j], q[j]);
+        SB[j] = horner4<R>(Q.bs[j], q[j]);
+    }
+}
+
 // binary64 re-solve of a near-degenerate point for the binary32 path; the
 // binary64 constants are read from device memory only when needed
 template <int M>
@@ -98,15 +141,38 @@ __device__ __forceinline__ Geo2<float> resolve64(const double *__restrict__ c64,
     return Geo2<float>{(float)d.dl, (float)d.cc, (float)d.r, (float)d.rinv, (float)d.x0, (float)d.x1};
 }
 
-template <int M, typename R>
-__device__ __forceinline__ void geo_at(const N2Const<M, R> &C, const R (&q)[M], Geo2<R> &g, uint32_t &flag)
+// the same for a model with higher powers: [dlt0, c0, dv[M][4], cv[M][4]]
+template <int M>
+__device__ __forceinline__ Geo2<float> resolve64_poly(const double *__restrict__ c64, const float (&q)[M])
+{
+    double dl = c64[0], cc = c64[1];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const double x = (double)q[j];
+        dl = fma2(x, horner4<double>(c64 + 2 + 4 * j, x), dl);
+        cc = fma2(x, horner4<double>(c64 + 2 + 4 * M + 4 * j, x), cc);
+    }
+    Geo2<double> d;
+    geo2<double>(dl, cc, d);
+    return Geo2<float>{(float)d.dl, (float)d.cc, (float)d.r, (float)d.rinv, (float)d.x0, (float)d.x1};
+}
+
+template <int M, typename R, bool POLY>
+__device__ __forceinline__ void geo_at(const N2Const<M, R> &C, const N2Extra<M, R, POLY> &Q, const R (&q)[M],
+                                       Geo2<R> &g, uint32_t &flag)
 {
     R dl, cc;
-    coupling_coords<M, R>(C, q, dl, cc);
+    if constexpr (POLY)
+        poly_coords<M, R>(C, Q, q, dl, cc);
+    else
+        coupling_coords<M, R>(C, q, dl, cc);
     geo2<R>(dl, cc, g);
     if constexpr (sizeof(R) == 4) {
         if (!(R(2) * g.r >= C.gap_thr)) {
-            g = resolve64<M>(C.c64, q);
+            if constexpr (POLY)
+                g = resolve64_poly<M>(Q.c64, q);
+            else
+                g = resolve64<M>(C.c64, q);
             flag |= kFlagResolved;
         }
     }
@@ -164,9 +230,10 @@ __device__ __forceinline__ void bin_values(double (&v)[32], bool live, int a, in
 
 // ---------------------------------------------------------------- sampling
 
-template <int M, typename R>
-__global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C, SampleArgs S, EnsDev<R> E,
-                                                           double *__restrict__ partials, int32_t n_out)
+template <int M, typename R, bool POLY>
+__global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C, N2Extra<M, double, POLY> Q,
+                                                           SampleArgs S, EnsDev<R> E, double *__restrict__ partials,
+                                                           int32_t n_out)
 {
     __shared__ double lds[4 * 32];
     const int slot = scatter_slot32(threadIdx.x & 63);
@@ -189,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
     }
     Geo2<double> g;
     uint32_t flag = 0;
-    geo_at<M, double>(C, q, g, flag);
+    geo_at<M, double, POLY>(C, Q, q, g, flag);
     double c0, c1;
     canon2<double>(g, c0, c1);
     if (!(g.r > 0.0)) {  // exact degeneracy: any basis diagonalises V; take the identity
@@ -276,6 +343,15 @@ __device__ __forceinline__ void force_terms(const N2Const<M, R> &C, const Geo2<R
         G[j] = g.dl * C.dlt[j] + g.cc * C.cpl[j];
 }
 
+// the same for a model with higher powers: G_j = dl phi^d'_j + cc phi^c'_j
+template <int M, typename R>
+__device__ __forceinline__ void poly_force_terms(const Geo2<R> &g, const R (&SD)[M], const R (&SC)[M], R (&G)[M])
+{
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        G[j] = fma2(g.dl, SD[j], g.cc * SC[j]);
+}
+
 // p += (dt/2) * mean force of element (a,b), lam = a + b - 1:
 // (dt/2)(F_a + F_b)/2 = -hk q - hb - (dt/2) lam G/r
 template <int M, typename R>
@@ -287,9 +363,20 @@ __device__ __forceinline__ void mean_force_kick(const N2Const<M, R> &C, const R 
         p[j] = (p[j] - C.hb[j]) - C.hk[j] * q[j] - h * G[j];
 }
 
+// the same with hb_j = (dt/2) phi^b'_j(q_j) (models with higher powers)
+template <int M, typename R>
+__device__ __forceinline__ void poly_mean_force_kick(const N2Const<M, R> &C, const R (&SB)[M], const R (&G)[M], R h,
+                                                     const R (&q)[M], R (&p)[M])
+{
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        p[j] = fma2(-C.hdt, SB[j], p[j]) - C.hk[j] * q[j] - h * G[j];
+}
+
 // All steps of one tile of kBlock walkers (the whole workgroup calls it).
-template <int M, typename R, int SCHEME>
-__device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const PropArgs &P, const EnsDev<R> &E,
+template <int M, typename R, int SCHEME, bool POLY>
+__device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const N2Extra<M, R, POLY> &Q,
+                                                  const PropArgs &P, const EnsDev<R> &E,
                                                   double *__restrict__ partials, int64_t tile, int slot, double *lds)
 {
     const int64_t i = tile * kBlock + threadIdx.x;
@@ -313,14 +400,20 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const 
     uint32_t flag = 0;
 
     Geo2<R> g;
-    geo_at<M, R>(C, q, g, flag);
+    geo_at<M, R, POLY>(C, Q, q, g, flag);
     // column signs of the stored frame relative to the canonical one; the
     // product s0 s1 is invariant along the walker, s1 is tracked
     const R s0_in = (p00 * (-g.x1) + p10 * g.x0) < R(0) ? R(-1) : R(1);
     R s1 = (p01 * g.x0 + p11 * g.x1) < R(0) ? R(-1) : R(1);
     const R sig = s0_in * s1;
     R G[M];
-    force_terms<M, R>(C, g, G);
+    R SD[M], SC[M], SB[M];  // polynomial slopes at the current point (POLY)
+    if constexpr (POLY) {
+        poly_slopes<M, R>(Q, q, SD, SC, SB);
+        poly_force_terms<M, R>(g, SD, SC, G);
+    } else {
+        force_terms<M, R>(C, g, G);
+    }
     double r_old = (double)g.r;
 
     int64_t step = P.step0;
@@ -342,10 +435,19 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const 
             // dt v.d_01 = s0 s1 (dl c_v - cc dl_v) / (2 r^2); the two
             // candidates (1-a, b) and (a, 1-b) carry f0 = +-x, f1 = +-x.
             R dlv = R(0), cv = R(0);
+            if constexpr (POLY) {
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-                dlv += p[j] * C.vdl[j];
-                cv += p[j] * C.vcp[j];
+                for (int j = 0; j < M; ++j) {
+                    const R vj = p[j] * C.dtm[j];
+                    dlv = fma2(vj, SD[j], dlv);
+                    cv = fma2(vj, SC[j], cv);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    dlv += p[j] * C.vdl[j];
+                    cv += p[j] * C.vcp[j];
+                }
             }
             const R x = sig * (g.dl * cv - g.cc * dlv) * (R(0.5) * (g.rinv * g.rinv));
             const R ax = x < R(0) ? -x : x;
@@ -378,14 +480,23 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const 
             // 2. velocity Verlet on the mean force of the current element
             const R lam = R(a + b - 1);
             const R xo0 = g.x0, xo1 = g.x1;
-            mean_force_kick<M, R>(C, G, lam * (C.hdt * g.rinv), q, p);
+            if constexpr (POLY)
+                poly_mean_force_kick<M, R>(C, SB, G, lam * (C.hdt * g.rinv), q, p);
+            else
+                mean_force_kick<M, R>(C, G, lam * (C.hdt * g.rinv), q, p);
 #pragma unroll
             for (int j = 0; j < M; ++j)
                 q[j] += C.dtm[j] * p[j];
-            geo_at<M, R>(C, q, g, flag);
+            geo_at<M, R, POLY>(C, Q, q, g, flag);
             s1 = (xo0 * g.x0 + xo1 * g.x1 < R(0)) ? -s1 : s1;  // frame continuity
-            force_terms<M, R>(C, g, G);
-            mean_force_kick<M, R>(C, G, lam * (C.hdt * g.rinv), q, p);
+            if constexpr (POLY) {
+                poly_slopes<M, R>(Q, q, SD, SC, SB);
+                poly_force_terms<M, R>(g, SD, SC, G);
+                poly_mean_force_kick<M, R>(C, SB, G, lam * (C.hdt * g.rinv), q, p);
+            } else {
+                force_terms<M, R>(C, g, G);
+                mean_force_kick<M, R>(C, G, lam * (C.hdt * g.rinv), q, p);
+            }
 
             // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar = 2 (a - b) r / hbar
             const double r_new = (double)g.r;
@@ -426,21 +537,22 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const 
     }
 }
 
-template <int M, typename R, int SCHEME>
-__global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, PropArgs P, EnsDev<R> E,
-                                                              double *__restrict__ partials)
+template <int M, typename R, int SCHEME, bool POLY>
+__global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, N2Extra<M, R, POLY> Q, PropArgs P,
+                                                              EnsDev<R> E, double *__restrict__ partials)
 {
     __shared__ double lds[4 * 32];
     const int slot = scatter_slot32(threadIdx.x & 63);
-    propagate_n2_tile<M, R, SCHEME>(C, P, E, partials, (int64_t)blockIdx.x, slot, lds);
+    propagate_n2_tile<M, R, SCHEME, POLY>(C, Q, P, E, partials, (int64_t)blockIdx.x, slot, lds);
 }
 
 // Persistent launch over (instance, tile) work items of many two-state
 // instances of one kernel class; items are taken from an atomic counter
 // (descriptors are sorted by decreasing work per tile).
-template <int M, typename R, int SCHEME>
-__global__ __launch_bounds__(kBlock) void batch_n2_kernel(const BatchItemN2<M, R> *__restrict__ items, int32_t n_items,
-                                                          int64_t total_tiles, unsigned long long *counter)
+template <int M, typename R, int SCHEME, bool POLY>
+__global__ __launch_bounds__(kBlock) void batch_n2_kernel(const BatchItemN2<M, R, POLY> *__restrict__ items,
+                                                          int32_t n_items, int64_t total_tiles,
+                                                          unsigned long long *counter)
 {
     __shared__ double lds[4 * 32];
     __shared__ long long item_sh;
@@ -462,8 +574,8 @@ __global__ __launch_bounds__(kBlock) void batch_n2_kernel(const BatchItemN2<M, R
             const int mid = (lo + hi + 1) >> 1;
             if (items[mid].tile_begin <= item) lo = mid; else hi = mid - 1;
         }
-        const BatchItemN2<M, R> &it = items[lo];
-        propagate_n2_tile<M, R, SCHEME>(it.C, it.P, it.E, it.partials, item - it.tile_begin, slot, lds);
+        const BatchItemN2<M, R, POLY> &it = items[lo];
+        propagate_n2_tile<M, R, SCHEME, POLY>(it.C, it.Q, it.P, it.E, it.partials, item - it.tile_begin, slot, lds);
         __syncthreads();
     }
 }
@@ -492,6 +604,23 @@ N2Const<M, R> make_const(const qcl_model_s &m, double dt)
     return C;
 }
 
+template <int M, typename R>
+N2Poly<M, R> make_poly(const qcl_model_s &m)
+{
+    N2Poly<M, R> Q{};
+    for (int j = 0; j < M && j < m.m; ++j)  // padded modes: zero coefficients
+        for (int k = 0; k < 4; ++k) {
+            const double *row = &m.n2poly[(size_t)j * 20];
+            Q.dv[j][k] = (R)row[0 + k];
+            Q.ds[j][k] = (R)row[4 + k];
+            Q.cv[j][k] = (R)row[8 + k];
+            Q.cs[j][k] = (R)row[12 + k];
+            Q.bs[j][k] = (R)row[16 + k];
+        }
+    Q.c64 = m.d_model + m.n2poly64_offset;
+    return Q;
+}
+
 template <typename R>
 EnsDev<R> ens_dev(const qcl_ensemble &e)
 {
@@ -504,10 +633,22 @@ hipError_t sample_m(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemb
 {
     const dim3 grid((unsigned)n_tiles(ens.n_traj)), block(kBlock);
     const N2Const<M, double> C = make_const<M, double>(m, 1.0);
-    if (ens.prec == QCL_FP64)
-        hipLaunchKernelGGL((sample_n2_kernel<M, double>), grid, block, 0, s, C, sa, ens_dev<double>(ens), partials, n_out);
-    else
-        hipLaunchKernelGGL((sample_n2_kernel<M, float>), grid, block, 0, s, C, sa, ens_dev<float>(ens), partials, n_out);
+    if (m.degree > 1) {
+        const N2Poly<M, double> Q = make_poly<M, double>(m);
+        if (ens.prec == QCL_FP64)
+            hipLaunchKernelGGL((sample_n2_kernel<M, double, true>), grid, block, 0, s, C, Q, sa, ens_dev<double>(ens),
+                               partials, n_out);
+        else
+            hipLaunchKernelGGL((sample_n2_kernel<M, float, true>), grid, block, 0, s, C, Q, sa, ens_dev<float>(ens),
+                               partials, n_out);
+    } else {
+        if (ens.prec == QCL_FP64)
+            hipLaunchKernelGGL((sample_n2_kernel<M, double, false>), grid, block, 0, s, C, N2Linear{}, sa,
+                               ens_dev<double>(ens), partials, n_out);
+        else
+            hipLaunchKernelGGL((sample_n2_kernel<M, float, false>), grid, block, 0, s, C, N2Linear{}, sa,
+                               ens_dev<float>(ens), partials, n_out);
+    }
     return hipGetLastError();
 }
 
@@ -519,12 +660,22 @@ void propagate_mr(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_
     const PropArgs P{ens.step, pd.n_steps, pd.cadence, pd.n_out, pd.scheme, (uint32_t)pd.seed,
                      (uint32_t)(pd.seed >> 32)};
     const N2Const<M, R> C = make_const<M, R>(m, pd.dt);
+    if (m.degree > 1) {
+        const N2Poly<M, R> Q = make_poly<M, R>(m);
+        if (pd.scheme == QCL_TRANS_LINEAR)
+            hipLaunchKernelGGL((propagate_n2_kernel<M, R, QCL_TRANS_LINEAR, true>), grid, block, 0, s, C, Q, P,
+                               ens_dev<R>(ens), partials);
+        else
+            hipLaunchKernelGGL((propagate_n2_kernel<M, R, QCL_TRANS_NORMALIZED, true>), grid, block, 0, s, C, Q, P,
+                               ens_dev<R>(ens), partials);
+        return;
+    }
     if (pd.scheme == QCL_TRANS_LINEAR)
-        hipLaunchKernelGGL((propagate_n2_kernel<M, R, QCL_TRANS_LINEAR>), grid, block, 0, s, C, P, ens_dev<R>(ens),
-                           partials);
-    else
-        hipLaunchKernelGGL((propagate_n2_kernel<M, R, QCL_TRANS_NORMALIZED>), grid, block, 0, s, C, P,
+        hipLaunchKernelGGL((propagate_n2_kernel<M, R, QCL_TRANS_LINEAR, false>), grid, block, 0, s, C, N2Linear{}, P,
                            ens_dev<R>(ens), partials);
+    else
+        hipLaunchKernelGGL((propagate_n2_kernel<M, R, QCL_TRANS_NORMALIZED, false>), grid, block, 0, s, C,
+                           N2Linear{}, P, ens_dev<R>(ens), partials);
 }
 
 template <int M>
@@ -538,13 +689,15 @@ hipError_t propagate_m(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_
     return hipGetLastError();
 }
 
-template <int M, typename R>
+template <int M, typename R, bool POLY>
 size_t item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
                int64_t tile_begin, void *out)
 {
     if (out) {
-        BatchItemN2<M, R> it{};
+        BatchItemN2<M, R, POLY> it{};
         it.C = make_const<M, R>(m, pd.dt);
+        if constexpr (POLY)
+            it.Q = make_poly<M, R>(m);
         it.P = PropArgs{ens.step, pd.n_steps, pd.cadence, pd.n_out, pd.scheme, (uint32_t)pd.seed,
                         (uint32_t)(pd.seed >> 32), m.m};
         it.E = ens_dev<R>(ens);
@@ -552,27 +705,27 @@ size_t item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_des
         it.tile_begin = tile_begin;
         std::memcpy(out, &it, sizeof(it));
     }
-    return sizeof(BatchItemN2<M, R>);
+    return sizeof(BatchItemN2<M, R, POLY>);
 }
 
-template <int M, typename R>
+template <int M, typename R, bool POLY>
 hipError_t batch_m_r(int scheme, const void *items, int32_t n_items, int64_t total_tiles,
                      unsigned long long *counter, hipStream_t s)
 {
     int cus = 0, per_cu = 0, dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const void *fn = scheme == QCL_TRANS_LINEAR ? (const void *)batch_n2_kernel<M, R, QCL_TRANS_LINEAR>
-                                                : (const void *)batch_n2_kernel<M, R, QCL_TRANS_NORMALIZED>;
+    const void *fn = scheme == QCL_TRANS_LINEAR ? (const void *)batch_n2_kernel<M, R, QCL_TRANS_LINEAR, POLY>
+                                                : (const void *)batch_n2_kernel<M, R, QCL_TRANS_NORMALIZED, POLY>;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0);
     const int64_t grid = std::min<int64_t>(total_tiles, (int64_t)std::max(1, cus) * std::max(1, per_cu));
-    const BatchItemN2<M, R> *it = (const BatchItemN2<M, R> *)items;
+    const BatchItemN2<M, R, POLY> *it = (const BatchItemN2<M, R, POLY> *)items;
     if (scheme == QCL_TRANS_LINEAR)
-        hipLaunchKernelGGL((batch_n2_kernel<M, R, QCL_TRANS_LINEAR>), dim3((unsigned)grid), dim3(kBlock), 0, s, it,
-                           n_items, total_tiles, counter);
-    else
-        hipLaunchKernelGGL((batch_n2_kernel<M, R, QCL_TRANS_NORMALIZED>), dim3((unsigned)grid), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL((batch_n2_kernel<M, R, QCL_TRANS_LINEAR, POLY>), dim3((unsigned)grid), dim3(kBlock), 0, s,
                            it, n_items, total_tiles, counter);
+    else
+        hipLaunchKernelGGL((batch_n2_kernel<M, R, QCL_TRANS_NORMALIZED, POLY>), dim3((unsigned)grid), dim3(kBlock), 0,
+                           s, it, n_items, total_tiles, counter);
     return hipGetLastError();
 }
 
@@ -580,16 +733,22 @@ template <int M>
 size_t item_m(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
               int64_t tile_begin, void *out)
 {
-    return ens.prec == QCL_FP64 ? item_n2<M, double>(m, ens, pd, partials, tile_begin, out)
-                                : item_n2<M, float>(m, ens, pd, partials, tile_begin, out);
+    if (m.degree > 1)
+        return ens.prec == QCL_FP64 ? item_n2<M, double, true>(m, ens, pd, partials, tile_begin, out)
+                                    : item_n2<M, float, true>(m, ens, pd, partials, tile_begin, out);
+    return ens.prec == QCL_FP64 ? item_n2<M, double, false>(m, ens, pd, partials, tile_begin, out)
+                                : item_n2<M, float, false>(m, ens, pd, partials, tile_begin, out);
 }
 
 template <int M>
-hipError_t batch_m(int prec, int scheme, const void *items, int32_t n_items, int64_t total_tiles,
+hipError_t batch_m(bool poly, int prec, int scheme, const void *items, int32_t n_items, int64_t total_tiles,
                    unsigned long long *counter, hipStream_t s)
 {
-    return prec == QCL_FP64 ? batch_m_r<M, double>(scheme, items, n_items, total_tiles, counter, s)
-                            : batch_m_r<M, float>(scheme, items, n_items, total_tiles, counter, s);
+    if (poly)
+        return prec == QCL_FP64 ? batch_m_r<M, double, true>(scheme, items, n_items, total_tiles, counter, s)
+                                : batch_m_r<M, float, true>(scheme, items, n_items, total_tiles, counter, s);
+    return prec == QCL_FP64 ? batch_m_r<M, double, false>(scheme, items, n_items, total_tiles, counter, s)
+                            : batch_m_r<M, float, false>(scheme, items, n_items, total_tiles, counter, s);
 }
 
 }  // namespace
@@ -610,18 +769,18 @@ size_t batch_item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_pr
     }
 }
 
-hipError_t launch_batch_n2(int modes, int prec, int scheme, const void *items, int32_t n_items, int64_t total_tiles,
-                           unsigned long long *counter, hipStream_t s)
+hipError_t launch_batch_n2(int modes, bool poly, int prec, int scheme, const void *items, int32_t n_items,
+                           int64_t total_tiles, unsigned long long *counter, hipStream_t s)
 {
     switch (modes) {
-    case 1: return batch_m<1>(prec, scheme, items, n_items, total_tiles, counter, s);
-    case 2: return batch_m<2>(prec, scheme, items, n_items, total_tiles, counter, s);
-    case 3: return batch_m<3>(prec, scheme, items, n_items, total_tiles, counter, s);
-    case 4: return batch_m<4>(prec, scheme, items, n_items, total_tiles, counter, s);
-    case 5: return batch_m<5>(prec, scheme, items, n_items, total_tiles, counter, s);
-    case 6: return batch_m<6>(prec, scheme, items, n_items, total_tiles, counter, s);
-    case 7: return batch_m<7>(prec, scheme, items, n_items, total_tiles, counter, s);
-    case 8: return batch_m<8>(prec, scheme, items, n_items, total_tiles, counter, s);
+    case 1: return batch_m<1>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
+    case 2: return batch_m<2>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
+    case 3: return batch_m<3>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
+    case 4: return batch_m<4>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
+    case 5: return batch_m<5>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
+    case 6: return batch_m<6>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
+    case 7: return batch_m<7>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
+    case 8: return batch_m<8>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
     default: return hipErrorNotSupported;
     }
 }

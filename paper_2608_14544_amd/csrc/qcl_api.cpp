@@ -270,7 +270,8 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
             continue;
         const qcl_model_s &m = *it.model;
         // general kernels are specialised on padded modes and rank bucket
-        const int modes = m.fast2 ? m.m : qcl::padded_modes(m.m) * 64 + m.rank_pad + (m.degree > 1 ? 32 : 0);
+        const int poly = m.degree > 1 ? 1 : 0;
+        const int modes = m.fast2 ? m.m + 16 * poly : qcl::padded_modes(m.m) * 64 + m.rank_pad + 32 * poly;
         BatchClass *c = nullptr;
         const int occ = qcl::occupancy_variant(m, it.ens->prec, it.prop.occupancy);
         for (BatchClass &k : plan.classes)
@@ -381,7 +382,7 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
     m->degree = D;
     if (poly)
         m->poly.assign(poly->a, poly->a + (size_t)M * (D - 1) * n * n);
-    m->fast2 = (n == 2 && M <= qcl::kMaxFastModes && D == 1);
+    m->fast2 = (n == 2 && M <= qcl::kMaxFastModes);
     // energy scale: |V0| plus each mode's coupling over its zero-point-ish length
     double scale = 0.0;
     for (int i = 0; i < n * n; ++i)
@@ -419,6 +420,23 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
         }
         m->dlt0 = 0.5 * (m->v0[0] - m->v0[3]);
         m->c0 = m->v0[1];
+        if (D > 1) {
+            // per mode and power k = 1..4 (zero past the degree): dl, cc and
+            // Vbar parts of A_jk, as value and slope coefficients
+            m->n2poly.assign((size_t)M * 20, 0.0);
+            for (int j = 0; j < M; ++j)
+                for (int k = 1; k <= D; ++k) {
+                    const double *A = k == 1 ? &m->k[(size_t)j * 4]
+                                             : &m->poly[((size_t)j * (D - 1) + (k - 2)) * 4];
+                    const double bar = 0.5 * (A[0] + A[3]), dl = 0.5 * (A[0] - A[3]), cc = A[1];
+                    double *row = &m->n2poly[(size_t)j * 20];
+                    row[0 + k - 1] = dl;
+                    row[4 + k - 1] = k * dl;
+                    row[8 + k - 1] = cc;
+                    row[12 + k - 1] = k * cc;
+                    row[16 + k - 1] = k * bar;
+                }
+        }
     }
 
     hipError_t e = hipGetDevice(&m->device);
@@ -434,6 +452,15 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
         packed.push_back(m->c0);
         packed.insert(packed.end(), m->dlt.begin(), m->dlt.end());
         packed.insert(packed.end(), m->cpl.begin(), m->cpl.end());
+        if (D > 1) {
+            m->n2poly64_offset = packed.size();
+            packed.push_back(m->dlt0);
+            packed.push_back(m->c0);
+            for (int part : {0, 8})  // dv, then cv
+                for (int j = 0; j < M; ++j)
+                    for (int k = 0; k < 4; ++k)
+                        packed.push_back(m->n2poly[(size_t)j * 20 + part + k]);
+        }
     }
     // general-N tables (factored couplings), binary64 then binary32
     const int T = n * (n + 1) / 2;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <vector>
 
 #include "qcl.h"
@@ -121,11 +122,31 @@ struct PropArgs {
     int32_t m;  // modes actually present (general kernels)
 };
 
+// Two-state model with higher powers of each mode: per mode j the
+// polynomials (no constant term) of dl, of cc and of Vbar, each in four
+// coefficients c_1..c_4 (value) and 1c_1..4c_4 (slope); the linear part K_j
+// is c_1.  dl = dlt0 + sum_j phi^d_j(q_j), cc = c0 + sum_j phi^c_j(q_j), and
+// the mean force needs only the slope of phi^b_j.
+template <int M, typename R>
+struct N2Poly {
+    R dv[M][4], ds[M][4];  // dl: value and slope coefficients
+    R cv[M][4], cs[M][4];  // cc
+    R bs[M][4];            // Vbar: slope coefficients
+    // binary64 copies [dlt0, c0, dv[M][4], cv[M][4]] in device memory, read
+    // only by the binary32 path's near-degenerate re-solve
+    const double *c64;
+};
+struct N2Linear {};  // no extra constants for a linear model
+
+template <int M, typename R, bool POLY>
+using N2Extra = std::conditional_t<POLY, N2Poly<M, R>, N2Linear>;
+
 // Batched work: one descriptor per instance, tile_begin = prefix sum of the
 // tiles of the preceding descriptors of the same kernel class.
-template <int M, typename R>
+template <int M, typename R, bool POLY = false>
 struct BatchItemN2 {
     N2Const<M, R> C;
+    N2Extra<M, R, POLY> Q;
     PropArgs P;
     EnsDev<R> E;
     double *partials;
@@ -157,13 +178,15 @@ struct qcl_model_s {
     double *d_model = nullptr;  // device: V0 [N*N], K [M*N*N], then two-state binary64
                                 // constants [dlt0, c0, dlt[M], cpl[M]]
     size_t c64_offset = 0;      // element offset of the two-state constants
+    size_t n2poly64_offset = 0; // element offset of the two-state polynomial constants (binary64)
+    std::vector<double> n2poly; // [M][5][4]: dv, ds, cv, cs, bs per mode (two states, higher powers)
     size_t gen64_offset = 0;    // element offset of the general-N binary64 constants
     size_t gen32_byte_offset = 0;  // byte offset of the general-N binary32 constants
     int32_t rank = 0;           // rank of the mode couplings (general-N factorisation)
     int32_t rank_pad = 1;       // rank bucket RB the general kernels are specialised on
     int32_t degree = 1;         // highest power of q_j in V(q) (> 1: kernels_poly{N}.hip)
     std::vector<double> poly;   // [M][degree-1][N][N] higher-power matrices A_jk (k >= 2)
-    bool fast2 = false;         // two-state closed-form kernels apply (N = 2, M <= 8, linear)
+    bool fast2 = false;         // two-state closed-form kernels apply (N = 2, M <= 8)
 };
 
 namespace qcl {
@@ -225,8 +248,8 @@ inline Ret with_general(const qcl_model_s &m, Ret none, F &&fn)
 
 size_t batch_item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
                      int64_t tile_begin, void *out);
-hipError_t launch_batch_n2(int modes, int prec, int scheme, const void *items, int32_t n_items, int64_t total_tiles,
-                           unsigned long long *counter, hipStream_t s);
+hipError_t launch_batch_n2(int modes, bool poly, int prec, int scheme, const void *items, int32_t n_items,
+                           int64_t total_tiles, unsigned long long *counter, hipStream_t s);
 // device-side copy of host words carried in kernel arguments; zeroing of counters
 hipError_t upload_words(const uint64_t *words, size_t n_words, uint64_t *dst, hipStream_t s);
 hipError_t zero_words(uint64_t *dst, size_t n_words, hipStream_t s);
@@ -259,7 +282,7 @@ inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, int o
                                int32_t n_items, int64_t total_tiles, unsigned long long *counter, hipStream_t s)
 {
     if (m.fast2)  // the transition rule is a template parameter of the two-state kernels
-        return launch_batch_n2(m.m, prec, scheme, items, n_items, total_tiles, counter, s);
+        return launch_batch_n2(m.m, m.degree > 1, prec, scheme, items, n_items, total_tiles, counter, s);
     const int mp = padded_modes(m.m), rb = m.rank_pad;
     return with_general(m, hipErrorNotSupported, [&](auto tag) {
         return launch_batch_general_n(mp, rb, prec, occ, items, n_items, total_tiles, counter, s, tag);
