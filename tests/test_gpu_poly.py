@@ -176,3 +176,23 @@ def test_poly_largest_bucket_n4_m128(P):
         assert ensemble_close(out_g, out_o, wl.run.n_traj)
     out32, st32, _, _ = gpu_run(P, wl, prec="fp32")
     assert np.all(np.isfinite(st32["w"])) and np.all(np.isfinite(out32))
+
+
+def test_poly_two_state_closed_form_slicing_and_linear_rule(P):
+    """Two states, at most 8 modes: the closed-form kernels with polynomial
+    dl, cc and Vbar; bitwise slicing in both precisions and the linear
+    rule against the oracle."""
+    wl = W.pyrazine_qvc(n_traj=3000, n_steps=90, cadence=10)
+    for prec in ("fp64", "fp32"):
+        out1, st1, _, _ = gpu_run(P, wl, prec=prec)
+        out2, st2, _, _ = gpu_run(P, wl, prec=prec, split=[13, 27, 50])
+        for k in st1:
+            assert np.array_equal(st1[k], st2[k]), (prec, k)
+        assert np.array_equal(out1, out2), prec
+    wl = W.random_poly(8, n_states=2, n_modes=8, degree=4, n_traj=1500, n_steps=60, cadence=10)
+    out_g, st_g, _, _ = gpu_run(P, wl, scheme=1)
+    out_o, st_o, _, fl_o = oracle_run(wl, scheme=1)
+    assert np.array_equal(st_g["flags"] & 8, np.asarray(fl_o) & 8)
+    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label="poly n2 m8 linear")
+    if nflip == 0:
+        assert ensemble_close(out_g, out_o, wl.run.n_traj)
