@@ -8,4 +8,5 @@ with it; both sides read model numbers from :mod:`workloads`.
 ``oracle.branches``  exact all-branches expectation for tiny cases.
 ``oracle.grid``      phase-space grid solution of Eq. 1 (one mode, two states).
 ``oracle.decay``     horizons and decay rate of the excited population.
+``oracle.resample``  fixed-budget systematic resampling of an ensemble.
 """
