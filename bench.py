@@ -25,6 +25,9 @@ two.  Two further legs are reported in the same line:
   poly     models with higher powers of each mode (state-dependent
            frequencies, anharmonicity) on the general kernels;
   many_states  6- and 8-state models on the general kernels.
+  resample qcl_resample of the headline ensemble (1e7 walkers) against HBM
+           bandwidth, and the replica spread of P(t) with and without
+           resampling every 1-10 fs (64 x 1e6 walkers).
 
 Prints one JSON line.
 
@@ -241,6 +244,52 @@ def many_states_leg(P, torch):
     return _model_runs(P, torch, cases)
 
 
+def resample_leg(P, torch, n_traj=10_000_000, reps=20, replicas=64, replica_traj=1_000_000):
+    """Fixed-budget resampling (qcl_resample) of the headline ensemble
+    (pyrazine-like model, 1e7 walkers, binary32, after 200 steps): device
+    time per call from HIP events on the launch stream and the rate against
+    HBM, counting the algorithmic bytes (every walker's state read once and
+    written once).  Then the replica study: 64 runs of 1e6 walkers on
+    disjoint id ranges over 30 fs (1 fs bins), resampled every 1, 2, 5 or
+    10 fs or never, with the replica spread of the excited population at
+    10, 20 and 30 fs."""
+    import workloads as W
+    from paper_2608_14544_amd import branching
+    wl = W.pyrazine_ci()
+    r = wl.run
+    prec = "fp32"
+    model = P.Model(wl.model)
+    src = P.Ensemble(model, n_traj, prec)
+    dst = P.Ensemble(model, n_traj, prec)
+    part = P.Partials(model, n_traj, 2)
+    stream = torch.cuda.current_stream()
+    P.qcl_sample_initial(model, wl.init, r.seed, src, part, stream)
+    P.qcl_propagate(model, src, r.dt, 200, 200, r.seed, part, 0, stream)
+    ws = P.qcl_resample(model, src, dst, r.seed, None, stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        P.qcl_resample(model, src, dst, r.seed, ws, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / reps
+    M, N = model.n_modes, model.n_states
+    rs = 4 if prec == "fp32" else 8
+    state_bytes = (2 * M + N * N) * rs + 8 + 8 + 1 + 1 + 4
+    alg = 2 * state_bytes * n_traj
+    del src, dst, part, ws
+    torch.cuda.empty_cache()
+    out = {"n_traj": n_traj, "prec": prec, "ms": ms, "walkers_per_s": n_traj / (ms / 1e3),
+           "algorithmic_bytes_per_walker": 2 * state_bytes, "GB_per_s": alg / (ms / 1e3) / 1e9,
+           "frac_of_hbm_peak": alg / (ms / 1e3) / 8e12}
+    sw = W.pyrazine_ci(n_traj=0, n_steps=60, cadence=2)
+    out["replicas"] = {"n_traj": replica_traj, "replicas": replicas, "steps": 60,
+                       "dt_fs": sw.run.dt * sw.model.time_unit_fs,
+                       "by_interval": branching.replica_spread(sw, replica_traj, replicas, [None, 2, 4, 10, 20],
+                                                               [10.0, 20.0, 30.0], prec)}
+    return out
+
+
 def _model_runs(P, torch, cases):
     out = []
     for name, wl in cases:
@@ -390,8 +439,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling,convergence,poly,many_states",
-                    help="comma-separated subset of headline,spin_boson,batched,served,scaling")
+    ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling,convergence,poly,many_states,"
+                    "resample",
+                    help="comma-separated subset of the default legs")
     ap.add_argument("--served-jobs", type=int, default=200)
     ap.add_argument("--served-quantum-work", type=float, default=2e8,
                     help="walker-steps per resident job per serving round")
@@ -523,6 +573,12 @@ def main():
         print("[bench] many states: " + "; ".join(
             f"{x['model']} fp32 {x['fp32']['value']:.3e}, fp64 {x['fp64']['value']:.3e}"
             for x in line["many_states"]), file=sys.stderr, flush=True)
+    if "resample" in legs:
+        line["resample"] = resample_leg(P, torch)
+        rs = line["resample"]
+        print(f"[bench] resample: {rs['ms']:.3f} ms per 1e7 walkers, {rs['GB_per_s']:.0f} GB/s; replica SD at "
+              + ", ".join(f"{k} {v['replica_sd']}" for k, v in rs["replicas"]["by_interval"].items()),
+              file=sys.stderr, flush=True)
     if "convergence" in legs:
         line["convergence"] = convergence_leg(P, torch)
         for key, v in line["convergence"].items():

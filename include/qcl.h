@@ -306,6 +306,30 @@ qcl_status qcl_propagate_batch(const qcl_batch_item *items, int32_t n_items, voi
 qcl_status qcl_reduce_observables(qcl_model model, double *partials, int64_t n_traj,
                                   int32_t n_out, double *out, void *stream);
 
+/* Fixed-budget resampling between propagation calls (the paper's CPU code
+ * spawned walkers and let their number grow, Sec. II.B; this keeps T).
+ * The T walkers of src are replaced in dst by T copies drawn by systematic
+ * resampling in proportion to |w|, decided in exact integer arithmetic:
+ *   k_i = ceil(|w_i| / w_max * 2^32) for walkers with finite nonzero w and
+ *         finite phase (else 0; w_max over those walkers),
+ *   P_i = k_0 + ... + k_{i-1}, K = P_T,
+ *   output j copies the source i with P_i <= X_j < P_{i+1},
+ *   X_j = floor((j 2^32 + U) K / (T 2^32)), U = word 0 of Philox4x32-10 with
+ *   key (seed lo, seed hi) and counter (traj_offset lo, traj_offset hi,
+ *   step lo, 3),
+ * and output j gets the weight w_i * (K / (T k_i)) (binary64), so every
+ * walker's expected contribution is unchanged.  The rest of the state is
+ * copied; output j continues with the random stream of global id
+ * traj_offset + j.  If K = 0 the ensemble is copied unchanged.
+ * src and dst: same model, precision, n_traj (< 2^31), ld and traj_offset;
+ * no array shared between them.  dst->step is set to src->step; src is not
+ * changed.  workspace: device memory of qcl_resample_workspace_bytes bytes,
+ * 256-byte aligned, caller-owned (contents undefined afterwards).  Errors:
+ * INVALID_ARG, DEVICE.  Asynchronous on stream. */
+qcl_status qcl_resample_workspace_bytes(int64_t n_traj, size_t *bytes);
+qcl_status qcl_resample(qcl_model model, const qcl_ensemble *src, qcl_ensemble *dst, uint64_t seed,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
 /* Thread-local description of the last failure on this thread. */
 const char *qcl_last_error(void);
 

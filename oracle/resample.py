@@ -21,7 +21,8 @@ Steps, in exact integer arithmetic wherever a decision is taken:
    (T 2^32)).
 6. The copy's weight is w_i * (K / (T k_i)), with K, T and k_i converted to
    binary64 and the product T k_i formed in binary64.  The expected number
-   of copies of i is T k_i / K, so the expected weight is w_i.
+   of copies of i is T k_i / K up to the comb's integer grid (within 2^-32
+   over the 2^32 offsets), so the expected weight is w_i to that accuracy.
 
 If K = 0 (no walker has a nonzero finite weight) the ensemble is copied
 unchanged.  The state (q, p, U, phase, a, b, flags) of walker i is copied as
@@ -30,6 +31,8 @@ traj_offset + j.
 """
 from __future__ import annotations
 
+import bisect
+import itertools
 import math
 
 import numpy as np
@@ -75,6 +78,19 @@ def indices(k, U: int):
             i += 1
         src.append(i)
     return src, K
+
+
+def prefix(k):
+    """Step 3 alone: [P_0 = 0, P_1, ..., P_T = K] (Python ints)."""
+    return [0] + list(itertools.accumulate(k))
+
+
+def source(P, U: int, j: int) -> int:
+    """Step 5 for one output walker j: the i with P_i <= X_j < P_{i+1}
+    (requires K = P[-1] > 0)."""
+    T, K = len(P) - 1, P[-1]
+    X = ((j * TWO32 + U) * K) // (T * TWO32)
+    return bisect.bisect_right(P, X) - 1
 
 
 def resample(st: "oc.State", seed: int) -> "oc.State":

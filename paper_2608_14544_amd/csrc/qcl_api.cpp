@@ -814,6 +814,50 @@ qcl_status qcl_propagate_batch(const qcl_batch_item *items, int32_t n_items, voi
     return QCL_OK;
 }
 
+qcl_status qcl_resample_workspace_bytes(int64_t n_traj, size_t *bytes)
+{
+    if (!bytes)
+        return fail(QCL_ERR_INVALID_ARG, "bytes is NULL");
+    if (n_traj < 0 || n_traj >= ((int64_t)1 << 31))
+        return fail(QCL_ERR_INVALID_ARG, "resampling needs 0 <= n_traj < 2^31");
+    *bytes = n_traj == 0 ? 0 : qcl::resample_layout(n_traj).bytes;
+    return QCL_OK;
+}
+
+qcl_status qcl_resample(qcl_model m, const qcl_ensemble *src, qcl_ensemble *dst, uint64_t seed, void *workspace,
+                        size_t workspace_bytes, void *stream)
+{
+    if (qcl_status st = check_model(m))
+        return st;
+    if (qcl_status st = check_ensemble(*m, src))
+        return st;
+    if (qcl_status st = check_ensemble(*m, dst))
+        return st;
+    if (src->n_traj != dst->n_traj || src->prec != dst->prec || src->ld != dst->ld ||
+        src->traj_offset != dst->traj_offset)
+        return fail(QCL_ERR_INVALID_ARG, "src and dst differ in n_traj, precision, ld or traj_offset");
+    if (src->n_traj >= ((int64_t)1 << 31))
+        return fail(QCL_ERR_INVALID_ARG, "resampling needs n_traj < 2^31");
+    if (src->n_traj > 0) {
+        const void *a[] = {src->q, src->p, src->u, src->w, src->phase, src->a, src->b, src->flags};
+        const void *b[] = {dst->q, dst->p, dst->u, dst->w, dst->phase, dst->a, dst->b, dst->flags};
+        for (const void *x : a)
+            for (const void *y : b)
+                if (x && x == y)
+                    return fail(QCL_ERR_INVALID_ARG, "src and dst share an array");
+        const size_t need = qcl::resample_layout(src->n_traj).bytes;
+        if (!workspace || ((uintptr_t)workspace % 256) || workspace_bytes < need)
+            return fail(QCL_ERR_INVALID_ARG, "workspace must be 256-byte aligned and hold %zu bytes", need);
+        if (qcl_status st = check_device(*m))
+            return st;
+        const hipError_t e = qcl::launch_resample(*m, *src, *dst, seed, workspace, (hipStream_t)stream);
+        if (e != hipSuccess)
+            return device_fail(e, "resample launch");
+    }
+    dst->step = src->step;
+    return QCL_OK;
+}
+
 qcl_status qcl_reduce_observables(qcl_model m, double *partials, int64_t n_traj, int32_t n_out, double *out,
                                   void *stream)
 {

@@ -305,6 +305,14 @@ inline hipError_t launch_propagate_general(const qcl_model_s &m, const qcl_ensem
 hipError_t launch_reduce(int n_states, double *partials, int64_t n_traj, int32_t n_out, double *out,
                          hipStream_t stream);
 
+// workspace of qcl_resample: byte offsets of its parts and the total
+struct ResampleLayout {
+    size_t wmax, P, tiles, supers, comb, start, bytes;  // byte offsets into the workspace, total size
+};
+ResampleLayout resample_layout(int64_t n_traj);
+hipError_t launch_resample(const qcl_model_s &m, const qcl_ensemble &src, const qcl_ensemble &dst, uint64_t seed,
+                           void *workspace, hipStream_t stream);
+
 inline int64_t n_tiles(int64_t n_traj) { return (n_traj + kBlock - 1) / kBlock; }
 inline int64_t tile_values(int n_states) { return 8LL * n_states * n_states; }
 

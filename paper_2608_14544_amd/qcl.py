@@ -84,7 +84,7 @@ EXPORTS = ("qcl_create_model", "qcl_create_model_poly", "qcl_destroy_model", "qc
            "qcl_model_modes", "qcl_model_rank", "qcl_model_degree",
            "qcl_ensemble_bytes", "qcl_ensemble_bind", "qcl_partials_bytes",
            "qcl_sample_initial", "qcl_propagate", "qcl_batch_workspace_bytes", "qcl_propagate_batch",
-           "qcl_reduce_observables", "qcl_last_error")
+           "qcl_reduce_observables", "qcl_resample_workspace_bytes", "qcl_resample", "qcl_last_error")
 
 _lock = threading.Lock()
 _lib = None
@@ -120,6 +120,8 @@ def load_library(path: str = LIB_PATH):
         L.qcl_batch_workspace_bytes.argtypes = [C.POINTER(qcl_batch_item), i32, C.POINTER(sz)]
         L.qcl_propagate_batch.argtypes = [C.POINTER(qcl_batch_item), i32, vp, sz, vp]
         L.qcl_reduce_observables.argtypes = [vp, vp, i64, i32, vp, vp]
+        L.qcl_resample_workspace_bytes.argtypes = [i64, C.POINTER(sz)]
+        L.qcl_resample.argtypes = [vp, C.POINTER(qcl_ensemble), C.POINTER(qcl_ensemble), u64, vp, sz, vp]
         L.qcl_last_error.argtypes = []
         L.qcl_last_error.restype = C.c_char_p
         for name in EXPORTS[:-1]:
@@ -377,6 +379,26 @@ def qcl_reduce_observables(model: Model, partials: Partials, n_traj: int, out=No
     _check(load_library().qcl_reduce_observables(model.handle, partials.ptr, int(n_traj), partials.n_out,
                                                  C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(stream))))
     return out
+
+
+def qcl_resample_workspace_bytes(n_traj: int) -> int:
+    nb = C.c_size_t(0)
+    _check(load_library().qcl_resample_workspace_bytes(int(n_traj), C.byref(nb)))
+    return nb.value
+
+
+def qcl_resample(model: Model, src: Ensemble, dst: Ensemble, seed: int, workspace: Optional[Workspace] = None,
+                 stream=None):
+    """Fixed-budget systematic resampling of src into dst (same size, precision
+    and traj_offset); dst continues at src's step.  Returns the workspace."""
+    L = load_library()
+    nb = C.c_size_t(0)
+    _check(L.qcl_resample_workspace_bytes(src.n_traj, C.byref(nb)))
+    ws = workspace or Workspace(device=src.buffer.device)
+    ptr, have = ws.get(nb.value)
+    _check(L.qcl_resample(model.handle, C.byref(src.c), C.byref(dst.c), int(seed) & 0xFFFFFFFFFFFFFFFF, ptr, have,
+                          C.c_void_p(_stream_handle(stream))))
+    return ws
 
 
 def run(workload, prec="fp64", n_traj: Optional[int] = None, n_steps: Optional[int] = None,

@@ -142,3 +142,16 @@ def test_binding_fails_loudly_without_library(tmp_path):
             qcl.load_library(str(tmp_path / "missing.so"))
         finally:
             qcl._lib = old
+
+
+def test_resample_validation_on_host():
+    qcl, L = _lib()
+    b = C.c_size_t(123)
+    assert L.qcl_resample_workspace_bytes(0, C.byref(b)) == qcl.QCL_OK and b.value == 0
+    # the prefix sums P (8 bytes a walker), tile and group sums, the maximum
+    assert L.qcl_resample_workspace_bytes(1000, C.byref(b)) == qcl.QCL_OK
+    assert b.value >= 8 * 1001 and b.value % 256 == 0
+    assert L.qcl_resample_workspace_bytes(-1, C.byref(b)) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_resample_workspace_bytes(1 << 31, C.byref(b)) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_resample_workspace_bytes(10, None) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_resample(None, None, None, 0, None, 0, None) == qcl.QCL_ERR_INVALID_ARG

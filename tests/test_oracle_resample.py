@@ -86,3 +86,17 @@ def test_quantization_and_offset_definitions():
     # the offset is word 0 of the Philox block at counter (offset, step, 3)
     x = oc.philox([7, 0, 11, 3], [5, 0])
     assert R.offset_word(5, 7, 11) == int(x[0])
+
+
+def test_per_output_source_matches_the_sequential_walk():
+    # zero weights in the middle and at both ends give empty intervals that
+    # the search must step over
+    rng = np.random.default_rng(4)
+    w = rng.lognormal(0, 2.0, size=300)
+    w[[0, 5, 6, 7, 150, 299]] = 0.0
+    k, _ = R.quantized(w.tolist(), [0.0] * 300)
+    P = R.prefix(k)
+    assert P[-1] == sum(k) and len(P) == 301
+    for U in (0, 77, (1 << 32) - 1):
+        src, _ = R.indices(k, U)
+        assert [R.source(P, U, j) for j in range(300)] == src
