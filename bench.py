@@ -283,6 +283,8 @@ def resample_leg(P, torch, n_traj=10_000_000, reps=20, replicas=64, replica_traj
            "algorithmic_bytes_per_walker": 2 * state_bytes, "GB_per_s": alg / (ms / 1e3) / 1e9,
            "frac_of_hbm_peak": alg / (ms / 1e3) / 8e12}
     sw = W.pyrazine_ci(n_traj=0, n_steps=60, cadence=2)
+    if not replicas:
+        return out
     out["replicas"] = {"n_traj": replica_traj, "replicas": replicas, "steps": 60,
                        "dt_fs": sw.run.dt * sw.model.time_unit_fs,
                        "by_interval": branching.replica_spread(sw, replica_traj, replicas, [None, 2, 4, 10, 20],
@@ -442,6 +444,8 @@ def main():
     ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling,convergence,poly,many_states,"
                     "resample",
                     help="comma-separated subset of the default legs")
+    ap.add_argument("--resample-replicas", type=int, default=64,
+                    help="replicas of the resampling study (0: time the resampling only)")
     ap.add_argument("--served-jobs", type=int, default=200)
     ap.add_argument("--served-quantum-work", type=float, default=2e8,
                     help="walker-steps per resident job per serving round")
@@ -574,11 +578,11 @@ def main():
             f"{x['model']} fp32 {x['fp32']['value']:.3e}, fp64 {x['fp64']['value']:.3e}"
             for x in line["many_states"]), file=sys.stderr, flush=True)
     if "resample" in legs:
-        line["resample"] = resample_leg(P, torch)
+        line["resample"] = resample_leg(P, torch, replicas=args.resample_replicas)
         rs = line["resample"]
-        print(f"[bench] resample: {rs['ms']:.3f} ms per 1e7 walkers, {rs['GB_per_s']:.0f} GB/s; replica SD at "
-              + ", ".join(f"{k} {v['replica_sd']}" for k, v in rs["replicas"]["by_interval"].items()),
-              file=sys.stderr, flush=True)
+        print(f"[bench] resample: {rs['ms']:.3f} ms per 1e7 walkers, {rs['GB_per_s']:.0f} GB/s"
+              + ("; replica SD " + ", ".join(f"{k} {v['replica_sd']}" for k, v in rs["replicas"]["by_interval"].items())
+                 if "replicas" in rs else ""), file=sys.stderr, flush=True)
     if "convergence" in legs:
         line["convergence"] = convergence_leg(P, torch)
         for key, v in line["convergence"].items():

@@ -14,10 +14,11 @@
 // 2^-32 of T k_i / K).
 //
 // Passes (all bound by HBM bandwidth):
-//   1. exact maximum of |w|: grid-stride workgroup maxima, one atomic
-//      maximum of the bit pattern per workgroup (non-negative doubles order
-//      like their bit patterns);
-//   2. per 256-walker tile, the sum of k_i;
+//   1. exact maximum of |w|: per-tile maxima, then one atomic maximum per
+//      group of 256 tiles (non-negative doubles order like their bit
+//      patterns);
+//   2. per 1024-walker tile (four consecutive walkers a lane), the sum of
+//      k_i;
 //   3. exclusive scan of the tile sums per group of 256 tiles, with the
 //      group totals;
 //   4. one workgroup: exclusive scan of the group totals, K after the last;
@@ -43,7 +44,11 @@ namespace qcl {
 namespace {
 
 constexpr double kTwo32 = 4294967296.0;
-constexpr int kMaxGridMax = 2048;  // workgroups of pass 1
+constexpr int kItems = 4;                // consecutive walkers per lane in passes 1, 2 and 5
+constexpr int kQTile = kBlock * kItems;  // walkers per quantisation tile
+
+int64_t n_qtiles(int64_t n) { return (n + kQTile - 1) / kQTile; }
+int64_t n_groups_of(int64_t tiles) { return (tiles + kBlock - 1) / kBlock; }
 
 __device__ __forceinline__ bool live_weight(double w, double phase) { return isfinite(w) && isfinite(phase) && w != 0.0; }
 
@@ -85,27 +90,72 @@ __device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t v, uint64_t *ld
     return inclusive - v;
 }
 
-__global__ __launch_bounds__(kBlock) void rs_max_kernel(const double *__restrict__ w, const double *__restrict__ phase,
-                                                        int64_t n, unsigned long long *wmax_bits)
+// largest of one value per thread over the workgroup
+__device__ __forceinline__ uint64_t block_max_u64(uint64_t v, uint64_t *lds)
 {
-    __shared__ uint64_t lds[kBlock];
-    uint64_t bits = 0;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-#pragma unroll 4
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        const double x = w[i];
-        const uint64_t b = live_weight(x, phase[i]) ? (uint64_t)__double_as_longlong(fabs(x)) : 0;
-        bits = b > bits ? b : bits;
-    }
-    lds[threadIdx.x] = bits;
+    lds[threadIdx.x] = v;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off)
             lds[threadIdx.x] = lds[threadIdx.x] > lds[threadIdx.x + off] ? lds[threadIdx.x] : lds[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && lds[0] != 0)
-        atomicMax(wmax_bits, (unsigned long long)lds[0]);
+    const uint64_t r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// per quantisation tile, the bit pattern of the largest |w| of a live walker
+// (0 if none)
+__global__ __launch_bounds__(kBlock) void rs_tile_max_kernel(const double *__restrict__ w,
+                                                             const double *__restrict__ phase, int64_t n,
+                                                             uint64_t *__restrict__ tile_max)
+{
+    __shared__ uint64_t lds[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kQTile + (int64_t)threadIdx.x * kItems;
+    double x[kItems], f[kItems];
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {  // clamped indices: every load issues at once
+        const int64_t i = base + u < n ? base + u : n - 1;
+        x[u] = w[i];
+        f[u] = phase[i];
+    }
+    uint64_t bits = 0;
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        const uint64_t b = base + u < n && live_weight(x[u], f[u]) ? (uint64_t)__double_as_longlong(fabs(x[u])) : 0;
+        bits = b > bits ? b : bits;
+    }
+    const uint64_t mx = block_max_u64(bits, lds);
+    if (threadIdx.x == 0)
+        tile_max[blockIdx.x] = mx;
+}
+
+// per group of kBlock tiles, one atomic maximum into *wmax_bits
+__global__ __launch_bounds__(kBlock) void rs_max_groups_kernel(const uint64_t *__restrict__ tile_max, int64_t n_tiles,
+                                                               unsigned long long *wmax_bits)
+{
+    __shared__ uint64_t lds[kBlock];
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t mx = block_max_u64(t < n_tiles ? tile_max[t] : 0, lds);
+    if (threadIdx.x == 0 && mx != 0)
+        atomicMax(wmax_bits, (unsigned long long)mx);
+}
+
+// quantised weights of a lane's kItems consecutive walkers (0 past the end)
+__device__ __forceinline__ void lane_weights(const double *__restrict__ w, const double *__restrict__ phase, int64_t n,
+                                             int64_t base, double wmax, uint64_t (&k)[kItems])
+{
+    double x[kItems], f[kItems];
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        const int64_t i = base + u < n ? base + u : n - 1;
+        x[u] = w[i];
+        f[u] = phase[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kItems; ++u)
+        k[u] = base + u < n ? quantized(x[u], f[u], wmax) : 0;
 }
 
 __global__ __launch_bounds__(kBlock) void rs_tile_sum_kernel(const double *__restrict__ w,
@@ -114,10 +164,14 @@ __global__ __launch_bounds__(kBlock) void rs_tile_sum_kernel(const double *__res
                                                              uint64_t *__restrict__ tile_sums)
 {
     __shared__ uint64_t lds[kBlock];
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const double wmax = __longlong_as_double((long long)*wmax_bits);
-    const uint64_t ki = i < n ? quantized(w[i], phase[i], wmax) : 0;
-    const uint64_t s = block_sum_u64(ki, lds);
+    const int64_t base = (int64_t)blockIdx.x * kQTile + (int64_t)threadIdx.x * kItems;
+    uint64_t k[kItems];
+    lane_weights(w, phase, n, base, __longlong_as_double((long long)*wmax_bits), k);
+    uint64_t local = 0;
+#pragma unroll
+    for (int u = 0; u < kItems; ++u)
+        local += k[u];
+    const uint64_t s = block_sum_u64(local, lds);
     if (threadIdx.x == 0)
         tile_sums[blockIdx.x] = s;
 }
@@ -163,13 +217,21 @@ __global__ __launch_bounds__(kBlock) void rs_prefix_kernel(const double *__restr
                                                            uint64_t *__restrict__ P)
 {
     __shared__ uint64_t lds[kBlock];
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const double wmax = __longlong_as_double((long long)*wmax_bits);
-    const uint64_t ki = i < n ? quantized(w[i], phase[i], wmax) : 0;
+    const int64_t base = (int64_t)blockIdx.x * kQTile + (int64_t)threadIdx.x * kItems;
+    uint64_t k[kItems];
+    lane_weights(w, phase, n, base, __longlong_as_double((long long)*wmax_bits), k);
+    uint64_t local = 0;
+#pragma unroll
+    for (int u = 0; u < kItems; ++u)
+        local += k[u];
     uint64_t total;
-    const uint64_t ex = block_exclusive_u64(ki, lds, &total);
-    if (i < n)
-        P[i] = supers[blockIdx.x / kBlock] + tile_sums[blockIdx.x] + ex;
+    uint64_t run = supers[blockIdx.x / kBlock] + tile_sums[blockIdx.x] + block_exclusive_u64(local, lds, &total);
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        if (base + u < n)
+            P[base + u] = run;
+        run += k[u];
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0)
         P[n] = supers[n_groups];
 }
@@ -243,6 +305,17 @@ __global__ __launch_bounds__(kBlock) void rs_bounds_kernel(const uint64_t *__res
 }
 
 constexpr int kStage = 1024;  // largest slice of P a workgroup stages in LDS
+constexpr int kXcds = 8;      // workgroups are dealt to the XCDs round-robin
+
+// Output tile of a gather workgroup: each XCD (own L2) takes one contiguous
+// run of tiles, so the cache lines shared by neighbouring tiles' source
+// slices are fetched into one L2 only.  A bijection of [0, n_wg).
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t n_wg)
+{
+    const int64_t xcd = bid % kXcds, local = bid / kXcds;
+    const int64_t base = n_wg / kXcds, extra = n_wg % kXcds;
+    return xcd < extra ? xcd * (base + 1) + local : extra * (base + 1) + (xcd - extra) * base + local;
+}
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void rs_gather_kernel(EnsDev<R> S, EnsDev<R> D, int32_t m, int32_t nn,
@@ -253,13 +326,14 @@ __global__ __launch_bounds__(kBlock) void rs_gather_kernel(EnsDev<R> S, EnsDev<R
 {
     __shared__ uint64_t slice[kStage + 1];
     const int64_t n = S.n_traj;
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t wg = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t j = wg * kBlock + threadIdx.x;
     const uint64_t K = P[n];
     int64_t i = j;  // K == 0: no walker with a nonzero finite weight, copy unchanged
     double scale = 1.0;
     if (K != 0) {
         // every output of this workgroup has P[lo] <= X_j < P[hi]
-        const int64_t lo = start[blockIdx.x], hi = start[blockIdx.x + 1] + 1;
+        const int64_t lo = start[wg], hi = start[wg + 1] + 1;
         const bool staged = hi - lo <= kStage;  // uniform over the workgroup
         if (staged) {
             for (int64_t t = threadIdx.x; t <= hi - lo; t += kBlock)
@@ -297,22 +371,20 @@ EnsDev<R> ens_dev_rs(const qcl_ensemble &e)
     return EnsDev<R>{(R *)e.q, (R *)e.p, (R *)e.u, e.w, e.phase, e.a, e.b, e.flags, e.ld, e.n_traj, e.traj_offset};
 }
 
-int64_t n_groups_of(int64_t tiles) { return (tiles + kBlock - 1) / kBlock; }
-
 }  // namespace
 
 ResampleLayout resample_layout(int64_t n_traj)
 {
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     ResampleLayout L{};
-    const size_t T = (size_t)n_traj, tiles = (size_t)n_tiles(n_traj), groups = (size_t)n_groups_of(n_tiles(n_traj));
+    const size_t T = (size_t)n_traj, qt = (size_t)n_qtiles(n_traj), groups = (size_t)n_groups_of(n_qtiles(n_traj));
     L.wmax = 0;
     L.P = 256;
     L.tiles = L.P + up(8 * (T + 1));
-    L.supers = L.tiles + up(8 * tiles);
+    L.supers = L.tiles + up(8 * qt);
     L.comb = L.supers + up(8 * (groups + 1));
     L.start = L.comb + 256;
-    L.bytes = L.start + up(8 * (tiles + 1));
+    L.bytes = L.start + up(8 * ((size_t)n_tiles(n_traj) + 1));
     return L;
 }
 
@@ -322,7 +394,7 @@ hipError_t launch_resample(const qcl_model_s &m, const qcl_ensemble &S, const qc
     const int64_t n = S.n_traj;
     if (n == 0)
         return hipSuccess;
-    const int64_t tiles = n_tiles(n), groups = n_groups_of(tiles);
+    const int64_t qt = n_qtiles(n), groups = n_groups_of(qt), tiles = n_tiles(n);
     const ResampleLayout L = resample_layout(n);
     char *ws = (char *)workspace;
     auto *wmax = (unsigned long long *)(ws + L.wmax);
@@ -334,14 +406,15 @@ hipError_t launch_resample(const qcl_model_s &m, const qcl_ensemble &S, const qc
     hipError_t e = zero_words((uint64_t *)wmax, 1, s);
     if (e != hipSuccess)
         return e;
-    const dim3 grid((unsigned)tiles), block(kBlock);
-    const unsigned max_grid = (unsigned)(tiles < kMaxGridMax ? tiles : kMaxGridMax);
+    const dim3 qgrid((unsigned)qt), grid((unsigned)tiles), block(kBlock);
     const auto *cwmax = (const unsigned long long *)wmax;
-    hipLaunchKernelGGL(rs_max_kernel, dim3(max_grid), block, 0, s, S.w, S.phase, n, wmax);
-    hipLaunchKernelGGL(rs_tile_sum_kernel, grid, block, 0, s, S.w, S.phase, n, cwmax, tsum);
-    hipLaunchKernelGGL(rs_scan_groups_kernel, dim3((unsigned)groups), block, 0, s, tsum, tiles, sup);
+    // the tile maxima live in the tile-sum array until the tile sums replace them
+    hipLaunchKernelGGL(rs_tile_max_kernel, qgrid, block, 0, s, S.w, S.phase, n, tsum);
+    hipLaunchKernelGGL(rs_max_groups_kernel, dim3((unsigned)groups), block, 0, s, (const uint64_t *)tsum, qt, wmax);
+    hipLaunchKernelGGL(rs_tile_sum_kernel, qgrid, block, 0, s, S.w, S.phase, n, cwmax, tsum);
+    hipLaunchKernelGGL(rs_scan_groups_kernel, dim3((unsigned)groups), block, 0, s, tsum, qt, sup);
     hipLaunchKernelGGL(rs_scan_top_kernel, dim3(1), block, 0, s, sup, groups);
-    hipLaunchKernelGGL(rs_prefix_kernel, grid, block, 0, s, S.w, S.phase, n, cwmax, (const uint64_t *)tsum,
+    hipLaunchKernelGGL(rs_prefix_kernel, qgrid, block, 0, s, S.w, S.phase, n, cwmax, (const uint64_t *)tsum,
                        (const uint64_t *)sup, groups, P);
     // one lane per gather workgroup plus the closing entry
     hipLaunchKernelGGL(rs_bounds_kernel, dim3((unsigned)n_tiles(tiles + 1)), block, 0, s, (const uint64_t *)P, n,
