@@ -34,12 +34,15 @@ class Enumerator:
 
     # -- electronic structure (numpy eigh + sign conventions) -------------
     def V(self, q):
-        """V0 + sum_j q_j K_j (+ sum_j sum_k q_j^k A_jk for models with higher powers)."""
+        """V0 + sum_j q_j K_j (+ sum_j sum_k q_j^k A_jk for models with higher
+        powers, + sum_p q_i q_j B_p for cross-mode bilinear terms)."""
         v = self.m.v0 + np.tensordot(q, self.m.k, axes=(0, 0))
         poly = getattr(self.m, "poly", None)
         if poly is not None:
             for k in range(2, poly.shape[1] + 2):
                 v = v + np.tensordot(np.asarray(q) ** k, poly[:, k - 2], axes=(0, 0))
+        for i, j, B in getattr(self.m, "bilinear", None) or []:
+            v = v + q[i] * q[j] * np.asarray(B)
         return v
 
     def eig(self, q, Uprev=None):

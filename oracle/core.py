@@ -45,7 +45,8 @@ class _Model(C.Structure):
     _fields_ = [("n_states", C.c_int32), ("n_modes", C.c_int32),
                 ("mass", C.POINTER(C.c_double)), ("omega", C.POINTER(C.c_double)),
                 ("v0", C.POINTER(C.c_double)), ("k", C.POINTER(C.c_double)),
-                ("hbar", C.c_double), ("degree", C.c_int32), ("a", C.POINTER(C.c_double))]
+                ("hbar", C.c_double), ("degree", C.c_int32), ("a", C.POINTER(C.c_double)),
+                ("n_pairs", C.c_int32), ("pairs", C.POINTER(C.c_int32)), ("bpair", C.POINTER(C.c_double))]
 
 
 _dp = C.POINTER(C.c_double)
@@ -57,8 +58,8 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB):
-                build(force=False)
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)  # missing, or older than its source
             L = C.CDLL(_LIB)
             L.or_philox4x32_10.argtypes = [_up, _up, _up]
             L.or_uniform24.argtypes = [C.c_uint32]
@@ -114,8 +115,15 @@ class Model:
         poly = getattr(m, "poly", None)
         self.degree = 1 if poly is None else int(poly.shape[1]) + 1
         self.a = None if poly is None else np.ascontiguousarray(poly, np.float64)
+        bil = getattr(m, "bilinear", None) or []
+        self.n_pairs = len(bil)
+        self.pairs = np.ascontiguousarray([[int(i), int(j)] for i, j, _ in bil] or np.zeros((0, 2)), np.int32)
+        self.bpair = np.ascontiguousarray([np.asarray(B, np.float64) for _, _, B in bil]
+                                          or np.zeros((0, self.n, self.n)), np.float64)
         self.c = _Model(self.n, self.M, _d(self.mass), _d(self.omega), _d(self.v0), _d(self.k),
-                        float(m.hbar), self.degree, _d(self.a) if self.a is not None else None)
+                        float(m.hbar), self.degree, _d(self.a) if self.a is not None else None,
+                        self.n_pairs, _i(self.pairs) if self.n_pairs else None,
+                        _d(self.bpair) if self.n_pairs else None)
 
     @property
     def ref(self):
@@ -172,11 +180,12 @@ def mean_force(m, q, U, a, b):
 
 
 def velocity_nac(m, p, E, U, q=None):
-    """v.d for all pairs; q is needed when the model has powers above 1."""
+    """v.d for all pairs; q is needed when the model has powers above 1 or
+    cross-mode bilinear terms."""
     mm = _model(m)
     vd = np.zeros((mm.n, mm.n))
-    if q is None and mm.degree > 1:
-        raise ValueError("velocity_nac of a model with higher powers needs q")
+    if q is None and (mm.degree > 1 or mm.n_pairs):
+        raise ValueError("velocity_nac of a model with higher powers or bilinear terms needs q")
     qp = _d(np.ascontiguousarray(q, np.float64)) if q is not None else None
     lib().or_velocity_nac(mm.ref, qp, _d(np.ascontiguousarray(p, np.float64)),
                           _d(np.ascontiguousarray(E, np.float64)),

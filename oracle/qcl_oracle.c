@@ -61,6 +61,9 @@ typedef struct {
     double hbar;
     int32_t degree;       /* highest power of q_j in V(q): 1 (linear) .. 4 */
     const double *a;      /* [M][degree-1][N][N]: A_jk for k = 2..degree, or NULL */
+    int32_t n_pairs;      /* bilinear terms q_i q_j B_p, i != j (0: none) */
+    const int32_t *pairs; /* [n_pairs][2]: the modes (i, j) of each term */
+    const double *bpair;  /* [n_pairs][N][N]: B_p */
 } or_model;
 
 /* ------------------------------------------------------------------ */
@@ -217,7 +220,8 @@ static double poly_entry(const or_model *m, int j, int k, int i)
     return m->a[((size_t)j * (m->degree - 1) + (k - 2)) * n * n + i];
 }
 
-/* Electronic Hamiltonian V(q) = V0 + sum_j [q_j K_j + sum_{k=2..D} q_j^k A_jk]. */
+/* Electronic Hamiltonian V(q) = V0 + sum_j [q_j K_j + sum_{k=2..D} q_j^k A_jk]
+ * + sum_p q_{i_p} q_{j_p} B_p (cross-mode bilinear terms). */
 void or_potential(const or_model *m, const double *q, double *V)
 {
     int n = m->n_states, M = m->n_modes;
@@ -231,20 +235,32 @@ void or_potential(const or_model *m, const double *q, double *V)
                 v += qk * poly_entry(m, j, k, i);
             }
         }
+        for (int pr = 0; pr < m->n_pairs; ++pr)
+            v += q[m->pairs[2 * pr]] * q[m->pairs[2 * pr + 1]] * m->bpair[(size_t)pr * n * n + i];
         V[i] = v;
     }
 }
 
-/* dV/dq_j = K_j + sum_{k=2..D} k q_j^(k-1) A_jk, an N x N matrix. */
-static void mode_gradient(const or_model *m, int j, double qj, double *Gj)
+/* dV/dq_j = K_j + sum_{k=2..D} k q_j^(k-1) A_jk + sum over the bilinear
+ * terms that hold mode j of (the other mode's q) B_p, an N x N matrix.
+ * q may be NULL for a linear model. */
+static void mode_gradient(const or_model *m, int j, const double *q, double *Gj)
 {
     int n = m->n_states;
+    const double qj = q ? q[j] : 0.0;
     for (int i = 0; i < n * n; ++i) {
         double g = m->k[(size_t)j * n * n + i];
         double qk = 1.0;
         for (int k = 2; k <= m->degree; ++k) {
             qk *= qj;
             g += k * qk * poly_entry(m, j, k, i);
+        }
+        for (int pr = 0; q && pr < m->n_pairs; ++pr) {
+            const int pi = m->pairs[2 * pr], pj = m->pairs[2 * pr + 1];
+            if (pi == j)
+                g += q[pj] * m->bpair[(size_t)pr * n * n + i];
+            if (pj == j)
+                g += q[pi] * m->bpair[(size_t)pr * n * n + i];
         }
         Gj[i] = g;
     }
@@ -287,7 +303,7 @@ void or_mean_force(const or_model *m, const double *q, const double *U, int a, i
     int n = m->n_states;
     double G[OR_MAXN * OR_MAXN], Gj[OR_MAXN * OR_MAXN];
     for (int j = 0; j < m->n_modes; ++j) {
-        mode_gradient(m, j, q[j], Gj);
+        mode_gradient(m, j, q, Gj);
         rotate_to_adiabatic(n, U, Gj, G);
         F[j] = -m->mass[j] * m->omega[j] * m->omega[j] * q[j]
                - 0.5 * (G[a * n + a] + G[b * n + b]);
@@ -305,7 +321,7 @@ void or_velocity_nac(const or_model *m, const double *q, const double *p, const 
     for (int i = 0; i < n * n; ++i)
         Kv[i] = 0.0;
     for (int j = 0; j < m->n_modes; ++j) {
-        mode_gradient(m, j, q ? q[j] : 0.0, Gj);
+        mode_gradient(m, j, q, Gj);
         for (int i = 0; i < n * n; ++i)
             Kv[i] += (p[j] / m->mass[j]) * Gj[i];
     }
@@ -580,8 +596,13 @@ int or_propagate(const or_model *m, int64_t n_traj, int64_t traj_offset, int64_t
                  int32_t n_out, double *sums, uint32_t *flags, int64_t *n_fallback)
 {
     int n = m->n_states, M = m->n_modes, nslot = 8 * n * n;
-    if (n < 2 || n > OR_MAXN || M < 1 || M > OR_MAXM || cadence < 1 || n_steps < 0)
+    if (n < 2 || n > OR_MAXN || M < 1 || M > OR_MAXM || cadence < 1 || n_steps < 0 || m->n_pairs < 0)
         return 1;
+    for (int pr = 0; pr < m->n_pairs; ++pr) {
+        const int pi = m->pairs[2 * pr], pj = m->pairs[2 * pr + 1];
+        if (pi < 0 || pj < 0 || pi >= M || pj >= M || pi == pj)
+            return 1;
+    }
     int64_t n_chunks = (n_traj + OR_CHUNK - 1) / OR_CHUNK;
     size_t per = (size_t)n_out * nslot;
     double *part = (double *)calloc((size_t)(n_chunks > 0 ? n_chunks : 1) * per, sizeof(double));

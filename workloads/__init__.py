@@ -32,7 +32,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -54,6 +54,8 @@ class LVCModel:
     hbar: float = 1.0
     time_unit_fs: Optional[float] = None  # fs per internal time unit (eV models)
     poly: Optional[np.ndarray] = None  # [M, D-1, N, N]: A_jk for k = 2..D (D <= 4), each symmetric
+    # cross-mode bilinear terms q_i q_j B (i != j), B [N, N] symmetric
+    bilinear: Optional[List[Tuple[int, int, np.ndarray]]] = None
 
     def __post_init__(self):
         self.mass = np.ascontiguousarray(self.mass, dtype=np.float64)
@@ -62,6 +64,8 @@ class LVCModel:
         self.k = np.ascontiguousarray(self.k, dtype=np.float64)
         if self.poly is not None:
             self.poly = np.ascontiguousarray(self.poly, dtype=np.float64)
+        if self.bilinear is not None:
+            self.bilinear = [(int(i), int(j), np.ascontiguousarray(B, dtype=np.float64)) for i, j, B in self.bilinear]
 
     @property
     def degree(self) -> int:
@@ -285,6 +289,44 @@ def random_poly(index: int, n_states: int = 3, n_modes: int = 5, degree: int = 4
     init = InitSpec(kT=0.3, q0=np.zeros(M), state=N - 1)
     seed = (key << 32) | (index & 0xFFFFFFFF)
     return Workload(model, init, RunSpec(n_traj, n_steps, dt, cadence, seed))
+
+
+def pyrazine_bilinear(n_traj: int = 1_000_000, n_steps: int = 200, dt_fs: float = 0.5,
+                      cadence: int = 2, seed: int = 9) -> Workload:
+    """``pyrazine_qvc`` with two cross-mode bilinear terms: a state-dependent
+    mixing of the tuning modes nu1 and nu6a, q_1 q_6a diag(-0.006, 0.008),
+    and a bilinear part of the interstate coupling, q_6a q_10a (0.012 sigma_x)
+    (eV, dimensionless coordinates)."""
+    base = pyrazine_qvc(n_traj=n_traj, n_steps=n_steps, dt_fs=dt_fs, cadence=cadence, seed=seed)
+    m = base.model
+    bil = [(0, 1, np.diag([-0.006, 0.008])), (1, 2, np.array([[0.0, 0.012], [0.012, 0.0]]))]
+    model = LVCModel(name="pyrazine_bilinear", mass=m.mass, omega=m.omega, v0=m.v0, k=m.k, hbar=m.hbar,
+                     time_unit_fs=m.time_unit_fs, poly=m.poly, bilinear=bil)
+    return Workload(model, base.init, base.run)
+
+
+def random_bilinear(index: int, n_states: int = 3, n_modes: int = 5, n_pairs: int = 3, degree: int = 2,
+                    key: int = 8, n_traj: int = 2000, n_steps: int = 100, dt: float = 0.05,
+                    cadence: int = 10) -> Workload:
+    """``random_poly`` with ``n_pairs`` cross-mode bilinear terms on distinct
+    random mode pairs, each coupling a dense random symmetric matrix small
+    against the harmonic force constants (the surfaces stay confining)."""
+    wl = random_poly(index, n_states=n_states, n_modes=n_modes, degree=degree, key=key, n_traj=n_traj,
+                     n_steps=n_steps, dt=dt, cadence=cadence)
+    rng = np.random.Generator(np.random.Philox(key=[key + 1000, index]))
+    N, M = int(n_states), int(n_modes)
+    pairs = set()
+    while len(pairs) < n_pairs:
+        i, j = sorted(int(x) for x in rng.choice(M, size=2, replace=False))
+        pairs.add((i, j))
+    bil = []
+    for i, j in sorted(pairs):
+        a = rng.uniform(-0.04, 0.04, size=(N, N))
+        bil.append((i, j, 0.5 * (a + a.T)))
+    m = wl.model
+    wl.model = LVCModel(name=f"random_bilinear_{key}_{index}", mass=m.mass, omega=m.omega, v0=m.v0, k=m.k,
+                        poly=m.poly, bilinear=bil)
+    return wl
 
 
 def batched_instances(n_instances: int = 256, key: int = 4, **kw) -> List[Workload]:
