@@ -23,7 +23,7 @@ two.  Two further legs are reported in the same line:
   convergence  the pyrazine-like and spin-boson (kT 0.2) models at 1e6, 1e7
            and 1e8 walkers: horizons of agreement and the decay rate;
   poly     models with higher powers of each mode (state-dependent
-           frequencies, anharmonicity) on the general kernels;
+           frequencies, anharmonicity) and with cross-mode bilinear terms;
   many_states  6- and 8-state models on the general kernels.
   resample qcl_resample of the headline ensemble (1e7 walkers) against HBM
            bandwidth, and the replica spread of P(t) with and without
@@ -213,13 +213,18 @@ def poly_leg(P, torch):
     """Models with higher powers of each mode (general kernels, every
     coupling direction kept): the pyrazine-like model with state-dependent
     frequencies and a quartic tuning mode (1e7 walkers, 200 steps of 0.5 fs)
-    and a 3-state, 16-mode quartic model (1e6 walkers, 200 steps), both
-    precisions; walker-steps/s of sample + propagate + reduce and the
-    propagate kernel's own time."""
+    and a 3-state, 16-mode quartic model (1e6 walkers, 200 steps), then the
+    same pyrazine-like model with two cross-mode bilinear terms (1e7
+    walkers, 200 steps) and a 3-state, 16-mode quartic model with four
+    (1e6 walkers), both precisions; walker-steps/s of sample + propagate +
+    reduce and the propagate kernel's own time."""
     import workloads as W
     cases = (("pyrazine_qvc", W.pyrazine_qvc(n_traj=10_000_000, n_steps=200, cadence=10)),
              ("poly_n3_m16_d4", W.random_poly(20, n_states=3, n_modes=16, degree=4, n_traj=1_000_000,
-                                               n_steps=200, cadence=10, dt=0.02)))
+                                               n_steps=200, cadence=10, dt=0.02)),
+             ("pyrazine_bilinear", W.pyrazine_bilinear(n_traj=10_000_000, n_steps=200, cadence=10)),
+             ("bilinear_n3_m16_d4_p4", W.random_bilinear(20, n_states=3, n_modes=16, n_pairs=4, degree=4,
+                                                         n_traj=1_000_000, n_steps=200, cadence=10, dt=0.02)))
     return _model_runs(P, torch, cases)
 
 
@@ -298,7 +303,7 @@ def _model_runs(P, torch, cases):
         r = wl.run
         model = P.Model(wl.model)
         row = {"model": name, "n_states": model.n_states, "n_modes": model.n_modes, "degree": model.degree,
-               "rank": model.rank, "n_traj": r.n_traj, "n_steps": r.n_steps}
+               "pairs": model.n_pairs, "rank": model.rank, "n_traj": r.n_traj, "n_steps": r.n_steps}
         for prec in ("fp32", "fp64"):
             ms_step, ms_prop, _ = time_path(P, torch, model, wl, prec, r.n_traj, 3, 1)
             row[prec] = {"value": r.n_traj * r.n_steps / (ms_step / 1e3), "ms": ms_step, "propagate_ms": ms_prop,

@@ -187,15 +187,49 @@ typedef struct {
 } qcl_poly_desc;
 
 /* As qcl_create_model, with the higher powers of poly (read during the
- * call only).  Such a model always runs on the general-N kernels (also for
- * N = 2), with every coupling direction kept (rank padded to N(N+1)/2) and
- * the default register budget (qcl_prop_desc.occupancy is ignored).
+ * call only).  Two-state models with at most 8 modes run on the two-state
+ * closed-form kernels; the others on the general-N kernels with every
+ * coupling direction kept (rank padded to N(N+1)/2).  Both use the default
+ * register budget (qcl_prop_desc.occupancy is ignored).
  * Errors: as qcl_create_model; INVALID_ARG also for degree outside [2, 4],
  * a NULL poly->a, non-finite or asymmetric A_jk. */
 qcl_status qcl_create_model_poly(const qcl_model_desc *desc, const qcl_poly_desc *poly, qcl_model *out);
 
+#define QCL_MAX_PAIRS 4          /* bilinear terms per model */
+#define QCL_MAX_MODES_BILINEAR 32
+
+/* Cross-mode bilinear terms (the same extension of Eq. 1's potential as
+ * qcl_poly_desc, with couplings between two modes, e.g. the Duschinsky
+ * mixing of a quadratic vibronic-coupling model):
+ *   V(q) += sum_p q_{i_p} q_{j_p} B_p,   dV/dq_i += q_j B_p, dV/dq_j += q_i B_p.
+ * The Wigner initial state stays that of the harmonic wells (m_j, w_j). */
+typedef struct {
+    int32_t n_pairs;      /* 1 .. QCL_MAX_PAIRS */
+    int32_t reserved;
+    const int32_t *pairs; /* host [n_pairs][2]: modes (i, j), 0 <= i, j < M, i != j */
+    const double *b;      /* host [n_pairs][N][N] row-major: B_p, each symmetric to 1e-12 */
+} qcl_bilinear_desc;
+
+/* As qcl_create_model_poly (poly may be NULL: no powers above 1), with the
+ * bilinear terms of bil (read during the call only).  Such a model runs on
+ * the general-N kernels for N = 2..4 (also N = 2), every coupling direction
+ * kept, at most QCL_MAX_MODES_BILINEAR modes; qcl_model_degree reports at
+ * least 2.  On the device each term is split exactly as q_i q_j =
+ * ((q_i + q_j)^2 - (q_i - q_j)^2) / 4, two squared mode combinations with
+ * coefficients +-1.
+ * Errors: as qcl_create_model_poly; INVALID_ARG also for a NULL bil, pairs
+ * or b, n_pairs outside [1, QCL_MAX_PAIRS], a mode index out of range or
+ * i == j, non-finite or asymmetric B_p; UNSUPPORTED for more than 4 states
+ * or more than QCL_MAX_MODES_BILINEAR modes. */
+qcl_status qcl_create_model_bilinear(const qcl_model_desc *desc, const qcl_poly_desc *poly,
+                                     const qcl_bilinear_desc *bil, qcl_model *out);
+
+/* Number of bilinear terms of a model (0 for NULL or none). */
+int32_t qcl_model_pairs(qcl_model model);
+
 /* Highest power of q_j in the model's potential: 1 for a linear-vibronic
- * model, 2..4 for one built by qcl_create_model_poly, 0 for NULL. */
+ * model, 2..4 for one built by qcl_create_model_poly (at least 2 for one
+ * built by qcl_create_model_bilinear), 0 for NULL. */
 int32_t qcl_model_degree(qcl_model model);
 
 /* Frees a model (NULL is accepted).  Work that uses it must be complete. */

@@ -271,7 +271,8 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
         const qcl_model_s &m = *it.model;
         // general kernels are specialised on padded modes and rank bucket
         const int poly = m.degree > 1 ? 1 : 0;
-        const int modes = m.fast2 ? m.m + 16 * poly : qcl::padded_modes(m.m) * 64 + m.rank_pad + 32 * poly;
+        const int modes = m.fast2 ? m.m + 16 * poly
+                                  : qcl::padded_modes(m.m) * 64 + m.rank_pad + 32 * poly + 16 * (m.n_pairs > 0);
         BatchClass *c = nullptr;
         const int occ = qcl::occupancy_variant(m, it.ens->prec, it.prop.occupancy);
         for (BatchClass &k : plan.classes)
@@ -323,9 +324,10 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
     return QCL_OK;
 }
 
-// Builds a model (linear when poly is NULL); see qcl_create_model and
-// qcl_create_model_poly.
-qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_model *out)
+// Builds a model (linear when poly and bil are NULL); see qcl_create_model,
+// qcl_create_model_poly and qcl_create_model_bilinear.
+qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, const qcl_bilinear_desc *bil,
+                        qcl_model *out)
 {
     if (!d || !out)
         return fail(QCL_ERR_INVALID_ARG, "NULL argument");
@@ -350,7 +352,8 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
     for (int j = 0; j < M; ++j)
         if (!symmetric(d->k + (size_t)j * n * n, n))
             return fail(QCL_ERR_INVALID_ARG, "K_%d is not symmetric", j);
-    const int D = poly ? poly->degree : 1;
+    // a bilinear model runs on the kernels of models with higher powers
+    const int D = poly ? poly->degree : bil ? 2 : 1;
     if (n > 4 && M > QCL_MAX_MODES_MANY)
         return fail(QCL_ERR_UNSUPPORTED, "models with %d states support at most %d modes (got %d)", n,
                     QCL_MAX_MODES_MANY, M);
@@ -368,6 +371,27 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
                 if (!symmetric(poly->a + ((size_t)j * (D - 1) + (k - 2)) * n * n, n))
                     return fail(QCL_ERR_INVALID_ARG, "A_%d,%d is not symmetric", j, k);
     }
+    if (bil) {
+        if (bil->n_pairs < 1 || bil->n_pairs > QCL_MAX_PAIRS)
+            return fail(QCL_ERR_INVALID_ARG, "n_pairs %d outside [1, %d]", bil->n_pairs, QCL_MAX_PAIRS);
+        if (!bil->pairs || !bil->b)
+            return fail(QCL_ERR_INVALID_ARG, "bil->pairs or bil->b is NULL");
+        for (int p = 0; p < bil->n_pairs; ++p) {
+            const int i = bil->pairs[2 * p], j = bil->pairs[2 * p + 1];
+            if (i < 0 || j < 0 || i >= M || j >= M || i == j)
+                return fail(QCL_ERR_INVALID_ARG, "bilinear term %d: modes (%d, %d) invalid", p, i, j);
+        }
+        if (!finite_all(bil->b, (int64_t)bil->n_pairs * n * n))
+            return fail(QCL_ERR_INVALID_ARG, "non-finite bilinear coefficient");
+        for (int p = 0; p < bil->n_pairs; ++p)
+            if (!symmetric(bil->b + (size_t)p * n * n, n))
+                return fail(QCL_ERR_INVALID_ARG, "B_%d is not symmetric", p);
+        if (n > 4)
+            return fail(QCL_ERR_UNSUPPORTED, "bilinear terms need at most 4 states (got %d)", n);
+        if (M > QCL_MAX_MODES_BILINEAR)
+            return fail(QCL_ERR_UNSUPPORTED, "bilinear models support at most %d modes (got %d)",
+                        QCL_MAX_MODES_BILINEAR, M);
+    }
 
     qcl_model_s *m = new (std::nothrow) qcl_model_s();
     if (!m)
@@ -382,7 +406,14 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
     m->degree = D;
     if (poly)
         m->poly.assign(poly->a, poly->a + (size_t)M * (D - 1) * n * n);
-    m->fast2 = (n == 2 && M <= qcl::kMaxFastModes);
+    else if (D > 1)
+        m->poly.assign((size_t)M * (D - 1) * n * n, 0.0);
+    if (bil) {
+        m->n_pairs = bil->n_pairs;
+        m->pairs.assign(bil->pairs, bil->pairs + 2 * bil->n_pairs);
+        m->bpair.assign(bil->b, bil->b + (size_t)bil->n_pairs * n * n);
+    }
+    m->fast2 = (n == 2 && M <= qcl::kMaxFastModes && !bil);
     // energy scale: |V0| plus each mode's coupling over its zero-point-ish length
     double scale = 0.0;
     for (int i = 0; i < n * n; ++i)
@@ -401,6 +432,14 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
                 ak += std::fabs(m->poly[((size_t)j * (D - 1) + (k - 2)) * n * n + i]);
             scale += ak * lk;
         }
+    }
+    for (int p = 0; p < m->n_pairs; ++p) {
+        const int i = m->pairs[2 * p], j = m->pairs[2 * p + 1];
+        const double li = 1.0 / (m->omega[i] * std::sqrt(m->mass[i])), lj = 1.0 / (m->omega[j] * std::sqrt(m->mass[j]));
+        double bp = 0.0;
+        for (int e = 0; e < n * n; ++e)
+            bp += std::fabs(m->bpair[(size_t)p * n * n + e]);
+        scale += bp * li * lj;
     }
     m->energy_scale = scale > 0.0 ? scale : 1.0;
     // two-state constants (closed-form kernels)
@@ -528,7 +567,27 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_
                 for (int k = 0; k < 4; ++k)
                     gen.push_back((k + 1) * c[k]);
             }
+            if (m->n_pairs > 0)  // coefficients of mode j in the squared combinations
+                for (int sq = 0; sq < qcl::kSq; ++sq) {
+                    const int p = sq / 2;
+                    double cj = 0.0;
+                    if (real && p < m->n_pairs) {
+                        if (m->pairs[2 * p] == j)
+                            cj = 1.0;
+                        if (m->pairs[2 * p + 1] == j)
+                            cj = (sq % 2) ? -1.0 : 1.0;
+                    }
+                    gen.push_back(cj);
+                }
         }
+        if (m->n_pairs > 0)  // slot weights: q_i q_j B = (B/4) (q_i + q_j)^2 - (B/4) (q_i - q_j)^2, as lambda y^2 / 2
+            for (int sq = 0; sq < qcl::kSq; ++sq) {
+                const int p = sq / 2;
+                for (int a = 0; a < n; ++a)
+                    for (int b = a; b < n; ++b)
+                        gen.push_back(p < m->n_pairs ? ((sq % 2) ? -0.5 : 0.5) * m->bpair[(size_t)p * n * n + a * n + b]
+                                                     : 0.0);
+            }
     }
     while (packed.size() % 32)
         packed.push_back(0.0);
@@ -565,7 +624,7 @@ extern "C" {
 
 const char *qcl_last_error(void) { return g_last_error.c_str(); }
 
-qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out) { return create_model(d, nullptr, out); }
+qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out) { return create_model(d, nullptr, nullptr, out); }
 
 qcl_status qcl_create_model_poly(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_model *out)
 {
@@ -574,8 +633,21 @@ qcl_status qcl_create_model_poly(const qcl_model_desc *d, const qcl_poly_desc *p
             *out = nullptr;
         return fail(QCL_ERR_INVALID_ARG, "poly is NULL");
     }
-    return create_model(d, poly, out);
+    return create_model(d, poly, nullptr, out);
 }
+
+qcl_status qcl_create_model_bilinear(const qcl_model_desc *d, const qcl_poly_desc *poly, const qcl_bilinear_desc *bil,
+                                     qcl_model *out)
+{
+    if (!bil) {
+        if (out)
+            *out = nullptr;
+        return fail(QCL_ERR_INVALID_ARG, "bil is NULL");
+    }
+    return create_model(d, poly, bil, out);
+}
+
+int32_t qcl_model_pairs(qcl_model m) { return m ? m->n_pairs : 0; }
 
 int32_t qcl_model_degree(qcl_model m) { return m ? m->degree : 0; }
 

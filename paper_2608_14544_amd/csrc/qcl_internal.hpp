@@ -70,11 +70,15 @@ struct GenConst {
     const R *v0;
     const R *basis;
     const R *modes;
+    const R *sq;  // bilinear models: [kSq][RB] slot weights of the squared mode combinations
     R dt, hdt;
     double dt_hbar;
     R gap_thr;  // binary32 path: gaps below this are re-solved in binary64
     R rot_eps;  // Jacobi: rotate while |a_pq| > rot_eps * ||A||_F
 };
+
+// squared mode combinations of a bilinear model (two per term)
+constexpr int kSq = 2 * QCL_MAX_PAIRS;
 
 inline int padded_modes(int m)
 {
@@ -186,6 +190,9 @@ struct qcl_model_s {
     int32_t rank_pad = 1;       // rank bucket RB the general kernels are specialised on
     int32_t degree = 1;         // highest power of q_j in V(q) (> 1: kernels_poly{N}.hip)
     std::vector<double> poly;   // [M][degree-1][N][N] higher-power matrices A_jk (k >= 2)
+    int32_t n_pairs = 0;        // bilinear terms (> 0: kernels_bil{N}.hip)
+    std::vector<int32_t> pairs; // [n_pairs][2] modes of each term
+    std::vector<double> bpair;  // [n_pairs][N][N] B_p
     bool fast2 = false;         // two-state closed-form kernels apply (N = 2, M <= 8)
 };
 
@@ -199,6 +206,8 @@ template <int K>
 struct int_ {};  // general kernels of K states, linear couplings (kernels_gen{K}.hip)
 template <int K>
 struct poly_ {};  // general kernels of K states, higher powers (kernels_poly{K}.hip)
+template <int K>
+struct bil_ {};   // general kernels of K states, higher powers and bilinear terms (kernels_bil{K}.hip)
 
 #define QCL_DECLARE_GENERAL(TAG)                                                                              \
     hipError_t launch_sample_general_n(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,   \
@@ -219,6 +228,9 @@ QCL_DECLARE_GENERAL(int_<8>)
 QCL_DECLARE_GENERAL(poly_<2>)
 QCL_DECLARE_GENERAL(poly_<3>)
 QCL_DECLARE_GENERAL(poly_<4>)
+QCL_DECLARE_GENERAL(bil_<2>)
+QCL_DECLARE_GENERAL(bil_<3>)
+QCL_DECLARE_GENERAL(bil_<4>)
 #undef QCL_DECLARE_GENERAL
 
 // Calls fn with the tag of the general kernels a model runs on; `none` when
@@ -226,6 +238,14 @@ QCL_DECLARE_GENERAL(poly_<4>)
 template <typename Ret, typename F>
 inline Ret with_general(const qcl_model_s &m, Ret none, F &&fn)
 {
+    if (m.n_pairs > 0) {
+        switch (m.n) {
+        case 2: return fn(bil_<2>{});
+        case 3: return fn(bil_<3>{});
+        case 4: return fn(bil_<4>{});
+        default: return none;
+        }
+    }
     if (m.degree > 1) {
         switch (m.n) {
         case 2: return fn(poly_<2>{});

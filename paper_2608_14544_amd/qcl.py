@@ -56,6 +56,11 @@ class qcl_poly_desc(C.Structure):
     _fields_ = [("degree", C.c_int32), ("reserved", C.c_int32), ("a", C.POINTER(C.c_double))]
 
 
+class qcl_bilinear_desc(C.Structure):
+    _fields_ = [("n_pairs", C.c_int32), ("reserved", C.c_int32), ("pairs", C.POINTER(C.c_int32)),
+                ("b", C.POINTER(C.c_double))]
+
+
 class qcl_init_desc(C.Structure):
     _fields_ = [("kT", C.c_double), ("q0", C.POINTER(C.c_double)),
                 ("state", C.c_int32), ("basis", C.c_int32)]
@@ -80,8 +85,8 @@ class qcl_batch_item(C.Structure):
                 ("partials", C.c_void_p)]
 
 
-EXPORTS = ("qcl_create_model", "qcl_create_model_poly", "qcl_destroy_model", "qcl_model_states",
-           "qcl_model_modes", "qcl_model_rank", "qcl_model_degree",
+EXPORTS = ("qcl_create_model", "qcl_create_model_poly", "qcl_create_model_bilinear", "qcl_destroy_model",
+           "qcl_model_states", "qcl_model_modes", "qcl_model_rank", "qcl_model_degree", "qcl_model_pairs",
            "qcl_ensemble_bytes", "qcl_ensemble_bind", "qcl_partials_bytes",
            "qcl_sample_initial", "qcl_propagate", "qcl_batch_workspace_bytes", "qcl_propagate_batch",
            "qcl_reduce_observables", "qcl_resample_workspace_bytes", "qcl_resample", "qcl_last_error")
@@ -104,6 +109,10 @@ def load_library(path: str = LIB_PATH):
         L.qcl_create_model_poly.argtypes = [C.POINTER(qcl_model_desc), C.POINTER(qcl_poly_desc), C.POINTER(vp)]
         L.qcl_model_degree.argtypes = [vp]
         L.qcl_model_degree.restype = i32
+        L.qcl_create_model_bilinear.argtypes = [C.POINTER(qcl_model_desc), C.POINTER(qcl_poly_desc),
+                                                C.POINTER(qcl_bilinear_desc), C.POINTER(vp)]
+        L.qcl_model_pairs.argtypes = [vp]
+        L.qcl_model_pairs.restype = i32
         L.qcl_destroy_model.argtypes = [vp]
         L.qcl_model_states.argtypes = [vp]
         L.qcl_model_states.restype = i32
@@ -166,18 +175,29 @@ class Model:
                               _dptr(v0), _dptr(k), float(lvc.hbar))
         h = C.c_void_p()
         poly = getattr(lvc, "poly", None)
-        if poly is None:
-            _check(L.qcl_create_model(C.byref(desc), C.byref(h)))
-        else:
+        bil = getattr(lvc, "bilinear", None)
+        pd = None
+        if poly is not None:
             a = np.ascontiguousarray(poly, np.float64)
             self._arrays.append(a)
             pd = qcl_poly_desc(int(a.shape[1]) + 1, 0, _dptr(a))
+        if bil:
+            pairs = np.ascontiguousarray([[int(i), int(j)] for i, j, _ in bil], np.int32)
+            b = np.ascontiguousarray(np.stack([np.asarray(B, np.float64) for _, _, B in bil]), np.float64)
+            self._arrays += [pairs, b]
+            bd = qcl_bilinear_desc(len(bil), 0, pairs.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(b))
+            _check(L.qcl_create_model_bilinear(C.byref(desc), C.byref(pd) if pd is not None else None,
+                                               C.byref(bd), C.byref(h)))
+        elif pd is not None:
             _check(L.qcl_create_model_poly(C.byref(desc), C.byref(pd), C.byref(h)))
+        else:
+            _check(L.qcl_create_model(C.byref(desc), C.byref(h)))
         self.handle = h
         self.n_states = int(L.qcl_model_states(h))
         self.n_modes = int(L.qcl_model_modes(h))
         self.rank = int(L.qcl_model_rank(h))
         self.degree = int(L.qcl_model_degree(h))
+        self.n_pairs = int(L.qcl_model_pairs(h))
 
     def close(self):
         if getattr(self, "handle", None):

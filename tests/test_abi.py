@@ -155,3 +155,49 @@ def test_resample_validation_on_host():
     assert L.qcl_resample_workspace_bytes(1 << 31, C.byref(b)) == qcl.QCL_ERR_INVALID_ARG
     assert L.qcl_resample_workspace_bytes(10, None) == qcl.QCL_ERR_INVALID_ARG
     assert L.qcl_resample(None, None, None, 0, None, 0, None) == qcl.QCL_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("patch", ["zero_pairs", "five_pairs", "null_pairs", "null_b", "same_mode", "out_of_range",
+                                   "negative", "nan", "asym"])
+def test_create_model_bilinear_rejects_invalid(patch):
+    """Invalid bilinear terms are rejected on the host (INVALID_ARG)."""
+    qcl, L = _lib()
+    lvc = W.pyrazine_ci().model
+    d, keep = _desc(qcl, lvc)
+    n_pairs = {"zero_pairs": 0, "five_pairs": 5}.get(patch, 2)
+    pairs = np.array([[0, 1], [1, 2]] + [[0, 2]] * 3, np.int32)[:max(n_pairs, 1)]
+    b = np.zeros((max(n_pairs, 1), 2, 2))
+    if patch == "same_mode":
+        pairs[1] = [2, 2]
+    if patch == "out_of_range":
+        pairs[0] = [0, 3]
+    if patch == "negative":
+        pairs[1] = [-1, 0]
+    if patch == "nan":
+        b[0, 1, 1] = np.nan
+    if patch == "asym":
+        b[1, 0, 1] = 0.2
+    bd = qcl.qcl_bilinear_desc(n_pairs, 0,
+                               None if patch == "null_pairs" else pairs.ctypes.data_as(C.POINTER(C.c_int32)),
+                               None if patch == "null_b" else b.ctypes.data_as(C.POINTER(C.c_double)))
+    h = C.c_void_p()
+    st = L.qcl_create_model_bilinear(C.byref(d), None, C.byref(bd), C.byref(h))
+    assert st == qcl.QCL_ERR_INVALID_ARG, (patch, st, L.qcl_last_error())
+    assert not h.value and L.qcl_last_error()
+    assert L.qcl_create_model_bilinear(C.byref(d), None, None, C.byref(h)) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_model_pairs(None) == 0
+
+
+def test_bilinear_limits_on_host():
+    """Bilinear terms: at most 4 states and 32 modes (UNSUPPORTED)."""
+    qcl, L = _lib()
+    pairs = np.array([[0, 1]], np.int32)
+    for n, M in ((5, 4), (3, 33)):
+        lvc = W.random_lvc(70 + n, n_states=n, n_modes=M).model
+        d, keep = _desc(qcl, lvc)
+        b = np.zeros((1, n, n))
+        bd = qcl.qcl_bilinear_desc(1, 0, pairs.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   b.ctypes.data_as(C.POINTER(C.c_double)))
+        h = C.c_void_p()
+        assert L.qcl_create_model_bilinear(C.byref(d), None, C.byref(bd), C.byref(h)) == qcl.QCL_ERR_UNSUPPORTED
+        assert not h.value

@@ -1,0 +1,184 @@
+"""Models with cross-mode bilinear terms (V(q) += sum_p q_i q_j B_p, with or
+without higher powers of each mode) on the general kernels: binary64
+walkers against the oracle, binary32 ensembles, the linear rule, bitwise
+slicing and batching, ragged sizes and the full-size workload of the bench.
+
+The device splits each term as ((q_i + q_j)^2 - (q_i - q_j)^2) / 4, the
+oracle evaluates q_i q_j B_p directly: the two agree to rounding, so the
+binary64 tolerances are those of the other general-kernel models."""
+import numpy as np
+import pytest
+
+import workloads as W
+from test_gpu_batch import _assert_same, _batched, _solo
+from test_gpu_parity import _oracle_state, compare_walkers, ensemble_close, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2608_14544_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+CASES = {
+    "pyrazine_bilinear": lambda: W.pyrazine_bilinear(n_traj=2000, n_steps=60, cadence=6),
+    "n2_m3_p2": lambda: W.random_bilinear(0, n_states=2, n_modes=3, n_pairs=2),
+    "n3_m5_p4_d3": lambda: W.random_bilinear(1, n_states=3, n_modes=5, n_pairs=4, degree=3),
+    "n4_m4_p3_d4": lambda: W.random_bilinear(2, n_states=4, n_modes=4, n_pairs=3, degree=4),
+    "n3_m20_p4": lambda: W.random_bilinear(5, n_states=3, n_modes=20, n_pairs=4, n_traj=1000),
+}
+
+
+def test_model_pairs_and_degree(P):
+    m = P.Model(W.random_bilinear(1, n_states=3, n_modes=5, n_pairs=4, degree=3).model)
+    assert m.n_pairs == 4 and m.degree == 3
+    lin = W.pyrazine_ci().model
+    only = W.LVCModel(name="bil_only", mass=lin.mass, omega=lin.omega, v0=lin.v0, k=lin.k, hbar=lin.hbar,
+                      bilinear=[(0, 2, np.diag([0.01, -0.01]))])
+    m2 = P.Model(only)
+    assert m2.n_pairs == 1 and m2.degree == 2
+    assert P.Model(W.pyrazine_qvc().model).n_pairs == 0
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_bilinear_fp64_parity(P, name):
+    wl = CASES[name]()
+    out_g, st_g, s0_g, _ = gpu_run(P, wl)
+    out_o, st_o, s0_o, _ = oracle_run(wl)
+    compare_walkers(s0_g, s0_o, rtol=1e-11, label=name + " sample")
+    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label=name)
+    if nflip == 0:
+        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+
+
+def test_bilinear_only_model_fp64_parity(P):
+    """Bilinear terms without higher powers (the kernels take A = 0)."""
+    base = W.pyrazine_ci(n_traj=1500, n_steps=60, cadence=6)
+    lin = base.model
+    only = W.LVCModel(name="bil_only", mass=lin.mass, omega=lin.omega, v0=lin.v0, k=lin.k, hbar=lin.hbar,
+                      time_unit_fs=lin.time_unit_fs,
+                      bilinear=[(0, 1, np.diag([-0.01, 0.012])), (2, 0, np.array([[0.0, 0.015], [0.015, 0.0]]))])
+    wl = W.Workload(only, base.init, base.run)
+    out_g, st_g, _, _ = gpu_run(P, wl)
+    out_o, st_o, _, _ = oracle_run(wl)
+    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label="bilinear only")
+    if nflip == 0:
+        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+
+
+@pytest.mark.parametrize("name", ["pyrazine_bilinear", "n4_m4_p3_d4"])
+def test_bilinear_fp32_ensemble(P, name):
+    wl = CASES[name]()
+    wl.run.n_traj = 40_000
+    out_g, _, _, _ = gpu_run(P, wl, prec="fp32")
+    out_o, _, _, _ = oracle_run(wl)
+    d = np.abs(out_g[..., :2] - out_o[..., :2])
+    se = np.maximum(out_o[..., 2:], 1e-300)
+    print(name, "fp32 max abs err", d.max(), "max err/SE", (d / se).max(), flush=True)
+    assert np.all((d <= 1e-3) | (d <= 3 * se))
+
+
+def test_bilinear_linear_rule(P):
+    wl = CASES["n3_m5_p4_d3"]()
+    out_g, st_g, _, _ = gpu_run(P, wl, scheme=1)
+    out_o, st_o, _, fl_o = oracle_run(wl, scheme=1)
+    assert np.array_equal(st_g["flags"] & 8, np.asarray(fl_o) & 8)
+    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label="bilinear linear")
+    if nflip == 0:
+        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+
+
+@pytest.mark.parametrize("T", [0, 1, 255, 257])
+def test_bilinear_empty_and_ragged(P, T):
+    wl = W.random_bilinear(6, n_states=3, n_modes=4, n_pairs=2, n_traj=T, n_steps=40, cadence=7)
+    out_g, st_g, _, _ = gpu_run(P, wl)
+    if T == 0:
+        assert out_g is None and st_g["w"].size == 0
+        return
+    out_o, st_o, _, _ = oracle_run(wl)
+    compare_walkers(st_g, st_o, rtol=1e-9, label=f"bilinear T={T}")
+    assert ensemble_close(out_g, out_o, T)
+
+
+def test_bilinear_slicing_bitwise(P):
+    wl = W.random_bilinear(7, n_states=4, n_modes=6, n_pairs=4, degree=4, n_traj=3000, n_steps=90, cadence=10)
+    for prec in ("fp64", "fp32"):
+        out1, st1, _, _ = gpu_run(P, wl, prec=prec)
+        out2, st2, _, _ = gpu_run(P, wl, prec=prec, split=[13, 27, 50])
+        for k in st1:
+            assert np.array_equal(st1[k], st2[k]), (prec, k)
+        assert np.array_equal(out1, out2), prec
+
+
+def test_bilinear_in_mixed_batch_bitwise(P):
+    mix = [
+        (W.pyrazine_bilinear(n_traj=700, n_steps=60, cadence=6), "fp32", 0, 700),
+        (W.pyrazine_qvc(n_traj=500, n_steps=60, cadence=6), "fp32", 0, 500),
+        (W.random_bilinear(8, n_states=3, n_modes=5, n_pairs=3, degree=3, n_traj=300, n_steps=40, cadence=10),
+         "fp64", 1, 300),
+        (W.random_bilinear(9, n_states=4, n_modes=20, n_pairs=4, n_traj=257, n_steps=30, cadence=10), "fp32", 0, 257),
+        (W.random_lvc(8, n_states=3, n_modes=4, n_traj=400, n_steps=40, cadence=10), "fp32", 0, 400),
+    ]
+    solo = [_solo(P, wl, prec, scheme, T) for wl, prec, scheme, T in mix]
+    for slices in ((None,), (0.5, None)):
+        got = _batched(P, mix, slices)
+        for i, (a, b) in enumerate(zip(solo, got)):
+            _assert_same(a, b, f"bilinear batch item {i} slices {slices}")
+
+
+def test_bilinear_32_modes(P):
+    """The largest mode bucket of bilinear models (32 padded modes)."""
+    wl = W.random_bilinear(10, n_states=3, n_modes=30, n_pairs=4, degree=4, n_traj=300, n_steps=30, cadence=10)
+    out_g, st_g, _, _ = gpu_run(P, wl)
+    out_o, st_o, _, _ = oracle_run(wl)
+    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.01, label="bilinear M30")
+    if nflip == 0:
+        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+
+
+def test_bilinear_bench_configuration_full_size(P):
+    """The bench's bilinear workload at full size (pyrazine_bilinear, 1e7
+    walkers, 200 steps, one launch): binary64 walkers sampled across the
+    ensemble recomputed one by one by the oracle, and the binary32 run's
+    populations within 2e-3 of the binary64 run's while resolved."""
+    import torch
+    import oracle.core as oc
+    wl = W.pyrazine_bilinear(n_traj=10_000_000, n_steps=200, cadence=10)
+    r = wl.run
+    model = P.Model(wl.model)
+    outs = {}
+    for prec in ("fp64", "fp32"):
+        ens = P.Ensemble(model, r.n_traj, prec, zero=False)
+        part = P.Partials(model, r.n_traj, r.n_out)
+        P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
+        P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part)
+        outs[prec] = P.qcl_reduce_observables(model, part, r.n_traj).cpu().numpy()
+        if prec == "fp64":
+            t = ens.tensors()
+            ids = np.array([0, 255, 256, 1 << 20, 5_555_555, r.n_traj - 1])
+            g = {"q": t["q"][:, ids].cpu().numpy().T, "p": t["p"][:, ids].cpu().numpy().T,
+                 "U": t["u"][:, ids].cpu().numpy().T.reshape(-1, 2, 2), "w": t["w"][ids].cpu().numpy(),
+                 "phase": t["phase"][ids].cpu().numpy(), "a": t["a"][ids].cpu().numpy().astype(np.int32),
+                 "b": t["b"][ids].cpu().numpy().astype(np.int32)}
+        del ens, part
+        torch.cuda.empty_cache()
+    m = oc.Model(wl.model)
+    o = {k: [] for k in g}
+    for i in ids:
+        st, _ = oc.sample(m, wl.init, r.seed, 1, traj_offset=int(i))
+        oc.propagate(m, st, r.dt, r.n_steps, r.cadence, r.seed, r.n_out)
+        for k, v in _oracle_state(st).items():
+            o[k].append(v[0])
+    o = {k: np.array(v) for k, v in o.items()}
+    compare_walkers(g, o, rtol=1e-8, max_flip_frac=0.2, label="pyrazine_bilinear 1e7 sampled")
+    o64, o32 = outs["fp64"], outs["fp32"]
+    se = np.max(np.stack([o64[:, 0, i, i, 2] for i in range(2)]), axis=0)
+    res = int(np.argmax(~(se < 0.01))) if np.any(~(se < 0.01)) else len(se)
+    d = max(float(np.abs(o32[:res, 0, i, i, 0] - o64[:res, 0, i, i, 0]).max()) for i in range(2))
+    print("fp32 vs fp64 population diff", d, "over", res, "resolved bins", flush=True)
+    assert res >= 3 and d <= 2e-3
