@@ -279,3 +279,23 @@ def test_branching_without_resampling_is_the_plain_run(P):
     assert np.array_equal(a, b)
     # bins up to the first resampling are the plain run's, later ones differ
     assert np.array_equal(a[:3], plain[:3]) and not np.array_equal(a, plain)
+
+
+def test_replica_study_structure(P):
+    """The replica study on a small case: every interval reports its
+    times, means and spreads, the runs without resampling match the plain
+    runs' populations, and the same call twice gives the same numbers."""
+    from paper_2608_14544_amd import branching, study
+    wl = W.pyrazine_ci(n_traj=0, n_steps=20, cadence=2)
+    res = branching.replica_spread(wl, 2000, 3, [None, 4], [5.0, 10.0], "fp32")
+    assert set(res) == {"none", "every_4_steps"}
+    for v in res.values():
+        assert len(v["times"]) == len(v["mean"]) == len(v["replica_sd"]) == 2
+        assert all(np.isfinite(v["mean"])) and all(x >= 0 for x in v["replica_sd"])
+    ref = [study.population(P.run(wl, "fp32", n_traj=2000, traj_offset=k * 2000)[0])[0] for k in range(3)]
+    t = np.arange(ref[0].size) * wl.run.cadence * wl.run.dt * wl.model.time_unit_fs
+    i = int(np.argmin(np.abs(t - 10.0)))
+    assert res["none"]["mean"][1] == pytest.approx(float(np.mean([r[i] for r in ref])), rel=1e-12)
+    again = branching.replica_spread(wl, 2000, 3, [None, 4], [5.0, 10.0], "fp32")
+    for k in res:
+        assert res[k]["mean"] == again[k]["mean"] and res[k]["replica_sd"] == again[k]["replica_sd"]
