@@ -1,0 +1,8 @@
+// General-N kernels instantiated for N = 2 states, models with higher
+// separable powers of each mode and at most two cross-mode bilinear terms
+// (four squared combinations).
+#define QCL_GEN_N 2
+#define QCL_GEN_POLY 1
+#define QCL_GEN_BIL 1
+#define QCL_GEN_BIL_SQ 4
+#include "kernels_general.inc"

@@ -272,7 +272,8 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
         // general kernels are specialised on padded modes and rank bucket
         const int poly = m.degree > 1 ? 1 : 0;
         const int modes = m.fast2 ? m.m + 16 * poly
-                                  : qcl::padded_modes(m.m) * 64 + m.rank_pad + 32 * poly + 16 * (m.n_pairs > 0);
+                                  : qcl::padded_modes(m.m) * 64 + m.rank_pad + 32 * poly + 16 * (m.n_pairs > 0) +
+                                        8 * (m.n_pairs > 0 && qcl::sq_pad(m.n_pairs) == qcl::kSq);
         BatchClass *c = nullptr;
         const int occ = qcl::occupancy_variant(m, it.ens->prec, it.prop.occupancy);
         for (BatchClass &k : plan.classes)
@@ -568,7 +569,7 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, cons
                     gen.push_back((k + 1) * c[k]);
             }
             if (m->n_pairs > 0)  // coefficients of mode j in the squared combinations
-                for (int sq = 0; sq < qcl::kSq; ++sq) {
+                for (int sq = 0; sq < qcl::sq_pad(m->n_pairs); ++sq) {
                     const int p = sq / 2;
                     double cj = 0.0;
                     if (real && p < m->n_pairs) {
@@ -581,7 +582,7 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, cons
                 }
         }
         if (m->n_pairs > 0)  // slot weights: q_i q_j B = (B/4) (q_i + q_j)^2 - (B/4) (q_i - q_j)^2, as lambda y^2 / 2
-            for (int sq = 0; sq < qcl::kSq; ++sq) {
+            for (int sq = 0; sq < qcl::sq_pad(m->n_pairs); ++sq) {
                 const int p = sq / 2;
                 for (int a = 0; a < n; ++a)
                     for (int b = a; b < n; ++b)

@@ -77,8 +77,10 @@ struct GenConst {
     R rot_eps;  // Jacobi: rotate while |a_pq| > rot_eps * ||A||_F
 };
 
-// squared mode combinations of a bilinear model (two per term)
+// squared mode combinations of a bilinear model (two per term): the
+// kernels are built for 4 (at most two terms) and for kSq
 constexpr int kSq = 2 * QCL_MAX_PAIRS;
+inline int sq_pad(int n_pairs) { return n_pairs <= 2 ? 4 : kSq; }
 
 inline int padded_modes(int m)
 {
@@ -207,7 +209,9 @@ struct int_ {};  // general kernels of K states, linear couplings (kernels_gen{K
 template <int K>
 struct poly_ {};  // general kernels of K states, higher powers (kernels_poly{K}.hip)
 template <int K>
-struct bil_ {};   // general kernels of K states, higher powers and bilinear terms (kernels_bil{K}.hip)
+struct bil_ {};   // general kernels of K states, higher powers and up to 4 bilinear terms (kernels_bil{K}.hip)
+template <int K>
+struct bilh_ {};  // the same for at most 2 bilinear terms (kernels_bilh{K}.hip)
 
 #define QCL_DECLARE_GENERAL(TAG)                                                                              \
     hipError_t launch_sample_general_n(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,   \
@@ -231,6 +235,9 @@ QCL_DECLARE_GENERAL(poly_<4>)
 QCL_DECLARE_GENERAL(bil_<2>)
 QCL_DECLARE_GENERAL(bil_<3>)
 QCL_DECLARE_GENERAL(bil_<4>)
+QCL_DECLARE_GENERAL(bilh_<2>)
+QCL_DECLARE_GENERAL(bilh_<3>)
+QCL_DECLARE_GENERAL(bilh_<4>)
 #undef QCL_DECLARE_GENERAL
 
 // Calls fn with the tag of the general kernels a model runs on; `none` when
@@ -238,6 +245,14 @@ QCL_DECLARE_GENERAL(bil_<4>)
 template <typename Ret, typename F>
 inline Ret with_general(const qcl_model_s &m, Ret none, F &&fn)
 {
+    if (m.n_pairs > 0 && sq_pad(m.n_pairs) < kSq) {
+        switch (m.n) {
+        case 2: return fn(bilh_<2>{});
+        case 3: return fn(bilh_<3>{});
+        case 4: return fn(bilh_<4>{});
+        default: return none;
+        }
+    }
     if (m.n_pairs > 0) {
         switch (m.n) {
         case 2: return fn(bil_<2>{});

@@ -5,7 +5,9 @@ slicing and batching, ragged sizes and the full-size workload of the bench.
 
 The device splits each term as ((q_i + q_j)^2 - (q_i - q_j)^2) / 4, the
 oracle evaluates q_i q_j B_p directly: the two agree to rounding, so the
-binary64 tolerances are those of the other general-kernel models."""
+binary64 tolerances are those of the other general-kernel models.  Models
+with one or two terms run the four-combination builds, three or four terms
+the eight-combination builds; the cases cover both."""
 import numpy as np
 import pytest
 
@@ -31,6 +33,7 @@ CASES = {
     "n3_m5_p4_d3": lambda: W.random_bilinear(1, n_states=3, n_modes=5, n_pairs=4, degree=3),
     "n4_m4_p3_d4": lambda: W.random_bilinear(2, n_states=4, n_modes=4, n_pairs=3, degree=4),
     "n3_m20_p4": lambda: W.random_bilinear(5, n_states=3, n_modes=20, n_pairs=4, n_traj=1000),
+    "n3_m6_p1_d3": lambda: W.random_bilinear(11, n_states=3, n_modes=6, n_pairs=1, degree=3),
 }
 
 
