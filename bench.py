@@ -178,7 +178,34 @@ def cpu_baseline(wl, target_s: float):
     return {"value": rate, "unit": "trajectory-steps/s", "cores": oc.num_threads(), "kind": "oracle",
             "sample": f"{n} walkers x {wl.run.n_steps} steps of the same model (sample+propagate+reduce), "
                       f"{dt:.1f} s, FP64 C oracle, OpenMP over walkers",
-            "cpu_model": _cpu_model(), "single_thread": single}
+            "cpu_model": _cpu_model(), "single_thread": single, "other_legs": _oracle_other_legs()}
+
+
+def _oracle_other_legs():
+    """The oracle beside two further legs, on bounded samples (a few seconds
+    each): the bilinear model's propagation (65536 walkers x 200 steps) and
+    fixed-budget resampling (pure Python, 1e6 walkers with heavy-tailed
+    signed weights)."""
+    import numpy as np
+    import oracle.core as oc
+    import oracle.resample as orr
+    import workloads as W
+    bw = W.pyrazine_bilinear(n_traj=0, n_steps=200, cadence=10)
+    rb, dtb = _oracle_rate(bw, 65536)
+    T = 1_000_000
+    rng = np.random.default_rng(1)
+    st = oc.State(T, 2, 3)
+    st.q[:] = rng.normal(size=(T, 3))
+    st.p[:] = rng.normal(size=(T, 3))
+    st.w[:] = rng.lognormal(0.0, 2.5, T) * rng.choice([-1.0, 1.0], T)
+    st.phase[:] = rng.uniform(-20, 20, T)
+    t0 = time.perf_counter()
+    orr.resample(st, 21)
+    dtr = time.perf_counter() - t0
+    return {"pyrazine_bilinear": {"value": rb, "unit": "trajectory-steps/s", "cores": oc.num_threads(),
+                                  "sample": f"65536 walkers x 200 steps, {dtb:.2f} s"},
+            "resample": {"value": T / dtr, "unit": "walkers/s", "cores": 1,
+                         "sample": f"{T} walkers (2 states, 3 modes), {dtr:.2f} s, Python integers"}}
 
 
 def spin_boson_leg(P, torch):
