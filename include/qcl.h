@@ -195,8 +195,8 @@ typedef struct {
  * a NULL poly->a, non-finite or asymmetric A_jk. */
 qcl_status qcl_create_model_poly(const qcl_model_desc *desc, const qcl_poly_desc *poly, qcl_model *out);
 
-#define QCL_MAX_PAIRS 4          /* bilinear terms per model */
-#define QCL_MAX_MODES_BILINEAR 32
+#define QCL_MAX_PAIRS 8          /* bilinear terms per model */
+#define QCL_MAX_MODES_BILINEAR 32  /* 16 for models with more than 4 terms */
 
 /* Cross-mode bilinear terms (the same extension of Eq. 1's potential as
  * qcl_poly_desc, with couplings between two modes, e.g. the Duschinsky
@@ -213,14 +213,15 @@ typedef struct {
 /* As qcl_create_model_poly (poly may be NULL: no powers above 1), with the
  * bilinear terms of bil (read during the call only).  Such a model runs on
  * the general-N kernels for N = 2..4 (also N = 2), every coupling direction
- * kept, at most QCL_MAX_MODES_BILINEAR modes; qcl_model_degree reports at
+ * kept, at most QCL_MAX_MODES_BILINEAR modes (16 with more than 4 terms);
+ * qcl_model_degree reports at
  * least 2.  On the device each term is split exactly as q_i q_j =
  * ((q_i + q_j)^2 - (q_i - q_j)^2) / 4, two squared mode combinations with
  * coefficients +-1.
  * Errors: as qcl_create_model_poly; INVALID_ARG also for a NULL bil, pairs
  * or b, n_pairs outside [1, QCL_MAX_PAIRS], a mode index out of range or
  * i == j, non-finite or asymmetric B_p; UNSUPPORTED for more than 4 states
- * or more than QCL_MAX_MODES_BILINEAR modes. */
+ * or more than QCL_MAX_MODES_BILINEAR modes (16 with more than 4 terms). */
 qcl_status qcl_create_model_bilinear(const qcl_model_desc *desc, const qcl_poly_desc *poly,
                                      const qcl_bilinear_desc *bil, qcl_model *out);
 

@@ -273,7 +273,8 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
         const int poly = m.degree > 1 ? 1 : 0;
         const int modes = m.fast2 ? m.m + 16 * poly
                                   : qcl::padded_modes(m.m) * 64 + m.rank_pad + 32 * poly + 16 * (m.n_pairs > 0) +
-                                        8 * (m.n_pairs > 0 && qcl::sq_pad(m.n_pairs) == qcl::kSq);
+                                        8 * (m.n_pairs > 0 && qcl::sq_pad(m.n_pairs) == 8) +
+                                        4 * (m.n_pairs > 0 && qcl::sq_pad(m.n_pairs) == qcl::kSq);
         BatchClass *c = nullptr;
         const int occ = qcl::occupancy_variant(m, it.ens->prec, it.prop.occupancy);
         for (BatchClass &k : plan.classes)
@@ -392,6 +393,9 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, cons
         if (M > QCL_MAX_MODES_BILINEAR)
             return fail(QCL_ERR_UNSUPPORTED, "bilinear models support at most %d modes (got %d)",
                         QCL_MAX_MODES_BILINEAR, M);
+        if (bil->n_pairs > 4 && M > 16)
+            return fail(QCL_ERR_UNSUPPORTED, "models with more than 4 bilinear terms support at most 16 modes (got %d)",
+                        M);
     }
 
     qcl_model_s *m = new (std::nothrow) qcl_model_s();

@@ -78,9 +78,10 @@ struct GenConst {
 };
 
 // squared mode combinations of a bilinear model (two per term): the
-// kernels are built for 4 (at most two terms) and for kSq
+// kernels are built for 4 (at most two terms), 8 (four) and kSq (eight
+// terms, at most 16 modes)
 constexpr int kSq = 2 * QCL_MAX_PAIRS;
-inline int sq_pad(int n_pairs) { return n_pairs <= 2 ? 4 : kSq; }
+inline int sq_pad(int n_pairs) { return n_pairs <= 2 ? 4 : n_pairs <= 4 ? 8 : kSq; }
 
 inline int padded_modes(int m)
 {
@@ -212,6 +213,8 @@ template <int K>
 struct bil_ {};   // general kernels of K states, higher powers and up to 4 bilinear terms (kernels_bil{K}.hip)
 template <int K>
 struct bilh_ {};  // the same for at most 2 bilinear terms (kernels_bilh{K}.hip)
+template <int K>
+struct bilw_ {};  // the same for 5 to 8 bilinear terms, at most 16 modes (kernels_bilw{K}.hip)
 
 #define QCL_DECLARE_GENERAL(TAG)                                                                              \
     hipError_t launch_sample_general_n(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,   \
@@ -238,6 +241,9 @@ QCL_DECLARE_GENERAL(bil_<4>)
 QCL_DECLARE_GENERAL(bilh_<2>)
 QCL_DECLARE_GENERAL(bilh_<3>)
 QCL_DECLARE_GENERAL(bilh_<4>)
+QCL_DECLARE_GENERAL(bilw_<2>)
+QCL_DECLARE_GENERAL(bilw_<3>)
+QCL_DECLARE_GENERAL(bilw_<4>)
 #undef QCL_DECLARE_GENERAL
 
 // Calls fn with the tag of the general kernels a model runs on; `none` when
@@ -245,11 +251,19 @@ QCL_DECLARE_GENERAL(bilh_<4>)
 template <typename Ret, typename F>
 inline Ret with_general(const qcl_model_s &m, Ret none, F &&fn)
 {
-    if (m.n_pairs > 0 && sq_pad(m.n_pairs) < kSq) {
+    if (m.n_pairs > 0 && sq_pad(m.n_pairs) == 4) {
         switch (m.n) {
         case 2: return fn(bilh_<2>{});
         case 3: return fn(bilh_<3>{});
         case 4: return fn(bilh_<4>{});
+        default: return none;
+        }
+    }
+    if (m.n_pairs > 0 && sq_pad(m.n_pairs) == kSq) {
+        switch (m.n) {
+        case 2: return fn(bilw_<2>{});
+        case 3: return fn(bilw_<3>{});
+        case 4: return fn(bilw_<4>{});
         default: return none;
         }
     }

@@ -7,7 +7,8 @@ The device splits each term as ((q_i + q_j)^2 - (q_i - q_j)^2) / 4, the
 oracle evaluates q_i q_j B_p directly: the two agree to rounding, so the
 binary64 tolerances are those of the other general-kernel models.  Models
 with one or two terms run the four-combination builds, three or four terms
-the eight-combination builds; the cases cover both."""
+the eight-combination builds, five to eight terms (at most 16 modes) the
+sixteen-combination builds; the cases cover all three."""
 import numpy as np
 import pytest
 
@@ -34,6 +35,8 @@ CASES = {
     "n4_m4_p3_d4": lambda: W.random_bilinear(2, n_states=4, n_modes=4, n_pairs=3, degree=4),
     "n3_m20_p4": lambda: W.random_bilinear(5, n_states=3, n_modes=20, n_pairs=4, n_traj=1000),
     "n3_m6_p1_d3": lambda: W.random_bilinear(11, n_states=3, n_modes=6, n_pairs=1, degree=3),
+    "n2_m6_p8_d2": lambda: W.random_bilinear(12, n_states=2, n_modes=6, n_pairs=8),
+    "n4_m16_p6_d4": lambda: W.random_bilinear(13, n_states=4, n_modes=16, n_pairs=6, degree=4, n_traj=1000),
 }
 
 
@@ -126,6 +129,8 @@ def test_bilinear_in_mixed_batch_bitwise(P):
          "fp64", 1, 300),
         (W.random_bilinear(9, n_states=4, n_modes=20, n_pairs=4, n_traj=257, n_steps=30, cadence=10), "fp32", 0, 257),
         (W.random_lvc(8, n_states=3, n_modes=4, n_traj=400, n_steps=40, cadence=10), "fp32", 0, 400),
+        (W.random_bilinear(14, n_states=3, n_modes=8, n_pairs=7, degree=3, n_traj=300, n_steps=40, cadence=10),
+         "fp32", 0, 300),
     ]
     solo = [_solo(P, wl, prec, scheme, T) for wl, prec, scheme, T in mix]
     for slices in ((None,), (0.5, None)):
