@@ -195,8 +195,8 @@ typedef struct {
  * a NULL poly->a, non-finite or asymmetric A_jk. */
 qcl_status qcl_create_model_poly(const qcl_model_desc *desc, const qcl_poly_desc *poly, qcl_model *out);
 
-#define QCL_MAX_PAIRS 8          /* bilinear terms per model */
-#define QCL_MAX_MODES_BILINEAR 32  /* 16 for models with more than 4 terms */
+#define QCL_MAX_PAIRS 64         /* bilinear terms per model (see qcl_create_model_bilinear) */
+#define QCL_MAX_MODES_BILINEAR 32
 
 /* Cross-mode bilinear terms (the same extension of Eq. 1's potential as
  * qcl_poly_desc, with couplings between two modes, e.g. the Duschinsky
@@ -213,15 +213,19 @@ typedef struct {
 /* As qcl_create_model_poly (poly may be NULL: no powers above 1), with the
  * bilinear terms of bil (read during the call only).  Such a model runs on
  * the general-N kernels for N = 2..4 (also N = 2), every coupling direction
- * kept, at most QCL_MAX_MODES_BILINEAR modes (16 with more than 4 terms);
- * qcl_model_degree reports at
- * least 2.  On the device each term is split exactly as q_i q_j =
- * ((q_i + q_j)^2 - (q_i - q_j)^2) / 4, two squared mode combinations with
- * coefficients +-1.
+ * kept; qcl_model_degree reports at least 2.  On the device the terms
+ * become squared mode combinations y_s = c_s . q, with slot weights: either
+ * each term split exactly as q_i q_j = ((q_i + q_j)^2 - (q_i - q_j)^2) / 4
+ * (two combinations, coefficients +-1), or, when that needs fewer, the
+ * eigendecomposition of each coupling slot's M x M matrix (one combination
+ * per nonzero eigenvalue; dense couplings among a few modes, or mode mixing
+ * shared by the states).  At most 16 combinations, and at most 16 modes
+ * when more than 8 are needed.
  * Errors: as qcl_create_model_poly; INVALID_ARG also for a NULL bil, pairs
  * or b, n_pairs outside [1, QCL_MAX_PAIRS], a mode index out of range or
- * i == j, non-finite or asymmetric B_p; UNSUPPORTED for more than 4 states
- * or more than QCL_MAX_MODES_BILINEAR modes (16 with more than 4 terms). */
+ * i == j, non-finite or asymmetric B_p; UNSUPPORTED for more than 4 states,
+ * more than QCL_MAX_MODES_BILINEAR modes, more than 16 combinations, or
+ * more than 16 modes with more than 8 combinations. */
 qcl_status qcl_create_model_bilinear(const qcl_model_desc *desc, const qcl_poly_desc *poly,
                                      const qcl_bilinear_desc *bil, qcl_model *out);
 

@@ -273,8 +273,8 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
         const int poly = m.degree > 1 ? 1 : 0;
         const int modes = m.fast2 ? m.m + 16 * poly
                                   : qcl::padded_modes(m.m) * 64 + m.rank_pad + 32 * poly + 16 * (m.n_pairs > 0) +
-                                        8 * (m.n_pairs > 0 && qcl::sq_pad(m.n_pairs) == 8) +
-                                        4 * (m.n_pairs > 0 && qcl::sq_pad(m.n_pairs) == qcl::kSq);
+                                        8 * (m.n_pairs > 0 && qcl::sq_pad(m.n_sq) == 8) +
+                                        4 * (m.n_pairs > 0 && qcl::sq_pad(m.n_sq) == qcl::kSq);
         BatchClass *c = nullptr;
         const int occ = qcl::occupancy_variant(m, it.ens->prec, it.prop.occupancy);
         for (BatchClass &k : plan.classes)
@@ -324,6 +324,124 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
     }
     plan.bytes = off;
     return QCL_OK;
+}
+
+// Eigendecomposition A = V diag(e) V^T of a symmetric n x n matrix (row
+// major) by cyclic Jacobi rotations in binary64, until every off-diagonal
+// entry is below 1e-15 of the norm; eigenvectors in the columns of V.
+void jacobi_sym(int n, std::vector<double> A, std::vector<double> &e, std::vector<double> &V)
+{
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        V[(size_t)i * n + i] = 1.0;
+    double norm = 0.0;
+    for (double x : A)
+        norm += x * x;
+    norm = std::sqrt(norm);
+    for (int sweep = 0; sweep < 100 && norm > 0.0; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q)
+                off = std::max(off, std::fabs(A[(size_t)p * n + q]));
+        if (off <= 1e-15 * norm)
+            break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (apq == 0.0)
+                    continue;
+                // rotation angle that zeroes A_pq (Golub and Van Loan, Sec. 8.5)
+                const double theta = (A[(size_t)q * n + q] - A[(size_t)p * n + p]) / (2.0 * apq);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {  // A <- A G
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = c * akp - sn * akq;
+                    A[(size_t)k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // A <- G^T A
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = c * apk - sn * aqk;
+                    A[(size_t)q * n + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {  // V <- V G
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - sn * vkq;
+                    V[(size_t)k * n + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    e.resize(n);
+    for (int i = 0; i < n; ++i)
+        e[i] = A[(size_t)i * n + i];
+}
+
+// The squared mode combinations y_s = c_s . q of a model's bilinear terms,
+// with slot weights lam_sr such that sum_s lam_sr y_s^2 / 2 equals the
+// terms' part of slot r, sum_p q_i q_j B_p[r].  Two factorisations:
+//  - per term, ((q_i + q_j)^2 - (q_i - q_j)^2) / 4: two combinations with
+//    coefficients +-1 and weights +-B_p / 2, exact in binary64;
+//  - per slot r, the eigendecomposition of the M x M matrix C^r with
+//    C^r_ij = C^r_ji = the sum of B_p[r] over the terms on (i, j): one
+//    combination per eigenvalue above 1e-13 of the largest, weighted only
+//    in its own slot (exact to rounding).
+// The one with fewer combinations is kept; returns their number.
+int bilinear_squares(int n, int M, int P, const int32_t *pairs, const double *b, std::vector<double> &c,
+                     std::vector<double> &lam)
+{
+    const int T = n * (n + 1) / 2;
+    auto slot_value = [&](int p, int r) {
+        for (int a = 0, s = 0; a < n; ++a)
+            for (int bb = a; bb < n; ++bb, ++s)
+                if (s == r)
+                    return b[(size_t)p * n * n + a * n + bb];
+        return 0.0;
+    };
+    // the slot matrices and their eigen-combinations
+    std::vector<double> ec, el;
+    int n_eig = 0;
+    double emax = 0.0;
+    std::vector<std::vector<double>> evals(T), evecs(T);
+    for (int r = 0; r < T; ++r) {
+        std::vector<double> C((size_t)M * M, 0.0);
+        for (int p = 0; p < P; ++p) {
+            const int i = pairs[2 * p], j = pairs[2 * p + 1];
+            const double v = slot_value(p, r);
+            C[(size_t)i * M + j] += v;
+            C[(size_t)j * M + i] += v;
+        }
+        jacobi_sym(M, C, evals[r], evecs[r]);
+        for (double x : evals[r])
+            emax = std::max(emax, std::fabs(x));
+    }
+    for (int r = 0; r < T; ++r)
+        for (int k = 0; k < M; ++k)
+            if (std::fabs(evals[r][k]) > 1e-13 * emax) {
+                ++n_eig;
+                for (int j = 0; j < M; ++j)
+                    ec.push_back(evecs[r][(size_t)j * M + k]);
+                for (int rr = 0; rr < T; ++rr)
+                    el.push_back(rr == r ? evals[r][k] : 0.0);
+            }
+    if (n_eig < 2 * P) {
+        c.swap(ec);
+        lam.swap(el);
+        return n_eig;
+    }
+    c.assign((size_t)2 * P * M, 0.0);
+    lam.assign((size_t)2 * P * T, 0.0);
+    for (int p = 0; p < P; ++p) {
+        const int i = pairs[2 * p], j = pairs[2 * p + 1];
+        c[(size_t)(2 * p) * M + i] += 1.0;
+        c[(size_t)(2 * p) * M + j] += 1.0;
+        c[(size_t)(2 * p + 1) * M + i] += 1.0;
+        c[(size_t)(2 * p + 1) * M + j] -= 1.0;
+        for (int r = 0; r < T; ++r) {
+            lam[(size_t)(2 * p) * T + r] = 0.5 * slot_value(p, r);
+            lam[(size_t)(2 * p + 1) * T + r] = -0.5 * slot_value(p, r);
+        }
+    }
+    return 2 * P;
 }
 
 // Builds a model (linear when poly and bil are NULL); see qcl_create_model,
@@ -393,9 +511,17 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, cons
         if (M > QCL_MAX_MODES_BILINEAR)
             return fail(QCL_ERR_UNSUPPORTED, "bilinear models support at most %d modes (got %d)",
                         QCL_MAX_MODES_BILINEAR, M);
-        if (bil->n_pairs > 4 && M > 16)
-            return fail(QCL_ERR_UNSUPPORTED, "models with more than 4 bilinear terms support at most 16 modes (got %d)",
-                        M);
+    }
+    std::vector<double> sq_c, sq_lam;
+    int n_sq = 0;
+    if (bil) {
+        n_sq = bilinear_squares(n, M, bil->n_pairs, bil->pairs, bil->b, sq_c, sq_lam);
+        if (n_sq > qcl::kSq)
+            return fail(QCL_ERR_UNSUPPORTED, "the bilinear terms need %d squared mode combinations (at most %d)", n_sq,
+                        qcl::kSq);
+        if (n_sq > 8 && M > 16)
+            return fail(QCL_ERR_UNSUPPORTED, "bilinear terms needing more than 8 squared combinations support at most "
+                        "16 modes (got %d)", M);
     }
 
     qcl_model_s *m = new (std::nothrow) qcl_model_s();
@@ -417,6 +543,9 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, cons
         m->n_pairs = bil->n_pairs;
         m->pairs.assign(bil->pairs, bil->pairs + 2 * bil->n_pairs);
         m->bpair.assign(bil->b, bil->b + (size_t)bil->n_pairs * n * n);
+        m->n_sq = n_sq;
+        m->sq_c = sq_c;
+        m->sq_lam = sq_lam;
     }
     m->fast2 = (n == 2 && M <= qcl::kMaxFastModes && !bil);
     // energy scale: |V0| plus each mode's coupling over its zero-point-ish length
@@ -572,27 +701,14 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, cons
                 for (int k = 0; k < 4; ++k)
                     gen.push_back((k + 1) * c[k]);
             }
-            if (m->n_pairs > 0)  // coefficients of mode j in the squared combinations
-                for (int sq = 0; sq < qcl::sq_pad(m->n_pairs); ++sq) {
-                    const int p = sq / 2;
-                    double cj = 0.0;
-                    if (real && p < m->n_pairs) {
-                        if (m->pairs[2 * p] == j)
-                            cj = 1.0;
-                        if (m->pairs[2 * p + 1] == j)
-                            cj = (sq % 2) ? -1.0 : 1.0;
-                    }
-                    gen.push_back(cj);
-                }
+            if (m->n_pairs > 0)  // coefficients of mode j in the squared combinations (zero past n_sq)
+                for (int sq = 0; sq < qcl::sq_pad(m->n_sq); ++sq)
+                    gen.push_back(real && sq < m->n_sq ? m->sq_c[(size_t)sq * M + j] : 0.0);
         }
-        if (m->n_pairs > 0)  // slot weights: q_i q_j B = (B/4) (q_i + q_j)^2 - (B/4) (q_i - q_j)^2, as lambda y^2 / 2
-            for (int sq = 0; sq < qcl::sq_pad(m->n_pairs); ++sq) {
-                const int p = sq / 2;
-                for (int a = 0; a < n; ++a)
-                    for (int b = a; b < n; ++b)
-                        gen.push_back(p < m->n_pairs ? ((sq % 2) ? -0.5 : 0.5) * m->bpair[(size_t)p * n * n + a * n + b]
-                                                     : 0.0);
-            }
+        if (m->n_pairs > 0)  // slot weights lambda [sq][slot]
+            for (int sq = 0; sq < qcl::sq_pad(m->n_sq); ++sq)
+                for (int r = 0; r < T; ++r)
+                    gen.push_back(sq < m->n_sq ? m->sq_lam[(size_t)sq * T + r] : 0.0);
     }
     while (packed.size() % 32)
         packed.push_back(0.0);

@@ -77,11 +77,10 @@ struct GenConst {
     R rot_eps;  // Jacobi: rotate while |a_pq| > rot_eps * ||A||_F
 };
 
-// squared mode combinations of a bilinear model (two per term): the
-// kernels are built for 4 (at most two terms), 8 (four) and kSq (eight
-// terms, at most 16 modes)
-constexpr int kSq = 2 * QCL_MAX_PAIRS;
-inline int sq_pad(int n_pairs) { return n_pairs <= 2 ? 4 : n_pairs <= 4 ? 8 : kSq; }
+// squared mode combinations of a bilinear model: the kernels are built for
+// 4, 8 and kSq of them (kSq: at most 16 modes)
+constexpr int kSq = 16;
+inline int sq_pad(int n_sq) { return n_sq <= 4 ? 4 : n_sq <= 8 ? 8 : kSq; }
 
 inline int padded_modes(int m)
 {
@@ -193,9 +192,12 @@ struct qcl_model_s {
     int32_t rank_pad = 1;       // rank bucket RB the general kernels are specialised on
     int32_t degree = 1;         // highest power of q_j in V(q) (> 1: kernels_poly{N}.hip)
     std::vector<double> poly;   // [M][degree-1][N][N] higher-power matrices A_jk (k >= 2)
-    int32_t n_pairs = 0;        // bilinear terms (> 0: kernels_bil{N}.hip)
+    int32_t n_pairs = 0;        // bilinear terms (> 0: kernels_bil{,h,w}{N}.hip)
     std::vector<int32_t> pairs; // [n_pairs][2] modes of each term
     std::vector<double> bpair;  // [n_pairs][N][N] B_p
+    int32_t n_sq = 0;           // squared mode combinations representing them
+    std::vector<double> sq_c;   // [n_sq][M] mode coefficients of each combination
+    std::vector<double> sq_lam; // [n_sq][T] slot weights (X_r += lam_sr y_s^2 / 2)
     bool fast2 = false;         // two-state closed-form kernels apply (N = 2, M <= 8)
 };
 
@@ -210,11 +212,11 @@ struct int_ {};  // general kernels of K states, linear couplings (kernels_gen{K
 template <int K>
 struct poly_ {};  // general kernels of K states, higher powers (kernels_poly{K}.hip)
 template <int K>
-struct bil_ {};   // general kernels of K states, higher powers and up to 4 bilinear terms (kernels_bil{K}.hip)
+struct bil_ {};   // general kernels of K states, higher powers and bilinear terms as 8 squares (kernels_bil{K}.hip)
 template <int K>
-struct bilh_ {};  // the same for at most 2 bilinear terms (kernels_bilh{K}.hip)
+struct bilh_ {};  // the same with 4 squares (kernels_bilh{K}.hip)
 template <int K>
-struct bilw_ {};  // the same for 5 to 8 bilinear terms, at most 16 modes (kernels_bilw{K}.hip)
+struct bilw_ {};  // the same with 16 squares, at most 16 modes (kernels_bilw{K}.hip)
 
 #define QCL_DECLARE_GENERAL(TAG)                                                                              \
     hipError_t launch_sample_general_n(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens,   \
@@ -251,7 +253,7 @@ QCL_DECLARE_GENERAL(bilw_<4>)
 template <typename Ret, typename F>
 inline Ret with_general(const qcl_model_s &m, Ret none, F &&fn)
 {
-    if (m.n_pairs > 0 && sq_pad(m.n_pairs) == 4) {
+    if (m.n_pairs > 0 && sq_pad(m.n_sq) == 4) {
         switch (m.n) {
         case 2: return fn(bilh_<2>{});
         case 3: return fn(bilh_<3>{});
@@ -259,7 +261,7 @@ inline Ret with_general(const qcl_model_s &m, Ret none, F &&fn)
         default: return none;
         }
     }
-    if (m.n_pairs > 0 && sq_pad(m.n_pairs) == kSq) {
+    if (m.n_pairs > 0 && sq_pad(m.n_sq) == kSq) {
         switch (m.n) {
         case 2: return fn(bilw_<2>{});
         case 3: return fn(bilw_<3>{});

@@ -157,15 +157,15 @@ def test_resample_validation_on_host():
     assert L.qcl_resample(None, None, None, 0, None, 0, None) == qcl.QCL_ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("patch", ["zero_pairs", "nine_pairs", "null_pairs", "null_b", "same_mode", "out_of_range",
+@pytest.mark.parametrize("patch", ["zero_pairs", "too_many_pairs", "null_pairs", "null_b", "same_mode", "out_of_range",
                                    "negative", "nan", "asym"])
 def test_create_model_bilinear_rejects_invalid(patch):
     """Invalid bilinear terms are rejected on the host (INVALID_ARG)."""
     qcl, L = _lib()
     lvc = W.pyrazine_ci().model
     d, keep = _desc(qcl, lvc)
-    n_pairs = {"zero_pairs": 0, "nine_pairs": 9}.get(patch, 2)
-    pairs = np.array([[0, 1], [1, 2]] + [[0, 2]] * 7, np.int32)[:max(n_pairs, 1)]
+    n_pairs = {"zero_pairs": 0, "too_many_pairs": 65}.get(patch, 2)
+    pairs = np.array([[0, 1], [1, 2]] + [[0, 2]] * 63, np.int32)[:max(n_pairs, 1)]
     b = np.zeros((max(n_pairs, 1), 2, 2))
     if patch == "same_mode":
         pairs[1] = [2, 2]
@@ -189,14 +189,18 @@ def test_create_model_bilinear_rejects_invalid(patch):
 
 
 def test_bilinear_limits_on_host():
-    """Bilinear terms: at most 4 states and 32 modes, 16 modes with more
-    than 4 terms (UNSUPPORTED)."""
+    """Bilinear terms: at most 4 states and 32 modes, at most 16 squared
+    combinations, 16 modes when more than 8 are needed (UNSUPPORTED)."""
     qcl, L = _lib()
-    for n, M, P in ((5, 4, 1), (3, 33, 1), (3, 17, 5)):
+    rng = np.random.default_rng(3)
+    dense4 = [[i, j] for i in range(8) for j in range(i + 1, 8)]   # 28 pairs, 4 states: 56 or 80 squares
+    for n, M, pl in ((5, 4, [[0, 1]]), (3, 33, [[0, 1]]), (3, 17, [[0, k + 1] for k in range(5)]), (4, 8, dense4)):
         lvc = W.random_lvc(70 + n, n_states=n, n_modes=M).model
         d, keep = _desc(qcl, lvc)
-        pairs = np.array([[0, k + 1] for k in range(P)], np.int32)
-        b = np.zeros((P, n, n))
+        P = len(pl)
+        pairs = np.array(pl, np.int32)
+        a = rng.uniform(-1, 1, size=(P, n, n))
+        b = np.ascontiguousarray(a + a.transpose(0, 2, 1))
         bd = qcl.qcl_bilinear_desc(P, 0, pairs.ctypes.data_as(C.POINTER(C.c_int32)),
                                    b.ctypes.data_as(C.POINTER(C.c_double)))
         h = C.c_void_p()

@@ -6,9 +6,10 @@ slicing and batching, ragged sizes and the full-size workload of the bench.
 The device splits each term as ((q_i + q_j)^2 - (q_i - q_j)^2) / 4, the
 oracle evaluates q_i q_j B_p directly: the two agree to rounding, so the
 binary64 tolerances are those of the other general-kernel models.  Models
-with one or two terms run the four-combination builds, three or four terms
-the eight-combination builds, five to eight terms (at most 16 modes) the
-sixteen-combination builds; the cases cover all three."""
+needing up to 4, 8 or 16 squared combinations run the builds for 4, 8 or
+16; the cases cover all three, and both ways of forming the combinations
+(per term, and per slot from the eigendecomposition of the slot's mode-mode
+matrix, for models where every pair of modes is coupled)."""
 import numpy as np
 import pytest
 
@@ -37,6 +38,9 @@ CASES = {
     "n3_m6_p1_d3": lambda: W.random_bilinear(11, n_states=3, n_modes=6, n_pairs=1, degree=3),
     "n2_m6_p8_d2": lambda: W.random_bilinear(12, n_states=2, n_modes=6, n_pairs=8),
     "n4_m16_p6_d4": lambda: W.random_bilinear(13, n_states=4, n_modes=16, n_pairs=6, degree=4, n_traj=1000),
+    # every pair of modes coupled: the slot eigendecompositions need fewer combinations
+    "n2_m5_all_d3": lambda: W.random_bilinear(15, n_states=2, n_modes=5, all_pairs=True, degree=3),
+    "n2_m8_all_shared": lambda: W.random_bilinear(16, n_states=2, n_modes=8, all_pairs=True, shared=True),
 }
 
 

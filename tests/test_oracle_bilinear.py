@@ -28,7 +28,8 @@ def _V(model, q):
                                 W.random_bilinear(0, n_states=2, n_modes=3, n_pairs=2),
                                 W.random_bilinear(1, n_states=3, n_modes=5, n_pairs=4, degree=3),
                                 W.random_bilinear(2, n_states=4, n_modes=4, n_pairs=3, degree=4),
-                                W.random_bilinear(5, n_states=3, n_modes=6, n_pairs=8, degree=2)])
+                                W.random_bilinear(5, n_states=3, n_modes=6, n_pairs=8, degree=2),
+                                W.random_bilinear(15, n_states=2, n_modes=5, all_pairs=True, degree=3)])
 def test_bilinear_force_and_nac_vs_finite_differences(oracle_lib, wl):
     oc = oracle_lib
     model = wl.model

@@ -307,22 +307,30 @@ def pyrazine_bilinear(n_traj: int = 1_000_000, n_steps: int = 200, dt_fs: float 
 
 def random_bilinear(index: int, n_states: int = 3, n_modes: int = 5, n_pairs: int = 3, degree: int = 2,
                     key: int = 8, n_traj: int = 2000, n_steps: int = 100, dt: float = 0.05,
-                    cadence: int = 10) -> Workload:
+                    cadence: int = 10, all_pairs: bool = False, shared: bool = False) -> Workload:
     """``random_poly`` with ``n_pairs`` cross-mode bilinear terms on distinct
-    random mode pairs, each coupling a dense random symmetric matrix small
-    against the harmonic force constants (the surfaces stay confining)."""
+    random mode pairs (every pair with ``all_pairs``), each coupling a dense
+    random symmetric matrix small against the harmonic force constants (the
+    surfaces stay confining); with ``shared`` each coupling is a multiple of
+    the identity (mode mixing common to all states)."""
     wl = random_poly(index, n_states=n_states, n_modes=n_modes, degree=degree, key=key, n_traj=n_traj,
                      n_steps=n_steps, dt=dt, cadence=cadence)
     rng = np.random.Generator(np.random.Philox(key=[key + 1000, index]))
     N, M = int(n_states), int(n_modes)
     pairs = set()
+    if all_pairs:
+        pairs = {(i, j) for i in range(M) for j in range(i + 1, M)}
     while len(pairs) < n_pairs:
         i, j = sorted(int(x) for x in rng.choice(M, size=2, replace=False))
         pairs.add((i, j))
     bil = []
+    scale = 0.04 / max(1.0, math.sqrt(len(pairs) / 4.0))
     for i, j in sorted(pairs):
-        a = rng.uniform(-0.04, 0.04, size=(N, N))
-        bil.append((i, j, 0.5 * (a + a.T)))
+        if shared:
+            bil.append((i, j, rng.uniform(-scale, scale) * np.eye(N)))
+        else:
+            a = rng.uniform(-scale, scale, size=(N, N))
+            bil.append((i, j, 0.5 * (a + a.T)))
     m = wl.model
     wl.model = LVCModel(name=f"random_bilinear_{key}_{index}", mass=m.mass, omega=m.omega, v0=m.v0, k=m.k,
                         poly=m.poly, bilinear=bil)
