@@ -60,3 +60,29 @@ def test_server_rejects_oversized(P):
     res = {r.name: r for r in srv.run([0.0, 0.0], [big, small])}
     assert res["big"].error and res["big"].out is None
     assert np.array_equal(res["small"].out, _alone(P, small.workload, "fp32"))
+
+
+def test_served_mixed_model_families_equal_alone(P):
+    """Every model family through the server at once: linear, higher powers,
+    more than four states and bilinear terms of each combination count
+    (4, 8 and 16), in both precisions; each result bitwise the job alone."""
+    from paper_2608_14544_amd.serve import DeviceBackend, JobSpec, Server
+    wls = [
+        W.pyrazine_ci(n_traj=3000, n_steps=60, cadence=6),
+        W.pyrazine_qvc(n_traj=2000, n_steps=60, cadence=6),
+        W.random_poly(40, n_states=3, n_modes=12, degree=4, n_traj=1500, n_steps=40, cadence=10),
+        W.random_lvc(41, n_states=6, n_modes=5, n_traj=1000, n_steps=40, cadence=10),
+        W.pyrazine_bilinear(n_traj=2500, n_steps=60, cadence=6),
+        W.random_bilinear(42, n_states=3, n_modes=6, n_pairs=4, degree=3, n_traj=1200, n_steps=40, cadence=10),
+        W.random_bilinear(43, n_states=2, n_modes=8, all_pairs=True, shared=True, n_traj=1800, n_steps=40,
+                          cadence=10),
+    ]
+    specs = [JobSpec(wl, prec="fp64" if i % 2 else "fp32", name=f"job{i}") for i, wl in enumerate(wls)]
+    be = DeviceBackend()
+    fps = [be.footprint(s) for s in specs]
+    srv = Server(be, memory_budget=max(fps) * 3, max_slots=4, quantum_steps=16)
+    results = srv.run([0.002 * i for i in range(len(specs))], specs)
+    assert len(results) == len(specs) and not any(r.error for r in results)
+    by_name = {r.name: r for r in results}
+    for s in specs:
+        assert np.array_equal(by_name[s.name].out, _alone(P, s.workload, s.prec)), s.name
