@@ -242,16 +242,20 @@ def poly_leg(P, torch):
     frequencies and a quartic tuning mode (1e7 walkers, 200 steps of 0.5 fs)
     and a 3-state, 16-mode quartic model (1e6 walkers, 200 steps), then the
     same pyrazine-like model with two cross-mode bilinear terms (1e7
-    walkers, 200 steps) and a 3-state, 16-mode quartic model with four
-    (1e6 walkers), both precisions; walker-steps/s of sample + propagate +
-    reduce and the propagate kernel's own time."""
+    walkers, 200 steps), a 3-state, 16-mode quartic model with four, and a
+    2-state, 8-mode model with every pair of modes coupled by a mixing
+    shared by the states (sixteen squared combinations; 1e6 walkers), both
+    precisions; walker-steps/s of sample + propagate + reduce and the
+    propagate kernel's own time."""
     import workloads as W
     cases = (("pyrazine_qvc", W.pyrazine_qvc(n_traj=10_000_000, n_steps=200, cadence=10)),
              ("poly_n3_m16_d4", W.random_poly(20, n_states=3, n_modes=16, degree=4, n_traj=1_000_000,
                                                n_steps=200, cadence=10, dt=0.02)),
              ("pyrazine_bilinear", W.pyrazine_bilinear(n_traj=10_000_000, n_steps=200, cadence=10)),
              ("bilinear_n3_m16_d4_p4", W.random_bilinear(20, n_states=3, n_modes=16, n_pairs=4, degree=4,
-                                                         n_traj=1_000_000, n_steps=200, cadence=10, dt=0.02)))
+                                                         n_traj=1_000_000, n_steps=200, cadence=10, dt=0.02)),
+             ("bilinear_n2_m8_all_shared", W.random_bilinear(21, n_states=2, n_modes=8, all_pairs=True, shared=True,
+                                                             n_traj=1_000_000, n_steps=200, cadence=10)))
     return _model_runs(P, torch, cases)
 
 
@@ -314,6 +318,25 @@ def resample_leg(P, torch, n_traj=10_000_000, reps=20, replicas=64, replica_traj
     out = {"n_traj": n_traj, "prec": prec, "ms": ms, "walkers_per_s": n_traj / (ms / 1e3),
            "algorithmic_bytes_per_walker": 2 * state_bytes, "GB_per_s": alg / (ms / 1e3) / 1e9,
            "frac_of_hbm_peak": alg / (ms / 1e3) / 8e12}
+    # the same on a binary64 ensemble (sampled; the state arrays double in size)
+    src = P.Ensemble(model, n_traj, "fp64")
+    dst = P.Ensemble(model, n_traj, "fp64")
+    part = P.Partials(model, n_traj, 2)
+    P.qcl_sample_initial(model, wl.init, r.seed, src, part, stream)
+    P.qcl_propagate(model, src, r.dt, 200, 200, r.seed, part, 0, stream)
+    ws = P.qcl_resample(model, src, dst, r.seed, None, stream)
+    for a, b in ev:
+        a.record(stream)
+        P.qcl_resample(model, src, dst, r.seed, ws, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms64 = sum(a.elapsed_time(b) for a, b in ev) / reps
+    sb64 = (2 * M + N * N) * 8 + 22
+    out["fp64"] = {"ms": ms64, "algorithmic_bytes_per_walker": 2 * sb64,
+                   "GB_per_s": 2 * sb64 * n_traj / (ms64 / 1e3) / 1e9,
+                   "frac_of_hbm_peak": 2 * sb64 * n_traj / (ms64 / 1e3) / 8e12}
+    del src, dst, part, ws
+    torch.cuda.empty_cache()
     sw = W.pyrazine_ci(n_traj=0, n_steps=60, cadence=2)
     if not replicas:
         return out
