@@ -1,5 +1,5 @@
 """Fixed-budget branching: propagation with systematic resampling between
-calls, and the replica study that judges whether it pays.
+calls, and the replica study that measures whether it pays.
 
 The paper's CPU code spawned a walker whenever a transition was taken
 (Sec. II.B), so the weight growth prod(1 + S) along a walker became growth
