@@ -26,3 +26,18 @@ def test_traffic_only_for_the_profiled_build(tmp_path, monkeypatch):
     assert bench.measured_traffic(1000, "fp64") is None
     prof.write_text(prof.read_text().replace(good, "0" * 64))
     assert bench.measured_traffic(1000, "fp32") is None
+
+
+def test_committed_counters_match_the_current_kernel_sources():
+    """The headline's HBM counter profile was taken on the kernel sources as
+    they stand, so the bench line carries roofline.traffic."""
+    import bench
+    assert bench.measured_traffic(10_000_000, "fp32") is not None
+
+
+def test_oracle_beside_the_other_legs():
+    import bench
+    legs = bench._oracle_other_legs()
+    assert set(legs) == {"pyrazine_bilinear", "resample"}
+    for v in legs.values():
+        assert v["value"] > 0 and v["cores"] >= 1 and v["sample"]
