@@ -188,15 +188,16 @@ def test_million_walkers_bit_exact(P):
     _check(g, o, "1e6")
 
 
-def test_full_size_sampled(P):
-    """Ten million binary32 walkers of the pyrazine-like model (the ensemble
-    of the throughput runs) with heavy-tailed signed weights, 0.5% of them
-    zero: every output's source is checked for order and liveness, and 4096
-    sampled outputs against the oracle's per-output definition (source,
-    weight and state bit-exact)."""
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_full_size_sampled(P, prec):
+    """Ten million walkers of the pyrazine-like model (the ensemble of the
+    throughput runs, both precisions of the resampling leg) with
+    heavy-tailed signed weights, 0.5% of them zero: every output's source is
+    checked for order and liveness, and 4096 sampled outputs against the
+    oracle's per-output definition (source, weight and state bit-exact)."""
     import torch
     wl = W.pyrazine_ci()
-    T, prec, seed, step = 10_000_000, "fp32", 21, 200
+    T, seed, step = 10_000_000, 21, 200
     model = P.Model(wl.model)
     N, M = model.n_states, model.n_modes
     rng = np.random.default_rng(seed)
@@ -221,7 +222,7 @@ def test_full_size_sampled(P):
         assert g["w"][j] == s["w"][i] * (float(K) / (float(T) * float(k[i]))), j
         for key in ("q", "p", "U", "phase", "a", "b"):
             assert _same(g[key][j], s[key][i]), (j, key)
-    print(f"[1e7] K={K} U={U} distinct sources={len(np.unique(idx))}", flush=True)
+    print(f"[1e7 {prec}] K={K} U={U} distinct sources={len(np.unique(idx))}", flush=True)
 
 
 def test_propagate_resample_propagate_matches_oracle(P):
