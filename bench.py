@@ -548,7 +548,7 @@ def main():
     achieved = fl * tsteps / (ms_prop / 1e3) / 1e12
     peak = PEAK_TFLOPS[args.prec]
     line = {
-        "metric": "trajectory-steps/s (3-mode CI model, 1e7 walkers)",
+        "metric": "trajectory-steps/s FP32 vs FP64 (3-mode CI model, 1e7 traj); p50/p99 job latency",
         "value": value,
         "unit": "trajectory-steps/s",
         "n_gpus": 1,
