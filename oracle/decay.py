@@ -14,7 +14,12 @@ here turn that into numbers, with plain loops and closed-form sums:
   least-squares line through (t_k, ln P_k) with weights (P_k/SE_k)^2, the
   inverse of the first-order variance of ln P_k; the normal equations are
   solved in closed form, and the rate's standard error is the square root of
-  the slope's variance, W / (W Sxx - Sx^2).
+  the slope's variance, W / (W Sxx - Sx^2);
+- the fit's quality is chi^2 per degree of freedom, the weighted sum of
+  squared residuals of ln P over (bins - 2); when it exceeds 1 the single
+  exponential does not describe the window within the bins' errors, and the
+  rate's error is scaled by sqrt(chi^2/dof) (the Birge ratio), so the quoted
+  error covers the scatter the fit leaves.
 """
 from __future__ import annotations
 
@@ -69,3 +74,21 @@ def decay_rate(t, p, se, t0, t1):
     slope = (W * Sxy - Sx * Sy) / det
     intercept = (Sy - slope * Sx) / W
     return -slope, math.sqrt(W / det), math.exp(intercept), used
+
+
+def fit_quality(t, p, se, t0, t1, k, amp):
+    """chi^2 per degree of freedom of ln P = ln A - k t over t0 <= t <= t1,
+    each bin weighted by (P/SE)^2 (0 with fewer than three bins)."""
+    chi2 = 0.0
+    used = 0
+    for tk, pk, sk in zip(t, p, se):
+        if t0 <= tk <= t1:
+            r = math.log(pk) - (math.log(amp) - k * tk)
+            chi2 += (pk / sk) ** 2 * r * r
+            used += 1
+    return chi2 / (used - 2) if used > 2 else 0.0
+
+
+def scaled_rate_error(rate_se, chi2_per_dof):
+    """The rate's error scaled by the Birge ratio when the fit is poor."""
+    return rate_se * math.sqrt(max(1.0, chi2_per_dof))

@@ -305,12 +305,15 @@ class Ensemble:
 
 
 class Partials:
+    """Tile partial sums of one ensemble (qcl_partials_bytes of them)."""
+
     def __init__(self, model: Model, n_traj: int, n_out: int, device="cuda"):
         torch = _torch()
         nb = model.partials_bytes(n_traj, n_out)
         self.tensor = torch.zeros(max(nb // 8, 1), dtype=torch.float64, device=device)
         self.n_out = int(n_out)
         self.n_traj = int(n_traj)
+        self.n_states = int(model.n_states)
 
     @property
     def ptr(self):
@@ -319,7 +322,21 @@ class Partials:
 
 # ------------------------------------------------------------- entry points
 
+def _match(model: Model, ens: Optional[Ensemble] = None, partials: Optional[Partials] = None):
+    """Raises before any launch when the buffers were not made for this
+    model and for each other: the C ABI takes raw pointers, so a
+    mismatch would write past the end of a device buffer."""
+    if ens is not None:
+        if ens.model is not model and ens.model.handle.value != model.handle.value:
+            raise ValueError("the ensemble was made for another model")
+        if partials is not None and partials.n_traj != ens.n_traj:
+            raise ValueError(f"partials hold {partials.n_traj} walkers, the ensemble {ens.n_traj}")
+    if partials is not None and partials.n_states != model.n_states:
+        raise ValueError(f"partials hold {partials.n_states} states, the model {model.n_states}")
+
+
 def qcl_sample_initial(model: Model, init, seed: int, ens: Ensemble, partials: Partials, stream=None):
+    _match(model, ens, partials)
     q0 = np.ascontiguousarray(init.q0, np.float64)
     d = qcl_init_desc(float(init.kT), _dptr(q0), int(init.state), int(init.basis))
     _check(load_library().qcl_sample_initial(model.handle, C.byref(d), C.c_uint64(int(seed)), C.byref(ens.c),
@@ -328,6 +345,7 @@ def qcl_sample_initial(model: Model, init, seed: int, ens: Ensemble, partials: P
 
 def qcl_propagate(model: Model, ens: Ensemble, dt: float, n_steps: int, cadence: int, seed: int,
                   partials: Partials, scheme: int = QCL_TRANS_NORMALIZED, stream=None, occupancy: int = 0):
+    _match(model, ens, partials)
     pd = qcl_prop_desc(float(dt), int(n_steps), int(cadence), partials.n_out, int(scheme), int(seed),
                        int(occupancy), 0)
     _check(load_library().qcl_propagate(model.handle, C.byref(ens.c), C.byref(pd), partials.ptr,
@@ -344,6 +362,7 @@ class BatchJob:
         self.seed, self.scheme, self.occupancy = int(seed), int(scheme), int(occupancy)
 
     def item(self) -> qcl_batch_item:
+        _match(self.model, self.ens, self.partials)
         pd = qcl_prop_desc(self.dt, self.n_steps, self.cadence, self.partials.n_out, self.scheme,
                            self.seed, self.occupancy, 0)
         return qcl_batch_item(self.model.handle, C.pointer(self.ens.c), pd, self.partials.ptr)
@@ -389,6 +408,11 @@ def qcl_propagate_batch(jobs, workspace: Optional[Workspace] = None, stream=None
 def qcl_reduce_observables(model: Model, partials: Partials, n_traj: int, out=None, stream=None):
     """Returns a device tensor [n_out, 2, N, N, 4]: mean Re, mean Im, SE Re, SE Im."""
     torch = _torch()
+    _match(model, None, partials)
+    if int(n_traj) != partials.n_traj:
+        # the reduction's scratch rows sit after the tile rows of
+        # partials.n_traj walkers; another count would place them over live rows
+        raise ValueError(f"n_traj {n_traj} differs from the {partials.n_traj} walkers of the partials")
     N = model.n_states
     shape = (partials.n_out, 2, N, N, 4)
     if out is None:
@@ -412,6 +436,8 @@ def qcl_resample(model: Model, src: Ensemble, dst: Ensemble, seed: int, workspac
     """Fixed-budget systematic resampling of src into dst (same size, precision
     and traj_offset); dst continues at src's step.  Returns the workspace."""
     L = load_library()
+    _match(model, src)
+    _match(model, dst)
     nb = C.c_size_t(0)
     _check(L.qcl_resample_workspace_bytes(src.n_traj, C.byref(nb)))
     ws = workspace or Workspace(device=src.buffer.device)

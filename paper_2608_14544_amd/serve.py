@@ -11,8 +11,9 @@ models and sizes can share a launch).  Between quanta it
     (first come first served; a job that does not fit lets smaller ones
     behind it start, until it has waited ``max_backfill_wait`` seconds);
   * retires jobs whose last step has been enqueued: their observables are
-    reduced on the device, copied to host memory asynchronously and their
-    device buffers are given back.
+    reduced on the device and copied to host memory asynchronously; their
+    device buffers, and their share of the memory budget, are given back
+    once that copy has completed.
 
 A quantum is either a fixed step count per job (``quantum_steps``) or a
 fixed amount of work per job (``quantum_work`` walker-steps, i.e.
@@ -250,7 +251,9 @@ class Server:
                     j.pending = self.backend.finish(j.handle, j.spec)
                     self.backend.release(j.handle)
                     j.handle = None
-                    self.used -= j.footprint
+                    # the job's buffers stay alive until its reduction and
+                    # copy have completed: its footprint is given back in
+                    # _collect, once the result is ready
                     self.draining.append(j)
                 else:
                     still.append(j)
@@ -288,6 +291,7 @@ class Server:
         done, keep = [], []
         for j in self.draining:
             if j.pending.ready():
+                self.used -= j.footprint
                 r = JobResult(j.job_id, j.spec.name, j.pending.result(), j.arrival, j.admitted, self.now(),
                               j.spec.walker_steps)
                 self.results.append(r)

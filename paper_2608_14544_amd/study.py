@@ -26,7 +26,11 @@ numbers below are this module's readings of it):
   0.3, the fast segment of the decay (the pyrazine-like population drops
   from 0.8 to 0.3 within about 5 fs and then flattens near 0.2).  A run
   whose P is not positive somewhere in the window has no log fit; its rate
-  is reported as None.
+  is reported as None;
+- fit quality: chi^2 per degree of freedom of that fit.  Above 1 the single
+  exponential does not describe the window within the bins' errors, and the
+  reported rate error ``rate_se`` is the statistical one (``rate_se_stat``)
+  times sqrt(chi^2/dof), the Birge ratio.
 """
 from __future__ import annotations
 
@@ -84,11 +88,16 @@ def crossing_time(t: np.ndarray, p: np.ndarray, level: float) -> float:
 @dataclass
 class DecayFit:
     rate: float
-    rate_se: float
+    rate_se: float        # statistical error of the slope
     amplitude: float
     window: Tuple[float, float]
     n_bins: int
     chi2_per_dof: float
+
+    @property
+    def rate_se_scaled(self) -> float:
+        """The rate's error scaled by sqrt(chi^2/dof) when that exceeds 1."""
+        return self.rate_se * float(np.sqrt(max(1.0, self.chi2_per_dof)))
 
 
 def decay_fit(t: np.ndarray, p: np.ndarray, se: np.ndarray, window: Tuple[float, float]) -> DecayFit:
@@ -166,8 +175,8 @@ def summarize(curves: Sequence[Curve], tol: float = 0.02, window: Optional[Tuple
         if fit:
             try:
                 f = decay_fit(c.t, c.p, c.se, window)
-                row.update(rate=f.rate, rate_se=f.rate_se, amplitude=f.amplitude, fit_bins=f.n_bins,
-                           chi2_per_dof=f.chi2_per_dof)
+                row.update(rate=f.rate, rate_se=f.rate_se_scaled, rate_se_stat=f.rate_se, amplitude=f.amplitude,
+                           fit_bins=f.n_bins, chi2_per_dof=f.chi2_per_dof)
             except ValueError as e:  # a noisy run with P <= 0 inside the window has no log fit
                 row.update(rate=None, fit_error=str(e))
         rows.append(row)

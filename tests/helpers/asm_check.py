@@ -23,7 +23,9 @@ entered from an arm's last instruction or by ``s_cbranch_execz``.  A
 finding is a place to read, not proof of an error; the current kernels have
 none.
 
-    python -m paper_2608_14544_amd.asm_check        # all kernel sources, ~8 minutes
+    python tests/helpers/asm_check.py        # all kernel sources, ~8 minutes
+
+It is a test of the build, not part of the library.
 """
 from __future__ import annotations
 
@@ -35,7 +37,10 @@ import tempfile
 from concurrent.futures import ThreadPoolExecutor
 from typing import Dict, List, Tuple
 
-from . import build as B
+_ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+if _ROOT not in sys.path:
+    sys.path.insert(0, _ROOT)
+from paper_2608_14544_amd import build as B  # noqa: E402
 
 _LABEL = re.compile(r"^(\.LBB\d+_\d+):")
 _FUNC = re.compile(r"^(_Z\w+):")

@@ -206,3 +206,31 @@ def test_bilinear_limits_on_host():
         h = C.c_void_p()
         assert L.qcl_create_model_bilinear(C.byref(d), None, C.byref(bd), C.byref(h)) == qcl.QCL_ERR_UNSUPPORTED
         assert not h.value
+
+
+def test_binding_rejects_mismatched_buffers_before_any_launch():
+    """The binding checks that an ensemble, its partials and the model
+    belong together (the C ABI takes raw pointers, so a mismatch would
+    write past the end of a device buffer), and that a reduction uses the
+    partials' own walker count (its scratch rows follow the tile rows)."""
+    import types
+    from paper_2608_14544_amd import qcl
+    m1 = types.SimpleNamespace(handle=C.c_void_p(0x1000), n_states=2)
+    m2 = types.SimpleNamespace(handle=C.c_void_p(0x2000), n_states=3)
+    ens = types.SimpleNamespace(model=m1, n_traj=500)
+    part = types.SimpleNamespace(n_traj=500, n_states=2, n_out=3)
+    qcl._match(m1, ens, part)  # consistent
+    with pytest.raises(ValueError, match="another model"):
+        qcl._match(m2, ens, part)
+    with pytest.raises(ValueError, match="partials hold 400 walkers"):
+        qcl._match(m1, ens, types.SimpleNamespace(n_traj=400, n_states=2, n_out=3))
+    with pytest.raises(ValueError, match="states"):
+        qcl._match(m1, ens, types.SimpleNamespace(n_traj=500, n_states=3, n_out=3))
+    with pytest.raises(ValueError, match="n_traj 499"):
+        qcl.qcl_reduce_observables(m1, part, 499)
+    with pytest.raises(ValueError, match="another model"):
+        qcl.qcl_propagate(m2, ens, 0.1, 10, 5, 0, part)
+    with pytest.raises(ValueError, match="another model"):
+        qcl.BatchJob(m2, ens, part, 0.1, 10, 5, 0).item()
+    with pytest.raises(ValueError, match="another model"):
+        qcl.qcl_sample_initial(m2, None, 0, ens, part)

@@ -1,6 +1,6 @@
 """The assembly scan for vector writes placed before an exec restore at a
 join (host-only, on short excerpts of gfx950 assembly)."""
-from paper_2608_14544_amd.asm_check import scan
+from helpers.asm_check import scan
 
 BAD = """
 _ZN3qcl12_GLOBAL__N_119propagate_nN_kernelILi2E:

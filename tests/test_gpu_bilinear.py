@@ -15,7 +15,8 @@ import pytest
 
 import workloads as W
 from test_gpu_batch import _assert_same, _batched, _solo
-from test_gpu_parity import _oracle_state, compare_walkers, ensemble_close, gpu_run, oracle_run
+from parity import (check_ensemble32, check_ensemble64, compare_walkers, gpu_run, oracle_run, oracle_walkers,
+                    sample_ids, sampled_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -61,9 +62,8 @@ def test_bilinear_fp64_parity(P, name):
     out_g, st_g, s0_g, _ = gpu_run(P, wl)
     out_o, st_o, s0_o, _ = oracle_run(wl)
     compare_walkers(s0_g, s0_o, rtol=1e-11, label=name + " sample")
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label=name)
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.005, label=name)
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label=name)
 
 
 def test_bilinear_only_model_fp64_parity(P):
@@ -76,21 +76,17 @@ def test_bilinear_only_model_fp64_parity(P):
     wl = W.Workload(only, base.init, base.run)
     out_g, st_g, _, _ = gpu_run(P, wl)
     out_o, st_o, _, _ = oracle_run(wl)
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label="bilinear only")
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.005, label="bilinear only")
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label="bilinear only")
 
 
 @pytest.mark.parametrize("name", ["pyrazine_bilinear", "n4_m4_p3_d4"])
 def test_bilinear_fp32_ensemble(P, name):
     wl = CASES[name]()
     wl.run.n_traj = 40_000
-    out_g, _, _, _ = gpu_run(P, wl, prec="fp32")
-    out_o, _, _, _ = oracle_run(wl)
-    d = np.abs(out_g[..., :2] - out_o[..., :2])
-    se = np.maximum(out_o[..., 2:], 1e-300)
-    print(name, "fp32 max abs err", d.max(), "max err/SE", (d / se).max(), flush=True)
-    assert np.all((d <= 1e-3) | (d <= 3 * se))
+    out_g, st_g, _, _ = gpu_run(P, wl, prec="fp32")
+    out_o, st_o, _, _ = oracle_run(wl)
+    check_ensemble32(out_g, out_o, wl.run.n_traj, label=name, g=st_g, o=st_o)
 
 
 def test_bilinear_linear_rule(P):
@@ -98,9 +94,8 @@ def test_bilinear_linear_rule(P):
     out_g, st_g, _, _ = gpu_run(P, wl, scheme=1)
     out_o, st_o, _, fl_o = oracle_run(wl, scheme=1)
     assert np.array_equal(st_g["flags"] & 8, np.asarray(fl_o) & 8)
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label="bilinear linear")
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.005, label="bilinear linear")
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label="bilinear linear")
 
 
 @pytest.mark.parametrize("T", [0, 1, 255, 257])
@@ -111,8 +106,8 @@ def test_bilinear_empty_and_ragged(P, T):
         assert out_g is None and st_g["w"].size == 0
         return
     out_o, st_o, _, _ = oracle_run(wl)
-    compare_walkers(st_g, st_o, rtol=1e-9, label=f"bilinear T={T}")
-    assert ensemble_close(out_g, out_o, T)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, label=f"bilinear T={T}")
+    check_ensemble64(out_g, out_o, T, flip, st_g, st_o, label=f"bilinear T={T}")
 
 
 def test_bilinear_slicing_bitwise(P):
@@ -148,9 +143,8 @@ def test_bilinear_32_modes(P):
     wl = W.random_bilinear(10, n_states=3, n_modes=30, n_pairs=4, degree=4, n_traj=300, n_steps=30, cadence=10)
     out_g, st_g, _, _ = gpu_run(P, wl)
     out_o, st_o, _, _ = oracle_run(wl)
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.01, label="bilinear M30")
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.01, label="bilinear M30")
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label="bilinear M30")
 
 
 def test_bilinear_bench_configuration_full_size(P):
@@ -159,7 +153,6 @@ def test_bilinear_bench_configuration_full_size(P):
     ensemble recomputed one by one by the oracle, and the binary32 run's
     populations within 2e-3 of the binary64 run's while resolved."""
     import torch
-    import oracle.core as oc
     wl = W.pyrazine_bilinear(n_traj=10_000_000, n_steps=200, cadence=10)
     r = wl.run
     model = P.Model(wl.model)
@@ -171,26 +164,11 @@ def test_bilinear_bench_configuration_full_size(P):
         P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part)
         outs[prec] = P.qcl_reduce_observables(model, part, r.n_traj).cpu().numpy()
         if prec == "fp64":
-            t = ens.tensors()
-            ids = np.array([0, 255, 256, 1 << 20, 5_555_555, r.n_traj - 1])
-            g = {"q": t["q"][:, ids].cpu().numpy().T, "p": t["p"][:, ids].cpu().numpy().T,
-                 "U": t["u"][:, ids].cpu().numpy().T.reshape(-1, 2, 2), "w": t["w"][ids].cpu().numpy(),
-                 "phase": t["phase"][ids].cpu().numpy(), "a": t["a"][ids].cpu().numpy().astype(np.int32),
-                 "b": t["b"][ids].cpu().numpy().astype(np.int32)}
+            ids = sample_ids(r.n_traj, 120, seed=3, extra=[1 << 20, 5_555_555])
+            g = sampled_state(ens, ids)
         del ens, part
         torch.cuda.empty_cache()
-    m = oc.Model(wl.model)
-    o = {k: [] for k in g}
-    for i in ids:
-        st, _ = oc.sample(m, wl.init, r.seed, 1, traj_offset=int(i))
-        oc.propagate(m, st, r.dt, r.n_steps, r.cadence, r.seed, r.n_out)
-        for k, v in _oracle_state(st).items():
-            o[k].append(v[0])
-    o = {k: np.array(v) for k, v in o.items()}
-    compare_walkers(g, o, rtol=1e-8, max_flip_frac=0.2, label="pyrazine_bilinear 1e7 sampled")
-    o64, o32 = outs["fp64"], outs["fp32"]
-    se = np.max(np.stack([o64[:, 0, i, i, 2] for i in range(2)]), axis=0)
-    res = int(np.argmax(~(se < 0.01))) if np.any(~(se < 0.01)) else len(se)
-    d = max(float(np.abs(o32[:res, 0, i, i, 0] - o64[:res, 0, i, i, 0]).max()) for i in range(2))
-    print("fp32 vs fp64 population diff", d, "over", res, "resolved bins", flush=True)
-    assert res >= 3 and d <= 2e-3
+    o = oracle_walkers(wl, ids)
+    compare_walkers(g, o, rtol=1e-10, max_flip_frac=0.01, label="pyrazine_bilinear 1e7 sampled")
+    # binary32 against binary64 on every bin
+    check_ensemble32(outs["fp32"], outs["fp64"], r.n_traj, label="pyrazine_bilinear fp32 vs fp64")

@@ -5,9 +5,9 @@ above 2^26)."""
 import numpy as np
 import pytest
 
-import oracle.core as oc
 import workloads as W
-from test_gpu_parity import _oracle_state, compare_walkers, ensemble_close, gpu_run, oracle_run
+from parity import (check_ensemble32, check_ensemble64, compare_walkers, gpu_run, oracle_run, oracle_walkers,
+                    sample_ids, sampled_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -42,13 +42,10 @@ def test_general_largest_mode_bucket(P, n_states, n_modes):
     out_g, st_g, s0_g, _ = gpu_run(P, wl)
     out_o, st_o, s0_o, _ = oracle_run(wl)
     compare_walkers(s0_g, s0_o, rtol=1e-11, label=f"N{n_states} M{n_modes} sample")
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.01, label=f"N{n_states} M{n_modes}")
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
-    out32, _, _, _ = gpu_run(P, wl, prec="fp32")
-    d = np.abs(out32[..., :2] - out_o[..., :2])
-    se = np.maximum(out_o[..., 2:], 1e-300)
-    assert np.all((d <= 1e-3) | (d <= 3 * se))
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.01, label=f"N{n_states} M{n_modes}")
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label=f"N{n_states} M{n_modes}")
+    out32, st32, _, _ = gpu_run(P, wl, prec="fp32")
+    check_ensemble32(out32, out_o, wl.run.n_traj, label=f"N{n_states} M{n_modes} fp32", g=st32, o=st_o)
 
 
 def test_headline_model_at_1e8_walkers(P):
@@ -64,20 +61,9 @@ def test_headline_model_at_1e8_walkers(P):
     P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
     P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part)
     torch.cuda.synchronize()
-    t = ens.tensors()
-    ids = np.array([0, 1 << 24, (1 << 26) + 3, 77_777_777, r.n_traj - 257, r.n_traj - 1])
-    g = {"q": t["q"][:, ids].cpu().numpy().T, "p": t["p"][:, ids].cpu().numpy().T,
-         "U": t["u"][:, ids].cpu().numpy().T.reshape(-1, 2, 2), "w": t["w"][ids].cpu().numpy(),
-         "phase": t["phase"][ids].cpu().numpy(), "a": t["a"][ids].cpu().numpy().astype(np.int32),
-         "b": t["b"][ids].cpu().numpy().astype(np.int32)}
+    ids = sample_ids(r.n_traj, 120, seed=8, extra=[1 << 24, (1 << 26) + 3, 77_777_777])
+    g = sampled_state(ens, ids)
     del ens, part
     torch.cuda.empty_cache()
-    m = oc.Model(wl.model)
-    o = {k: [] for k in g}
-    for i in ids:
-        st, _ = oc.sample(m, wl.init, r.seed, 1, traj_offset=int(i))
-        oc.propagate(m, st, r.dt, r.n_steps, r.cadence, r.seed, r.n_out)
-        for k, v in _oracle_state(st).items():
-            o[k].append(v[0])
-    o = {k: np.array(v) for k, v in o.items()}
-    compare_walkers(g, o, rtol=1e-8, max_flip_frac=0.2, label="pyrazine 1e8 sampled")
+    o = oracle_walkers(wl, ids)
+    compare_walkers(g, o, rtol=1e-10, max_flip_frac=0.01, label="pyrazine 1e8 sampled")

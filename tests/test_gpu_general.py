@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from test_gpu_parity import compare_walkers, ensemble_close, gpu_run, oracle_run
+from parity import check_ensemble32, check_ensemble64, compare_walkers, gpu_run, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -40,21 +40,17 @@ def test_general_fp64_parity(P, name):
     out_g, st_g, s0_g, _ = gpu_run(P, wl)
     out_o, st_o, s0_o, _ = oracle_run(wl)
     compare_walkers(s0_g, s0_o, rtol=1e-11, label=name + " sample")
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label=name)
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.005, label=name)
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label=name)
 
 
 @pytest.mark.parametrize("name", ["n3_m3", "n4_m5", "n2_m12"])
 def test_general_fp32_ensemble(P, name):
     wl = CASES[name]()
     wl.run.n_traj = 40_000
-    out_g, _, _, _ = gpu_run(P, wl, prec="fp32")
-    out_o, _, _, _ = oracle_run(wl)
-    d = np.abs(out_g[..., :2] - out_o[..., :2])
-    se = np.maximum(out_o[..., 2:], 1e-300)
-    print(name, "fp32 max abs err", d.max(), "max err/SE", (d / se).max(), flush=True)
-    assert np.all((d <= 1e-3) | (d <= 3 * se))
+    out_g, st_g, _, _ = gpu_run(P, wl, prec="fp32")
+    out_o, st_o, _, _ = oracle_run(wl)
+    check_ensemble32(out_g, out_o, wl.run.n_traj, label=name, g=st_g, o=st_o)
 
 
 @pytest.mark.parametrize("T", [1, 255, 257])
@@ -62,8 +58,8 @@ def test_general_ragged(P, T):
     wl = W.random_lvc(3, n_states=3, n_modes=4, n_traj=T, n_steps=40, cadence=7)
     out_g, st_g, _, _ = gpu_run(P, wl)
     out_o, st_o, _, _ = oracle_run(wl)
-    compare_walkers(st_g, st_o, rtol=1e-9, label=f"general T={T}")
-    assert ensemble_close(out_g, out_o, T)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, label=f"general T={T}")
+    check_ensemble64(out_g, out_o, T, flip, st_g, st_o, label=f"general T={T}")
 
 
 def test_general_determinism_and_slicing(P):
@@ -95,14 +91,11 @@ def test_general_fp32_near_degenerate(P):
     threshold; ensemble averages stay within 1e-3 (or 3 SE) of the oracle."""
     wl = _crossing_model()
     out_g, st_g, _, _ = gpu_run(P, wl, prec="fp32")
-    out_o, _, _, _ = oracle_run(wl)
+    out_o, st_o, _, _ = oracle_run(wl)
     refined = (st_g["flags"] & 4) != 0
     print("refined walkers", refined.mean(), flush=True)
     assert refined.mean() > 0.002  # the refinement ran for a few hundred walkers
-    d = np.abs(out_g[..., :2] - out_o[..., :2])
-    se = np.maximum(out_o[..., 2:], 1e-300)
-    print("crossing3 fp32 max abs err", d.max(), "max err/SE", (d / se).max(), flush=True)
-    assert np.all((d <= 1e-3) | (d <= 3 * se))
+    check_ensemble32(out_g, out_o, wl.run.n_traj, label="crossing3", g=st_g, o=st_o)
 
 
 @pytest.mark.parametrize("name", ["n3_m3", "n4_m5"])
@@ -113,9 +106,8 @@ def test_general_linear_rule_parity(P, name):
     out_g, st_g, _, _ = gpu_run(P, wl, scheme=1)
     out_o, st_o, _, fl_o = oracle_run(wl, scheme=1)
     assert np.array_equal(st_g["flags"] & 8, np.asarray(fl_o) & 8)  # same walkers fell back
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label=name + " linear")
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.005, label=name + " linear")
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label=name + " linear")
 
 
 @pytest.mark.parametrize("n_states", [2, 3, 4])
@@ -132,6 +124,5 @@ def test_adiabatic_initial_state(P, n_states):
     out_o, st_o, s0_o, _ = oracle_run(wl)
     assert np.all(s0_g["a"] == n_states - 1) and np.all(s0_g["b"] == n_states - 1) and np.all(s0_g["w"] == 1.0)
     compare_walkers(s0_g, s0_o, rtol=1e-11, label=f"adiabatic N{n_states} sample")
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label=f"adiabatic N{n_states}")
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.005, label=f"adiabatic N{n_states}")
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label=f"adiabatic N{n_states}")

@@ -7,7 +7,7 @@ import pytest
 
 import workloads as W
 from test_gpu_batch import _assert_same, _batched, _solo
-from test_gpu_parity import compare_walkers, ensemble_close, gpu_run, oracle_run
+from parity import check_ensemble32, check_ensemble64, compare_walkers, gpu_run, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -58,21 +58,17 @@ def test_many_states_fp64_parity(P, name):
     out_g, st_g, s0_g, _ = gpu_run(P, wl)
     out_o, st_o, s0_o, _ = oracle_run(wl)
     compare_walkers(s0_g, s0_o, rtol=1e-10, label=name + " sample")
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.01, label=name)
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.01, label=name)
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label=name)
 
 
 @pytest.mark.parametrize("name", ["n6_m8_dense", "n8_m4_dense"])
 def test_many_states_fp32_ensemble(P, name):
     wl = CASES[name]()
     wl.run.n_traj = 20_000
-    out_g, _, _, _ = gpu_run(P, wl, prec="fp32")
-    out_o, _, _, _ = oracle_run(wl)
-    d = np.abs(out_g[..., :2] - out_o[..., :2])
-    se = np.maximum(out_o[..., 2:], 1e-300)
-    print(name, "fp32 max abs err", d.max(), "max err/SE", (d / se).max(), flush=True)
-    assert np.all((d <= 1e-3) | (d <= 3 * se))
+    out_g, st_g, _, _ = gpu_run(P, wl, prec="fp32")
+    out_o, st_o, _, _ = oracle_run(wl)
+    check_ensemble32(out_g, out_o, wl.run.n_traj, label=name, g=st_g, o=st_o)
 
 
 def test_many_states_linear_rule_and_ragged(P):
@@ -80,9 +76,8 @@ def test_many_states_linear_rule_and_ragged(P):
     out_g, st_g, _, _ = gpu_run(P, wl, scheme=1)
     out_o, st_o, _, fl_o = oracle_run(wl, scheme=1)
     assert np.array_equal(st_g["flags"] & 8, np.asarray(fl_o) & 8)
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.01, label="n6 linear ragged")
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.01, label="n6 linear ragged")
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label="n6 linear ragged")
 
 
 def test_many_states_slicing_and_batch_bitwise(P):

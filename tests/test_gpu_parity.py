@@ -1,19 +1,8 @@
-"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
-
-Tolerances (the headline configurations fix them):
-  * FP64 path, per walker: q, p, U, Phi within 1e-10 relative to
-    max(|value|, ensemble rms of that quantity), w within 1e-10 relative;
-    walkers whose transition decisions differ ("flips": a different final
-    element or |w| off by > 1e-6) are counted, reported and excluded.
-  * FP64 path, ensemble averages: within 1e-9 absolute, scaled by the
-    size of the summed terms where walker weights have grown past 1 (the
-    weights grow as prod(1 + S) along each walker, so late bins of the
-    conical-intersection model sum terms of order 1e5; there the bound is
-    1e-9 x the rms walker contribution, i.e. 1e-9 relative).
-  * FP32 path (binary32 propagation, binary64 phase/weights/sums):
-    ensemble averages within 1e-3 absolute or 3 standard errors.
-Integer state (element indices) must match exactly for non-flipped walkers.
-"""
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on
+the two-state workloads: per walker and per bin, FP64 and FP32, ragged and
+empty ensembles, determinism, the grid solution of Eq. 1, and the headline
+configuration at full size on sampled walkers.  Tolerances are stated in
+``parity.py``."""
 import json
 import math
 import os
@@ -21,8 +10,9 @@ import os
 import numpy as np
 import pytest
 
-import oracle.core as oc
 import workloads as W
+from parity import (check_ensemble32, check_ensemble64, compare_walkers, gpu_run, oracle_run, oracle_walkers,
+                    sample_ids, sampled_state)
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -37,72 +27,6 @@ def P():
     return pkg
 
 
-def _oracle_state(st):
-    return {"q": st.q, "p": st.p, "U": st.U, "w": st.w, "phase": st.phase, "a": st.a, "b": st.b}
-
-
-def compare_walkers(g, o, rtol=1e-10, max_flip_frac=0.0, label=""):
-    flip = (g["a"] != o["a"]) | (g["b"] != o["b"])
-    flip |= ~(np.abs(np.abs(g["w"]) - np.abs(o["w"])) <= 1e-6 * np.abs(o["w"]))
-    ok = ~flip
-    worst = {}
-    for key in ("q", "p", "U", "phase"):
-        gv, ov = g[key][ok], o[key][ok]
-        scale = max(float(np.sqrt(np.mean(o[key] ** 2))) if o[key].size else 1.0, 1e-300)
-        err = np.abs(gv - ov) / np.maximum(np.abs(ov), scale)
-        worst[key] = float(err.max()) if err.size else 0.0
-    errw = np.abs(g["w"][ok] - o["w"][ok]) / np.abs(o["w"][ok])
-    worst["w"] = float(errw.max()) if errw.size else 0.0
-    print(f"[{label}] walkers={len(ok)} flips={int(flip.sum())} worst-rel={worst}", flush=True)
-    assert flip.sum() <= max_flip_frac * len(ok), (label, int(flip.sum()))
-    for key, v in worst.items():
-        assert v <= rtol, (label, key, v)
-    return int(flip.sum())
-
-
-def ensemble_close(out_g, out_o, n_traj, tol=1e-9):
-    """max |gpu - oracle| over means, against tol * max(1, rms term)."""
-    rms = np.sqrt(out_o[..., 2:] ** 2 * n_traj + out_o[..., :2] ** 2)
-    bound = tol * np.maximum(1.0, rms)
-    err = np.abs(out_g[..., :2] - out_o[..., :2])
-    print("ensemble max abs err", float(err.max()), "max err/bound", float((err / bound).max()), flush=True)
-    return bool(np.all(err <= bound))
-
-
-def gpu_run(P, wl, prec="fp64", n_traj=None, n_steps=None, scheme=0, split=None):
-    import torch
-    r = wl.run
-    T = r.n_traj if n_traj is None else n_traj
-    S = r.n_steps if n_steps is None else n_steps
-    n_out = S // r.cadence + 1
-    model = P.Model(wl.model)
-    ens = P.Ensemble(model, T, prec)
-    part = P.Partials(model, T, n_out)
-    P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
-    sample_state = ens.to_numpy()
-    chunks = [S] if split is None else split
-    assert sum(chunks) == S
-    for c in chunks:
-        P.qcl_propagate(model, ens, r.dt, c, r.cadence, r.seed, part, scheme)
-    out = P.qcl_reduce_observables(model, part, T) if T > 0 else None
-    torch.cuda.synchronize()
-    return (out.cpu().numpy() if out is not None else None), ens.to_numpy(), sample_state, ens
-
-
-def oracle_run(wl, n_traj=None, n_steps=None, scheme=0):
-    r = wl.run
-    T = r.n_traj if n_traj is None else n_traj
-    S = r.n_steps if n_steps is None else n_steps
-    n_out = S // r.cadence + 1
-    m = oc.Model(wl.model)
-    st, s0 = oc.sample(m, wl.init, r.seed, T)
-    samp = _oracle_state(st.copy())
-    sums = np.zeros((n_out, 2, m.n, m.n, 4))
-    sums[0] = s0
-    oc.propagate(m, st, r.dt, S, r.cadence, r.seed, n_out, sums, scheme)
-    return oc.finalize(sums, T), _oracle_state(st), samp, st.flags
-
-
 # ------------------------------------------------------------------ FP64
 
 def test_spin_boson_1mode_fp64_full(P):
@@ -110,10 +34,12 @@ def test_spin_boson_1mode_fp64_full(P):
     out_g, st_g, s0_g, _ = gpu_run(P, wl)
     out_o, st_o, s0_o, _ = oracle_run(wl)
     compare_walkers(s0_g, s0_o, rtol=1e-12, label="sample")
-    compare_walkers(st_g, st_o, label="cfg0 end")
+    flip = compare_walkers(st_g, st_o, label="cfg0 end")
+    assert not flip.any()
     err = np.abs(out_g[..., :2] - out_o[..., :2]).max()
     print("ensemble max abs err", err, flush=True)
     assert err <= 1e-9
+    check_ensemble64(out_g, out_o, wl.run.n_traj, label="cfg0")
     np.testing.assert_allclose(out_g[..., 2:], out_o[..., 2:], rtol=1e-6, atol=1e-12)
 
 
@@ -126,9 +52,8 @@ def test_fp64_parity_models(P, name, T, S):
     out_g, st_g, s0_g, _ = gpu_run(P, wl, n_traj=T, n_steps=S)
     out_o, st_o, s0_o, _ = oracle_run(wl, n_traj=T, n_steps=S)
     compare_walkers(s0_g, s0_o, rtol=1e-12, label=name + " sample")
-    nflip = compare_walkers(st_g, st_o, max_flip_frac=0.002, label=name)
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, T)
+    flip = compare_walkers(st_g, st_o, max_flip_frac=0.002, label=name)
+    check_ensemble64(out_g, out_o, T, flip, st_g, st_o, label=name)
 
 
 @pytest.mark.parametrize("T", [1, 63, 255, 256, 257, 1000])
@@ -137,7 +62,8 @@ def test_ragged_sizes(P, T):
     S = 40
     out_g, st_g, _, _ = gpu_run(P, wl, n_traj=T, n_steps=S)
     out_o, st_o, _, _ = oracle_run(wl, n_traj=T, n_steps=S)
-    compare_walkers(st_g, st_o, label=f"T={T}")
+    flip = compare_walkers(st_g, st_o, label=f"T={T}")
+    assert not flip.any()
     assert np.abs(out_g[..., :2] - out_o[..., :2]).max() <= 1e-9
 
 
@@ -145,7 +71,8 @@ def test_linear_scheme_parity(P):
     wl = W.spin_boson_1mode(n_traj=4000, n_steps=100)
     out_g, st_g, _, _ = gpu_run(P, wl, scheme=1)
     out_o, st_o, _, _ = oracle_run(wl, scheme=1)
-    compare_walkers(st_g, st_o, label="linear")
+    flip = compare_walkers(st_g, st_o, label="linear")
+    assert not flip.any()
     assert np.abs(out_g[..., :2] - out_o[..., :2]).max() <= 1e-9
 
 
@@ -219,12 +146,8 @@ def test_fp32_ensemble_vs_oracle(P, name):
           "ohmic": W.spin_boson_ohmic(kT=0.2, n_traj=50_000, n_steps=400, cadence=40),
           "pyrazine": W.pyrazine_ci(n_traj=100_000, n_steps=100)}[name]
     out_g, st_g, _, _ = gpu_run(P, wl, prec="fp32")
-    out_o, _, _, _ = oracle_run(wl)
-    d = np.abs(out_g[..., :2] - out_o[..., :2])
-    se = np.maximum(out_o[..., 2:], 1e-300)
-    bad = (d > 1e-3) & (d > 3 * se)
-    print(name, "fp32 max abs err", d.max(), "max err/SE", (d / se).max(), flush=True)
-    assert not bad.any()
+    out_o, st_o, _, _ = oracle_run(wl)
+    check_ensemble32(out_g, out_o, wl.run.n_traj, label=name, g=st_g, o=st_o)
 
 
 # --------------------------------------------------------- whole estimator
@@ -250,9 +173,11 @@ def test_gpu_matches_grid_solution(P):
 
 def test_pyrazine_full_size_sampled_walkers(P):
     """The conical-intersection workload at its full size (1e7 walkers,
-    1000 steps) in the benchmark's launch configuration: sampled walkers
-    are recomputed one by one by the oracle, and ensemble invariants are
-    checked on the full reduction."""
+    1000 steps) in the benchmark's launch configuration: a few hundred
+    sampled walkers (first, last, tile edges and uniform draws) are
+    recomputed one by one by the oracle, at most 1 % of them may take a
+    different branch, and ensemble invariants are checked on the full
+    reduction."""
     import torch
     wl = W.pyrazine_ci()
     r = wl.run
@@ -263,26 +188,12 @@ def test_pyrazine_full_size_sampled_walkers(P):
     P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part)
     out = P.qcl_reduce_observables(model, part, r.n_traj).cpu().numpy()
     torch.cuda.synchronize()
-    t = ens.tensors()
-    rng = np.random.default_rng(0)
-    ids = np.unique(np.concatenate([[0, 1, 255, 256, r.n_traj - 1], rng.integers(0, r.n_traj, 59)]))
-    g = {"q": t["q"][:, ids].cpu().numpy().T, "p": t["p"][:, ids].cpu().numpy().T,
-         "U": t["u"][:, ids].cpu().numpy().T.reshape(-1, 2, 2), "w": t["w"][ids].cpu().numpy(),
-         "phase": t["phase"][ids].cpu().numpy(), "a": t["a"][ids].cpu().numpy().astype(np.int32),
-         "b": t["b"][ids].cpu().numpy().astype(np.int32)}
-    m = oc.Model(wl.model)
-    o = {k: [] for k in g}
-    for i in ids:
-        st, _ = oc.sample(m, wl.init, r.seed, 1, traj_offset=int(i))
-        oc.propagate(m, st, r.dt, r.n_steps, r.cadence, r.seed, r.n_out)
-        for k, v in _oracle_state(st).items():
-            o[k].append(v[0])
-    o = {k: np.array(v) for k, v in o.items()}
-    # 1000 steps through a conical intersection amplify rounding; a few
-    # walkers may take a different branch
-    compare_walkers(g, o, rtol=1e-8, max_flip_frac=0.05, label="pyrazine 1e7 sampled")
-    # ensemble invariants at early times (trace 1, Hermiticity) within 5 SE
-    for o_ in range(0, 11):
+    ids = sample_ids(r.n_traj, 250)
+    g = sampled_state(ens, ids)
+    o = oracle_walkers(wl, ids)
+    compare_walkers(g, o, rtol=1e-10, max_flip_frac=0.01, label="pyrazine 1e7 sampled")
+    # trace 1 and Hermiticity hold in expectation at every bin: within 5 SE
+    for o_ in range(out.shape[0]):
         tr = out[o_, 0, 0, 0, 0] + out[o_, 0, 1, 1, 0]
         se = math.hypot(out[o_, 0, 0, 0, 2], out[o_, 0, 1, 1, 2])
         assert abs(tr - 1) <= 5 * se + 1e-12, (o_, tr, se)

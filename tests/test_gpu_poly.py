@@ -7,7 +7,8 @@ import pytest
 
 import workloads as W
 from test_gpu_batch import _assert_same, _batched, _solo
-from test_gpu_parity import compare_walkers, ensemble_close, gpu_run, oracle_run
+from parity import (check_ensemble32, check_ensemble64, compare_walkers, gpu_run, oracle_run, oracle_walkers,
+                    sample_ids, sampled_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -44,21 +45,17 @@ def test_poly_fp64_parity(P, name):
     out_g, st_g, s0_g, _ = gpu_run(P, wl)
     out_o, st_o, s0_o, _ = oracle_run(wl)
     compare_walkers(s0_g, s0_o, rtol=1e-11, label=name + " sample")
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label=name)
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.005, label=name)
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label=name)
 
 
 @pytest.mark.parametrize("name", ["qvc_pyrazine", "n4_m3_d4"])
 def test_poly_fp32_ensemble(P, name):
     wl = CASES[name]()
     wl.run.n_traj = 40_000
-    out_g, _, _, _ = gpu_run(P, wl, prec="fp32")
-    out_o, _, _, _ = oracle_run(wl)
-    d = np.abs(out_g[..., :2] - out_o[..., :2])
-    se = np.maximum(out_o[..., 2:], 1e-300)
-    print(name, "fp32 max abs err", d.max(), "max err/SE", (d / se).max(), flush=True)
-    assert np.all((d <= 1e-3) | (d <= 3 * se))
+    out_g, st_g, _, _ = gpu_run(P, wl, prec="fp32")
+    out_o, st_o, _, _ = oracle_run(wl)
+    check_ensemble32(out_g, out_o, wl.run.n_traj, label=name, g=st_g, o=st_o)
 
 
 def test_poly_linear_rule(P):
@@ -66,9 +63,8 @@ def test_poly_linear_rule(P):
     out_g, st_g, _, _ = gpu_run(P, wl, scheme=1)
     out_o, st_o, _, fl_o = oracle_run(wl, scheme=1)
     assert np.array_equal(st_g["flags"] & 8, np.asarray(fl_o) & 8)
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label="poly linear")
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.005, label="poly linear")
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label="poly linear")
 
 
 def test_poly_slicing_bitwise(P):
@@ -103,9 +99,8 @@ def test_poly_large_mode_buckets(P, n_states, n_modes):
                        cadence=10, rank_full=False)
     out_g, st_g, _, _ = gpu_run(P, wl)
     out_o, st_o, _, _ = oracle_run(wl)
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.01, label=f"poly N{n_states} M{n_modes}")
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.01, label=f"poly N{n_states} M{n_modes}")
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label=f"poly N{n_states} M{n_modes}")
 
 
 def test_poly_bench_configuration_full_size(P):
@@ -114,8 +109,6 @@ def test_poly_bench_configuration_full_size(P):
     ensemble recomputed one by one by the oracle, and the binary32 run's
     populations within 2e-3 of the binary64 run's while resolved."""
     import torch
-    import oracle.core as oc
-    from test_gpu_parity import _oracle_state
     wl = W.pyrazine_qvc(n_traj=10_000_000, n_steps=200, cadence=10)
     r = wl.run
     model = P.Model(wl.model)
@@ -127,29 +120,14 @@ def test_poly_bench_configuration_full_size(P):
         P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part)
         outs[prec] = P.qcl_reduce_observables(model, part, r.n_traj).cpu().numpy()
         if prec == "fp64":
-            t = ens.tensors()
-            ids = np.array([0, 255, 256, 1 << 20, 5_555_555, r.n_traj - 1])
-            g = {"q": t["q"][:, ids].cpu().numpy().T, "p": t["p"][:, ids].cpu().numpy().T,
-                 "U": t["u"][:, ids].cpu().numpy().T.reshape(-1, 2, 2), "w": t["w"][ids].cpu().numpy(),
-                 "phase": t["phase"][ids].cpu().numpy(), "a": t["a"][ids].cpu().numpy().astype(np.int32),
-                 "b": t["b"][ids].cpu().numpy().astype(np.int32)}
+            ids = sample_ids(r.n_traj, 120, seed=3, extra=[1 << 20, 5_555_555])
+            g = sampled_state(ens, ids)
         del ens, part
         torch.cuda.empty_cache()
-    m = oc.Model(wl.model)
-    o = {k: [] for k in g}
-    for i in ids:
-        st, _ = oc.sample(m, wl.init, r.seed, 1, traj_offset=int(i))
-        oc.propagate(m, st, r.dt, r.n_steps, r.cadence, r.seed, r.n_out)
-        for k, v in _oracle_state(st).items():
-            o[k].append(v[0])
-    o = {k: np.array(v) for k, v in o.items()}
-    compare_walkers(g, o, rtol=1e-8, max_flip_frac=0.2, label="pyrazine_qvc 1e7 sampled")
-    o64, o32 = outs["fp64"], outs["fp32"]
-    se = np.max(np.stack([o64[:, 0, i, i, 2] for i in range(2)]), axis=0)
-    res = int(np.argmax(~(se < 0.01))) if np.any(~(se < 0.01)) else len(se)
-    d = max(float(np.abs(o32[:res, 0, i, i, 0] - o64[:res, 0, i, i, 0]).max()) for i in range(2))
-    print("fp32 vs fp64 population diff", d, "over", res, "resolved bins", flush=True)
-    assert res >= 3 and d <= 2e-3
+    o = oracle_walkers(wl, ids)
+    compare_walkers(g, o, rtol=1e-10, max_flip_frac=0.01, label="pyrazine_qvc 1e7 sampled")
+    # binary32 against binary64 on every bin
+    check_ensemble32(outs["fp32"], outs["fp64"], r.n_traj, label="pyrazine_qvc fp32 vs fp64")
 
 
 @pytest.mark.parametrize("T", [0, 1, 255, 257])
@@ -160,8 +138,8 @@ def test_poly_empty_and_ragged(P, T):
         assert out_g is None and st_g["w"].size == 0
         return
     out_o, st_o, _, _ = oracle_run(wl)
-    compare_walkers(st_g, st_o, rtol=1e-9, label=f"poly T={T}")
-    assert ensemble_close(out_g, out_o, T)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, label=f"poly T={T}")
+    check_ensemble64(out_g, out_o, T, flip, st_g, st_o, label=f"poly T={T}")
 
 
 def test_poly_largest_bucket_n4_m128(P):
@@ -171,9 +149,8 @@ def test_poly_largest_bucket_n4_m128(P):
                        rank_full=False)
     out_g, st_g, _, _ = gpu_run(P, wl)
     out_o, st_o, _, _ = oracle_run(wl)
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.02, label="poly N4 M128")
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.02, label="poly N4 M128")
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label="poly N4 M128")
     out32, st32, _, _ = gpu_run(P, wl, prec="fp32")
     assert np.all(np.isfinite(st32["w"])) and np.all(np.isfinite(out32))
 
@@ -193,6 +170,5 @@ def test_poly_two_state_closed_form_slicing_and_linear_rule(P):
     out_g, st_g, _, _ = gpu_run(P, wl, scheme=1)
     out_o, st_o, _, fl_o = oracle_run(wl, scheme=1)
     assert np.array_equal(st_g["flags"] & 8, np.asarray(fl_o) & 8)
-    nflip = compare_walkers(st_g, st_o, rtol=1e-9, max_flip_frac=0.005, label="poly n2 m8 linear")
-    if nflip == 0:
-        assert ensemble_close(out_g, out_o, wl.run.n_traj)
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, max_flip_frac=0.005, label="poly n2 m8 linear")
+    check_ensemble64(out_g, out_o, wl.run.n_traj, flip, st_g, st_o, label="poly n2 m8 linear")

@@ -57,8 +57,12 @@ def test_study_parity_fp64(S):
             print(f"n={row['n_traj']} no fit: {row.get('fit_error')}", flush=True)
             assert row["rate"] is None
             continue
-        print(f"n={row['n_traj']} rate={row['rate']:.6f}+-{row['rate_se']:.6f} oracle {k:.6f}", flush=True)
-        assert math.isclose(row["rate"], k, rel_tol=1e-8) and math.isclose(row["rate_se"], ks, rel_tol=1e-8)
+        chi2 = D.fit_quality(t, m, se, t0, t1, k, a)
+        print(f"n={row['n_traj']} rate={row['rate']:.6f}+-{row['rate_se']:.6f} chi2/dof={row['chi2_per_dof']:.3g} "
+              f"oracle {k:.6f} chi2/dof {chi2:.3g}", flush=True)
+        assert math.isclose(row["rate"], k, rel_tol=1e-8) and math.isclose(row["rate_se_stat"], ks, rel_tol=1e-8)
+        assert math.isclose(row["chi2_per_dof"], chi2, rel_tol=1e-6, abs_tol=1e-9)
+        assert math.isclose(row["rate_se"], D.scaled_rate_error(ks, chi2), rel_tol=1e-6)
         assert math.isclose(row["amplitude"], a, rel_tol=1e-8) and row["fit_bins"] == used
         fitted += 1
     assert fitted >= 1

@@ -78,6 +78,38 @@ def test_rate_error_covers_scatter():
     assert abs(rates.std() / np.mean(errs) - 1.0) < 0.08
 
 
+def test_fit_quality():
+    """chi^2/dof is 0 on an exact exponential, averages 1 over noisy copies
+    whose errors are the stated ones, and grows when one exponential does
+    not fit (a plateau); the scaled error then covers the scatter."""
+    t = np.linspace(0.0, 10.0, 11)
+    p0 = 0.9 * np.exp(-0.2 * t)
+    k, ks, a, _ = D.decay_rate(t, p0, 0.01 * p0, 0.0, 10.0)
+    assert D.fit_quality(t, p0, 0.01 * p0, 0.0, 10.0, k, a) < 1e-20
+    assert D.scaled_rate_error(ks, 0.3) == ks
+    rng = np.random.default_rng(11)
+    se = 0.002 * np.ones_like(t)
+    chis = []
+    for _ in range(2000):
+        p = p0 + rng.normal(0, 1, t.size) * se
+        k, ks, a, _ = D.decay_rate(t, p, se, 0.0, 10.0)
+        chis.append(D.fit_quality(t, p, se, 0.0, 10.0, k, a))
+    # mean of chi^2/9 is 1 (up to the log's second-order bias), SE 0.47/sqrt(2000)
+    assert abs(np.mean(chis) - 1.0) < 0.05
+    # a decay onto a plateau fitted by one exponential
+    pp = 0.7 * np.exp(-0.5 * t) + 0.2
+    rates, errs, scaled = [], [], []
+    for _ in range(2000):
+        p = pp + rng.normal(0, 1, t.size) * se
+        k, ks, a, _ = D.decay_rate(t, p, se, 0.0, 10.0)
+        c = D.fit_quality(t, p, se, 0.0, 10.0, k, a)
+        assert c > 10.0
+        rates.append(k)
+        scaled.append(D.scaled_rate_error(ks, c))
+        errs.append(ks)
+    assert np.mean(scaled) > 3.0 * np.mean(errs)
+
+
 def test_horizon_and_crossing():
     t = [0.0, 1.0, 2.0, 3.0]
     assert D.horizon(t, [0.01, -0.015, 0.03, 0.0], 0.02) == 1.0
@@ -135,7 +167,10 @@ def test_study_analysis_matches_oracle():
     assert res["window"] == [t0, t1]
     for row, (n, t, p, se) in zip(res["runs"], raw):
         k, ks, a, used = D.decay_rate(t, p, se, t0, t1)
-        assert math.isclose(row["rate"], k, rel_tol=1e-12) and math.isclose(row["rate_se"], ks, rel_tol=1e-12)
+        chi2 = D.fit_quality(t, p, se, t0, t1, k, a)
+        assert math.isclose(row["rate"], k, rel_tol=1e-12) and math.isclose(row["rate_se_stat"], ks, rel_tol=1e-12)
+        assert math.isclose(row["chi2_per_dof"], chi2, rel_tol=1e-9, abs_tol=1e-12)
+        assert math.isclose(row["rate_se"], D.scaled_rate_error(ks, chi2), rel_tol=1e-9)
         assert math.isclose(row["amplitude"], a, rel_tol=1e-12) and row["fit_bins"] == used
         assert row["resolved_until"] == D.horizon(t, se, 0.02)
         if n != 10**6:
