@@ -94,6 +94,7 @@ def time_path(P, torch, model, wl, prec, n_traj, steps, warmup):
     part = P.Partials(model, n_traj, r.n_out)
     n = model.n_states
     out = torch.empty((r.n_out, 2, n, n, 4), dtype=torch.float64, device="cuda")
+    excl = torch.empty(r.n_out, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
 
@@ -104,7 +105,7 @@ def time_path(P, torch, model, wl, prec, n_traj, steps, warmup):
         P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part, 0, stream)
         if i is not None:
             ev[i][1].record(stream)
-        P.qcl_reduce_observables(model, part, n_traj, out, stream)
+        P.qcl_reduce_observables_async(model, part, n_traj, out, excl, stream)
 
     for _ in range(warmup):
         one()

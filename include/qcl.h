@@ -32,6 +32,9 @@
  *     valid once the stream has reached the point of the call.
  *   - Nothing in qcl_sample_initial, qcl_propagate or
  *     qcl_reduce_observables allocates memory.
+ *   - Every device pointer (ensemble arrays, partials, out, workspaces) must
+ *     be 256-byte aligned (INVALID_ARG otherwise); qcl_ensemble_bind and
+ *     allocations of the HIP and torch allocators are.
  *   - A model's constants live on the device that was current when it was
  *     created; qcl_sample_initial, qcl_propagate and qcl_propagate_batch
  *     must be called with that device current (INVALID_ARG otherwise).
@@ -58,7 +61,11 @@ typedef enum {
     QCL_ERR_INVALID_ARG = 1,   /* bad size, pointer, value or layout */
     QCL_ERR_UNSUPPORTED = 2,   /* valid request this build cannot run */
     QCL_ERR_OUT_OF_MEMORY = 3, /* qcl_create_model could not allocate */
-    QCL_ERR_DEVICE = 4         /* a HIP call or kernel launch failed */
+    QCL_ERR_DEVICE = 4,        /* a HIP call or kernel launch failed */
+    QCL_ERR_NONFINITE = 5      /* qcl_reduce_observables: walkers with a
+                                  non-finite weight or phase were excluded
+                                  from the sums (the results are written;
+                                  qcl_last_error() states the count) */
 } qcl_status;
 
 typedef enum {
@@ -260,8 +267,11 @@ qcl_status qcl_ensemble_bind(qcl_model model, void *base, int64_t n_traj, int32_
                              int64_t traj_offset, qcl_ensemble *ens);
 
 /* Bytes of the partial-sum buffer for n_traj walkers and n_out bins:
- * n_tiles = ceil(n_traj/QCL_TILE) rows of n_out x 2 x N x N x 4 doubles,
- * plus scratch rows used by qcl_reduce_observables. */
+ * n_tiles = ceil(n_traj/QCL_TILE) rows of n_out x (2 x N x N x 4 + 1)
+ * doubles (per bin the sums of Re, Im, Re^2, Im^2 of every adiabatic and
+ * diabatic element, then the number of walkers excluded from the bin),
+ * plus scratch rows and n_out excluded counts used by
+ * qcl_reduce_observables. */
 qcl_status qcl_partials_bytes(qcl_model model, int64_t n_traj, int32_t n_out, size_t *bytes);
 
 /* Samples the initial ensemble (Sec. II.A, partial Wigner transform) and
@@ -340,10 +350,24 @@ qcl_status qcl_propagate_batch(const qcl_batch_item *items, int32_t n_items, voi
  *   [o][0][a][b] adiabatic rho_ab, [o][1][i][j] diabatic rho_ij, each as
  *   (mean Re, mean Im, standard error Re, standard error Im) over n_traj
  *   walkers (normalised by n_traj; SE = sqrt((S2 - S1^2/T)/(T(T-1)))).
- * The partials are read, not modified (scratch rows are).  n_traj >= 1.
- * Errors: INVALID_ARG, DEVICE. */
+ * A walker whose weight or phase is not finite (the sign problem, Sec. I,
+ * can drive |w| past the binary64 range) contributes zeros from the first
+ * bin it is non-finite at, and is counted per bin.  This call waits for the
+ * reduction to finish on the stream and returns QCL_ERR_NONFINITE when any
+ * bin excluded a walker, with the largest count and its bin in
+ * qcl_last_error(); out is written either way.  n_traj must be the walker
+ * count the partials were sized for (n_traj >= 1); the partials are read,
+ * not modified (their scratch rows and counts are).
+ * Errors: INVALID_ARG, DEVICE, NONFINITE. */
 qcl_status qcl_reduce_observables(qcl_model model, double *partials, int64_t n_traj,
                                   int32_t n_out, double *out, void *stream);
+
+/* The same reduction without waiting: enqueues it on the stream and
+ * returns.  When excluded is not NULL it receives the per-bin counts of
+ * excluded walkers (device int64 [n_out], 256-byte aligned).
+ * Errors: INVALID_ARG, DEVICE (never NONFINITE). */
+qcl_status qcl_reduce_observables_async(qcl_model model, double *partials, int64_t n_traj,
+                                        int32_t n_out, double *out, int64_t *excluded, void *stream);
 
 /* Fixed-budget resampling between propagation calls (the paper's CPU code
  * spawned walkers and let their number grow, Sec. II.B; this keeps T).

@@ -1,22 +1,29 @@
-// Fixed-order reduction of per-walker values into one tile partial.
+// Fixed-order reduction of per-walker bin values into one tile partial.
 //
-// A workgroup of kBlock walkers (4 wavefronts) sums V = 32 doubles per
-// walker.  Inside a wavefront a reduce-scatter butterfly pairs lanes l and
-// l^32, then l^16, l^8, l^4, l^2, l^1; at each stage a lane keeps half of
-// the values it still carries, summed with its partner's copy, so after the
-// last stage every lane holds the wavefront total of one value.  Data moves
-// with gfx950's register-only crossbar instructions: v_permlane32_swap and
-// v_permlane16_swap for the two widest stages (one swap per dword replaces a
-// shuffle-and-select), DPP row/quad permutations for the narrow ones.  No
-// LDS traffic is needed inside the wavefront.
+// A workgroup of kBlock walkers (4 wavefronts of 64) sums V doubles per
+// walker.  The values go through LDS, 8 at a time (one "pass"): every lane
+// writes its 8 values as one row of its wavefront's staging area (64 rows,
+// padded to 9 doubles so that the rows fall on distinct banks), then lane l
+// reads column (l & 7) of the 8 consecutive rows 8 (l >> 3) .. 8 (l >> 3) + 7
+// and adds them as a pairwise tree.  The 8 partial sums of a column sit in
+// lanes l, l ^ 8, l ^ 16, ..., l ^ 56 and are combined by three butterfly
+// stages: a DPP row rotation (l ^ 8), v_permlane16_swap (l ^ 16) and
+// v_permlane32_swap (l ^ 32), each applied to a register and a copy of
+// itself so that both lanes of a pair form the same sum.  Each wavefront
+// total is therefore a perfect binary tree over its 64 walkers in index
+// order; across the 4 wavefronts the totals are added as (w0 + w1) + (w2 + w3)
+// from a small LDS area, and the tiles are combined by the same tree in the
+// final reduction: the whole sum is a perfect pairwise tree over the global
+// walker index, bitwise independent of launch shape, batching and slicing.
 //
-// Which value ends in which lane is a fixed function of the lane index; it
-// is obtained by running the same data movement on the value indices
-// (scatter_slots), so the code does not depend on which half of a register
-// pair a swap instruction moves.  Across the 4 wavefronts the sums continue
-// in LDS as (w0 + w1) + (w2 + w3).  Every sum is therefore a fixed binary
-// tree over the walker index: bitwise repeatable and independent of how the
-// steps are split over launches.
+// Compared with reducing in registers, the transposition moves the data
+// through the LDS pipe and leaves 7 + 3 additions and 10 crossbar moves per
+// pass on the vector ALU; values that are zero in most lanes (the adiabatic
+// slots a walker is not in) are written as zeros and overwritten by the one
+// lane-dependent slot under an exec mask, with no per-value select.
+//
+// The count of walkers excluded from a bin (non-finite weight or phase) is
+// gathered with a wavefront ballot and stored after the bin's values.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,6 +31,16 @@
 #include <cstdint>
 
 namespace qcl {
+
+constexpr int kPassValues = 8;    // values per LDS pass
+constexpr int kStageStride = 9;   // doubles per staging row (8 values + 1 pad)
+constexpr int kFlushValues = 32;  // values per cross-wavefront flush (4 passes)
+
+struct BinLds {
+    double stage[4][64 * kStageStride];  // one staging area per wavefront
+    double wsum[2][4][kFlushValues];     // wavefront totals, double-buffered by flush
+    uint32_t excluded[2][4];
+};
 
 namespace rdetail {
 
@@ -34,204 +51,106 @@ __device__ __forceinline__ double mkd(uint32_t lo, uint32_t hi)
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// v_permlane32_swap / v_permlane16_swap on a pair of doubles
-__device__ __forceinline__ void swap32(double &a, double &b)
+// x + x(lane ^ 8): row rotation by 8 inside each row of 16 lanes
+__device__ __forceinline__ double add_xor8(double x)
 {
-    auto l = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
-    auto h = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
-    a = mkd(l[0], h[0]);
-    b = mkd(l[1], h[1]);
-}
-__device__ __forceinline__ void swap16(double &a, double &b)
-{
-    auto l = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
-    auto h = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
-    a = mkd(l[0], h[0]);
-    b = mkd(l[1], h[1]);
-}
-__device__ __forceinline__ void swap32i(int &a, int &b)
-{
-    auto r = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false);
-    a = (int)r[0];
-    b = (int)r[1];
-}
-__device__ __forceinline__ void swap16i(int &a, int &b)
-{
-    auto r = __builtin_amdgcn_permlane16_swap((uint32_t)a, (uint32_t)b, false, false);
-    a = (int)r[0];
-    b = (int)r[1];
+    const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo32(x), 0x128, 0xF, 0xF, false);
+    const uint32_t h = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi32(x), 0x128, 0xF, 0xF, false);
+    return x + mkd(l, h);
 }
 
-// value of lane l ^ D for D in {8, 4, 2, 1} (DPP; every lane reads a lane
-// of its own row of 16)
-template <int D>
-__device__ __forceinline__ uint32_t xlane32(uint32_t x)
+// x(lane) + x(lane ^ 16): v_permlane16_swap of x with itself leaves rows
+// (r0, r0, r2, r2) in the first operand and (r1, r1, r3, r3) in the second,
+// so every lane adds the even row's value to the odd row's in that order
+__device__ __forceinline__ double add_xor16(double x)
 {
-    if constexpr (D == 8) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);  // row_ror:8
-    } else if constexpr (D == 4) {
-        // row_half_mirror (l -> l ^ 7 within 8) then quad mirror (l -> l ^ 3)
-        const int m = __builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false);
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, m, 0x1B, 0xF, 0xF, false);  // quad_perm [3,2,1,0]
-    } else if constexpr (D == 2) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
-    } else {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
-    }
-}
-template <int D>
-__device__ __forceinline__ double xlane(double x)
-{
-    return mkd(xlane32<D>(lo32(x)), xlane32<D>(hi32(x)));
+    const auto l = __builtin_amdgcn_permlane16_swap(lo32(x), lo32(x), false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi32(x), hi32(x), false, false);
+    return mkd(l[0], h[0]) + mkd(l[1], h[1]);
 }
 
-// one narrow stage: lanes with bit D clear keep the lower half
-template <int D, int H>
-__device__ __forceinline__ void narrow_stage(double *v, bool upper)
+// x(lane) + x(lane ^ 32), the same with the two halves of the wavefront
+__device__ __forceinline__ double add_xor32(double x)
 {
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-        const double lo = v[i] + xlane<D>(v[i]);
-        const double hi = v[i + H] + xlane<D>(v[i + H]);
-        v[i] = upper ? hi : lo;
-    }
+    const auto l = __builtin_amdgcn_permlane32_swap(lo32(x), lo32(x), false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi32(x), hi32(x), false, false);
+    return mkd(l[0], h[0]) + mkd(l[1], h[1]);
 }
 
 }  // namespace rdetail
 
-// Value index each lane holds after wave_reduce32 (same movement on ints).
-__device__ __forceinline__ int scatter_slot32(int lane)
-{
-    using namespace rdetail;
-    int id[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        int a = i, b = i + 16;
-        swap32i(a, b);
-        id[i] = a;
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        int a = id[i], b = id[i + 8];
-        swap16i(a, b);
-        id[i] = a;
-    }
-    id[0] = (lane & 8) ? id[4] : id[0];
-    id[1] = (lane & 8) ? id[5] : id[1];
-    id[2] = (lane & 8) ? id[6] : id[2];
-    id[3] = (lane & 8) ? id[7] : id[3];
-    id[0] = (lane & 4) ? id[2] : id[0];
-    id[1] = (lane & 4) ? id[3] : id[1];
-    id[0] = (lane & 2) ? id[1] : id[0];
-    return id[0];
-}
+// Reduction state of one bin (or one block of up to kFlushValues values of
+// a bin) in one workgroup; every thread of the workgroup makes the same
+// calls.  Usage per pass: put() the 8 values (or zero_row() and a masked
+// put()), then pass(); after at most 4 passes flush().
+struct BinReducer {
+    BinLds &L;
+    int &parity;  // the workgroup's flush counter (kept by the caller across bins)
+    int lane, wave;
+    double *row;
+    int npass = 0;
 
-// Reduce-scatter of 32 doubles over the 64 lanes; lane l ends with the
-// wavefront total of value scatter_slot32(l) in v[0] (lanes l and l^1 hold
-// the same value).
-__device__ __forceinline__ void wave_reduce32(double (&v)[32], int lane)
-{
-    using namespace rdetail;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        double a = v[i], b = v[i + 16];
-        swap32(a, b);
-        v[i] = a + b;
+    __device__ __forceinline__ BinReducer(BinLds &lds, int &flush_parity)
+        : L(lds), parity(flush_parity), lane(threadIdx.x & 63), wave(threadIdx.x >> 6)
+    {
+        row = &L.stage[wave][lane * kStageStride];
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        double a = v[i], b = v[i + 8];
-        swap16(a, b);
-        v[i] = a + b;
-    }
-    narrow_stage<8, 4>(v, (lane & 8) != 0);
-    narrow_stage<4, 2>(v, (lane & 4) != 0);
-    narrow_stage<2, 1>(v, (lane & 2) != 0);
-    v[0] = v[0] + xlane<1>(v[0]);
-}
 
-// Sums v over the workgroup and writes the first n_valid of the 32 totals
-// to dst (threads 0..n_valid-1).  lds holds 4*32 doubles;
-// slot = scatter_slot32(lane).  All threads call it.
-__device__ __forceinline__ void block_reduce_store32(double (&v)[32], int slot, double *__restrict__ dst,
-                                                     double *lds, int n_valid = 32)
-{
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    wave_reduce32(v, lane);
-    if ((lane & 1) == 0)
-        lds[wave * 32 + slot] = v[0];
-    __syncthreads();
-    if (threadIdx.x < n_valid) {
+    __device__ __forceinline__ void zero_row()
+    {
+#pragma unroll
+        for (int j = 0; j < kPassValues; ++j)
+            row[j] = 0.0;
+    }
+
+    __device__ __forceinline__ void put(int col, double x) { row[col] = x; }
+
+    // the wavefront totals of the 8 staged values
+    __device__ __forceinline__ void pass()
+    {
+        using namespace rdetail;
+        __builtin_amdgcn_wave_barrier();
+        const double *c = &L.stage[wave][(lane >> 3) * 8 * kStageStride + (lane & 7)];
+        const double s01 = c[0 * kStageStride] + c[1 * kStageStride];
+        const double s23 = c[2 * kStageStride] + c[3 * kStageStride];
+        const double s45 = c[4 * kStageStride] + c[5 * kStageStride];
+        const double s67 = c[6 * kStageStride] + c[7 * kStageStride];
+        double s = (s01 + s23) + (s45 + s67);
+        s = add_xor8(s);
+        s = add_xor16(s);
+        s = add_xor32(s);
+        if (lane < kPassValues)
+            L.wsum[parity & 1][wave][npass * kPassValues + lane] = s;
+        __builtin_amdgcn_wave_barrier();
+        ++npass;
+    }
+
+    // Walkers excluded from this bin (counted per wavefront).
+    __device__ __forceinline__ void count_excluded(bool excluded)
+    {
+        const unsigned long long m = __ballot(excluded);
+        if (lane == 0)
+            L.excluded[parity & 1][wave] = (uint32_t)__popcll(m);
+    }
+
+    // Adds the 4 wavefront totals of the values staged so far and writes
+    // the first n of them to dst (threads 0..n-1); thread 32 writes the
+    // excluded count to *count_dst when it is given.  The wavefront totals
+    // are double-buffered by the flush counter, so one barrier per flush
+    // suffices: a buffer is written again only after the next flush's
+    // barrier, which every reader of this flush has passed.
+    __device__ __forceinline__ void flush(double *__restrict__ dst, int n, double *__restrict__ count_dst)
+    {
+        __syncthreads();
         const int t = threadIdx.x;
-        dst[t] = (lds[t] + lds[32 + t]) + (lds[64 + t] + lds[96 + t]);
+        const int k = parity & 1;
+        if (t < n)
+            dst[t] = (L.wsum[k][0][t] + L.wsum[k][1][t]) + (L.wsum[k][2][t] + L.wsum[k][3][t]);
+        if (count_dst && t == kFlushValues)
+            *count_dst = (double)((L.excluded[k][0] + L.excluded[k][1]) + (L.excluded[k][2] + L.excluded[k][3]));
+        npass = 0;
+        parity ^= 1;
     }
-    __syncthreads();
-}
-
-// Value index each lane holds after wave_reduce16.
-__device__ __forceinline__ int scatter_slot16(int lane)
-{
-    using namespace rdetail;
-    int id[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        int a = i, b = i + 8;
-        swap32i(a, b);
-        id[i] = a;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int a = id[i], b = id[i + 4];
-        swap16i(a, b);
-        id[i] = a;
-    }
-    id[0] = (lane & 8) ? id[2] : id[0];
-    id[1] = (lane & 8) ? id[3] : id[1];
-    id[0] = (lane & 4) ? id[1] : id[0];
-    return id[0];
-}
-
-// Reduce-scatter of 16 doubles over the 64 lanes (the same stages as
-// wave_reduce32 with half the values live): lane l ends with the wavefront
-// total of value scatter_slot16(l) in v[0] (lanes l, l^1, l^2, l^3 agree).
-__device__ __forceinline__ void wave_reduce16(double (&v)[16], int lane)
-{
-    using namespace rdetail;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        double a = v[i], b = v[i + 8];
-        swap32(a, b);
-        v[i] = a + b;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        double a = v[i], b = v[i + 4];
-        swap16(a, b);
-        v[i] = a + b;
-    }
-    narrow_stage<8, 2>(v, (lane & 8) != 0);
-    narrow_stage<4, 1>(v, (lane & 4) != 0);
-    v[0] = v[0] + xlane<2>(v[0]);
-    v[0] = v[0] + xlane<1>(v[0]);
-}
-
-// block_reduce_store32 for 16 values; lds holds 4*16 doubles,
-// slot = scatter_slot16(lane).
-__device__ __forceinline__ void block_reduce_store16(double (&v)[16], int slot, double *__restrict__ dst,
-                                                     double *lds, int n_valid = 16)
-{
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    wave_reduce16(v, lane);
-    if ((lane & 3) == 0)
-        lds[wave * 16 + slot] = v[0];
-    __syncthreads();
-    if (threadIdx.x < n_valid) {
-        const int t = threadIdx.x;
-        dst[t] = (lds[t] + lds[16 + t]) + (lds[32 + t] + lds[48 + t]);
-    }
-    __syncthreads();
-}
+};
 
 }  // namespace qcl

@@ -180,12 +180,16 @@ __device__ __forceinline__ void geo_at(const N2Const<M, R> &C, const N2Extra<M, 
         flag |= kFlagDegenerate;
 }
 
-// Per-walker contributions of one output bin, [slot][stat] with slots
-// 0..3 adiabatic (a*2+b) and 4..7 diabatic (i*2+j), stats Re, Im, Re^2, Im^2.
+// One output bin of the workgroup's tile, reduced into dst (tile_values(2)
+// doubles: [slot][stat] with slots 0..3 adiabatic (a*2+b) and 4..7 diabatic
+// (i*2+j), stats Re, Im, Re^2, Im^2, then the excluded count).  The
+// adiabatic terms sit in the walker's own slot only: the staging rows are
+// cleared and that slot written under an exec mask.  Diabatic terms use
 // U_ia U_jb = (a == b ? 1 : s0 s1) C_ia C_jb with the canonical frame C.
+// Every thread of the workgroup calls it.
 template <typename R>
-__device__ __forceinline__ void bin_values(double (&v)[32], bool live, int a, int b, double w, double phase,
-                                           R c0, R c1, R sig)
+__device__ __forceinline__ void bin_n2(BinLds &L, int &parity, bool live, int a, int b, double w, double phase,
+                                       R c0, R c1, R sig, double *__restrict__ dst)
 {
     double sn, cs;
     if constexpr (sizeof(R) == 4) {
@@ -196,36 +200,46 @@ __device__ __forceinline__ void bin_values(double (&v)[32], bool live, int a, in
     } else {
         sincos_phase(phase, sn, cs);
     }
-    double re = w * cs, im = -w * sn;
     const bool ok = live && isfinite(w) && isfinite(phase);
-    re = ok ? re : 0.0;
-    im = ok ? im : 0.0;
+    const double re = ok ? w * cs : 0.0;
+    const double im = ok ? -w * sn : 0.0;
+    const double re2 = re * re, im2 = im * im;
+    BinReducer B(L, parity);
     const int s = a * 2 + b;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const bool on = (t == s);
-        v[4 * t + 0] = on ? re : 0.0;
-        v[4 * t + 1] = on ? im : 0.0;
-        v[4 * t + 2] = on ? re * re : 0.0;
-        v[4 * t + 3] = on ? im * im : 0.0;
+    for (int p = 0; p < 2; ++p) {  // adiabatic slots 2p and 2p + 1
+        B.zero_row();
+        if ((s >> 1) == p) {
+            const int c = 4 * (s & 1);
+            B.put(c + 0, re);
+            B.put(c + 1, im);
+            B.put(c + 2, re2);
+            B.put(c + 3, im2);
+        }
+        B.pass();
     }
-    const double d0 = (double)c0, d1 = (double)c1;
+    // an excluded walker contributes exact zeros (its frame may be NaN)
+    const double d0 = ok ? (double)c0 : 0.0, d1 = ok ? (double)c1 : 0.0;
     const double ua0 = a ? d0 : -d1;  // C_0a
     const double ua1 = a ? d1 : d0;   // C_1a
     const double ub0 = b ? d0 : -d1;  // C_0b
     const double ub1 = b ? d1 : d0;   // C_1b
     const double sg = (a == b) ? 1.0 : (double)sig;
-    // an excluded walker contributes exact zeros (its frame may be NaN)
-    const double c[4] = {ok ? sg * (ua0 * ub0) : 0.0, ok ? sg * (ua0 * ub1) : 0.0, ok ? sg * (ua1 * ub0) : 0.0,
-                         ok ? sg * (ua1 * ub1) : 0.0};
+    const double cf[4] = {sg * (ua0 * ub0), sg * (ua0 * ub1), sg * (ua1 * ub0), sg * (ua1 * ub1)};
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const double r = re * c[t], m = im * c[t];
-        v[16 + 4 * t + 0] = r;
-        v[16 + 4 * t + 1] = m;
-        v[16 + 4 * t + 2] = r * r;
-        v[16 + 4 * t + 3] = m * m;
+    for (int p = 0; p < 2; ++p) {  // diabatic cells 2p and 2p + 1
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double r = re * cf[2 * p + h], m = im * cf[2 * p + h];
+            B.put(4 * h + 0, r);
+            B.put(4 * h + 1, m);
+            B.put(4 * h + 2, r * r);
+            B.put(4 * h + 3, m * m);
+        }
+        B.pass();
     }
+    B.count_excluded(live && !ok);
+    B.flush(dst, 32, dst + 32);
 }
 
 // ---------------------------------------------------------------- sampling
@@ -235,8 +249,8 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
                                                            SampleArgs S, EnsDev<R> E, double *__restrict__ partials,
                                                            int32_t n_out)
 {
-    __shared__ double lds[4 * 32];
-    const int slot = scatter_slot32(threadIdx.x & 63);
+    __shared__ BinLds lds;
+    int parity = 0;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool live = i < E.n_traj;
     const uint64_t gid = (uint64_t)(E.traj_offset + (live ? i : 0));
@@ -307,9 +321,8 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
         w = (prod > 0.0 ? 1.0 : -1.0) * Z;
     }
 
-    double v[32];
-    bin_values<double>(v, live, a, b, w, 0.0, c0, c1, s0 * s1);
-    block_reduce_store32(v, slot, partials + ((int64_t)blockIdx.x * n_out + 0) * 32, lds);
+    bin_n2<double>(lds, parity, live, a, b, w, 0.0, c0, c1, s0 * s1,
+                   partials + ((int64_t)blockIdx.x * n_out + 0) * tile_values(2));
 
     if (live) {
         const int64_t ld = E.ld;
@@ -377,7 +390,8 @@ __device__ __forceinline__ void poly_mean_force_kick(const N2Const<M, R> &C, con
 template <int M, typename R, int SCHEME, bool POLY>
 __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const N2Extra<M, R, POLY> &Q,
                                                   const PropArgs &P, const EnsDev<R> &E,
-                                                  double *__restrict__ partials, int64_t tile, int slot, double *lds)
+                                                  double *__restrict__ partials, int64_t tile, BinLds &lds,
+                                                  int &parity)
 {
     const int64_t i = tile * kBlock + threadIdx.x;
     const bool live = i < E.n_traj;
@@ -507,9 +521,8 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const 
         if (step == next_bin && next_bin / P.cadence < P.n_out) {
             R c0, c1;
             canon2<R>(g, c0, c1);
-            double v[32];
-            bin_values<R>(v, live, a, b, w, phase, c0, c1, sig);
-            block_reduce_store32(v, slot, partials + (tile * P.n_out + next_bin / P.cadence) * 32, lds);
+            bin_n2<R>(lds, parity, live, a, b, w, phase, c0, c1, sig,
+                      partials + (tile * P.n_out + next_bin / P.cadence) * tile_values(2));
         }
     }
     if (!(isfinite(w) && isfinite(phase)))
@@ -541,9 +554,9 @@ template <int M, typename R, int SCHEME, bool POLY>
 __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, N2Extra<M, R, POLY> Q, PropArgs P,
                                                               EnsDev<R> E, double *__restrict__ partials)
 {
-    __shared__ double lds[4 * 32];
-    const int slot = scatter_slot32(threadIdx.x & 63);
-    propagate_n2_tile<M, R, SCHEME, POLY>(C, Q, P, E, partials, (int64_t)blockIdx.x, slot, lds);
+    __shared__ BinLds lds;
+    int parity = 0;
+    propagate_n2_tile<M, R, SCHEME, POLY>(C, Q, P, E, partials, (int64_t)blockIdx.x, lds, parity);
 }
 
 // Persistent launch over (instance, tile) work items of many two-state
@@ -554,9 +567,9 @@ __global__ __launch_bounds__(kBlock) void batch_n2_kernel(const BatchItemN2<M, R
                                                           int32_t n_items, int64_t total_tiles,
                                                           unsigned long long *counter)
 {
-    __shared__ double lds[4 * 32];
+    __shared__ BinLds lds;
     __shared__ long long item_sh;
-    const int slot = scatter_slot32(threadIdx.x & 63);
+    int parity = 0;
     for (;;) {
         if (threadIdx.x == 0)
             item_sh = (long long)atomicAdd(counter, 1ull);
@@ -575,7 +588,7 @@ __global__ __launch_bounds__(kBlock) void batch_n2_kernel(const BatchItemN2<M, R
             if (items[mid].tile_begin <= item) lo = mid; else hi = mid - 1;
         }
         const BatchItemN2<M, R, POLY> &it = items[lo];
-        propagate_n2_tile<M, R, SCHEME, POLY>(it.C, it.Q, it.P, it.E, it.partials, item - it.tile_begin, slot, lds);
+        propagate_n2_tile<M, R, SCHEME, POLY>(it.C, it.Q, it.P, it.E, it.partials, item - it.tile_begin, lds, parity);
         __syncthreads();
     }
 }

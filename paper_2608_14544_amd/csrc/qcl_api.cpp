@@ -58,6 +58,8 @@ bool symmetric(const double *a, int n)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+bool aligned256(const void *p) { return ((uintptr_t)p & 255) == 0; }
+
 size_t real_size(int32_t prec) { return prec == QCL_FP64 ? sizeof(double) : sizeof(float); }
 
 int64_t leading_dim(int64_t n_traj) { return std::max<int64_t>(64, (n_traj + 63) / 64 * 64); }
@@ -121,6 +123,15 @@ int factor_couplings(int M, int T, const std::vector<double> &kmat, std::vector<
     return rank;
 }
 
+// Rows of a partials buffer: one per tile, then the scratch rows of the
+// pairwise passes of the reduction (at most 1/8 + 1/64 of them); the
+// per-bin excluded counts of qcl_reduce_observables follow.
+int64_t partials_rows(int64_t n_traj)
+{
+    const int64_t t = qcl::n_tiles(n_traj);
+    return t + (t + 7) / 8 + (t + 63) / 64;
+}
+
 qcl_status check_model(qcl_model m)
 {
     if (!m)
@@ -158,10 +169,9 @@ qcl_status check_ensemble(const qcl_model_s &m, const qcl_ensemble *e)
     if (e->n_traj > 0) {
         if (!e->q || !e->p || !e->u || !e->w || !e->phase || !e->a || !e->b)
             return fail(QCL_ERR_INVALID_ARG, "ensemble array pointer is NULL");
-        const size_t rs = real_size(e->prec);
-        if (((uintptr_t)e->q % rs) || ((uintptr_t)e->p % rs) || ((uintptr_t)e->u % rs) ||
-            ((uintptr_t)e->w % 8) || ((uintptr_t)e->phase % 8) || ((uintptr_t)e->flags % 4))
-            return fail(QCL_ERR_INVALID_ARG, "misaligned ensemble array");
+        if (!aligned256(e->q) || !aligned256(e->p) || !aligned256(e->u) || !aligned256(e->w) ||
+            !aligned256(e->phase) || !aligned256(e->a) || !aligned256(e->b) || !aligned256(e->flags))
+            return fail(QCL_ERR_INVALID_ARG, "ensemble arrays must be 256-byte aligned");
     }
     (void)m;
     return QCL_OK;
@@ -189,10 +199,23 @@ qcl_status check_propagate(qcl_model m, const qcl_ensemble *ens, const qcl_prop_
                     pd->n_out);
     if (ens->step + (int64_t)pd->n_steps > ((int64_t)1 << 33))
         return fail(QCL_ERR_INVALID_ARG, "global step counter out of range");
-    if (ens->n_traj > 0 && (!partials || ((uintptr_t)partials % 8)))
-        return fail(QCL_ERR_INVALID_ARG, "partials is NULL or misaligned");
+    if (ens->n_traj > 0 && (!partials || !aligned256(partials)))
+        return fail(QCL_ERR_INVALID_ARG, "partials is NULL or not 256-byte aligned");
     if (ens->n_traj > 0 && pd->n_steps > 0)
         return check_device(*m);
+    return QCL_OK;
+}
+
+qcl_status check_reduce(qcl_model m, const double *partials, int64_t n_traj, int32_t n_out, const double *out)
+{
+    if (qcl_status st = check_model(m))
+        return st;
+    if (n_traj < 1)
+        return fail(QCL_ERR_INVALID_ARG, "n_traj must be >= 1 to average");
+    if (n_out < 1)
+        return fail(QCL_ERR_INVALID_ARG, "n_out must be >= 1");
+    if (!partials || !out || !aligned256(partials) || !aligned256(out))
+        return fail(QCL_ERR_INVALID_ARG, "partials/out NULL or not 256-byte aligned");
     return QCL_OK;
 }
 
@@ -741,6 +764,104 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, cons
 
 }  // namespace
 
+namespace qcl {
+
+qcl_status set_error(qcl_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+// The batched call with a given workspace.  fixed_workspace: the library's
+// own per-device array (qcl_propagate_batch_static): a plan that does not
+// fit is reported against its stated limit, and every class runs on the
+// caller's stream in turn (no side streams are created).
+qcl_status propagate_batch_in(const qcl_batch_item *items, int32_t n_items, void *workspace, size_t workspace_bytes,
+                              void *stream, bool fixed_workspace)
+{
+    BatchPlan plan;
+    if (qcl_status st = plan_batch(items, n_items, plan))
+        return st;
+    if (plan.bytes > 0) {
+        if (!workspace || ((uintptr_t)workspace % 256))
+            return fail(QCL_ERR_INVALID_ARG, "workspace is NULL or not 256-byte aligned");
+        if (workspace_bytes < plan.bytes)
+            return fixed_workspace
+                       ? fail(QCL_ERR_INVALID_ARG,
+                              "this batch needs %zu bytes of descriptors; the static workspace holds %zu "
+                              "(QCL_STATIC_WORKSPACE_BYTES): split the batch, or use qcl_propagate_batch",
+                              plan.bytes, workspace_bytes)
+                       : fail(QCL_ERR_INVALID_ARG, "workspace holds %zu bytes, %zu needed", workspace_bytes,
+                              plan.bytes);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *ws = (uint8_t *)workspace;
+    std::vector<uint64_t> words(plan.bytes / 8, 0);
+    for (const BatchClass &c : plan.classes) {
+        int64_t tile_begin = 0;
+        for (size_t k = 0; k < c.order.size(); ++k) {
+            const qcl_batch_item &it = items[c.order[k]];
+            qcl::batch_item(*it.model, *it.ens, it.prop, it.partials, tile_begin,
+                            (uint8_t *)words.data() + c.offset + k * c.item_bytes);
+            tile_begin += qcl::n_tiles(it.ens->n_traj);
+        }
+    }
+    if (plan.bytes > 0) {
+        // counters (first word of each class block) are zero in the uploaded image
+        hipError_t e = qcl::upload_words(words.data(), words.size(), (uint64_t *)ws, s);
+        if (e != hipSuccess)
+            return device_fail(e, "batch descriptor upload");
+    }
+    auto launch_class = [&](const BatchClass &c, hipStream_t on) {
+        return qcl::launch_batch(*items[c.order[0]].model, c.prec, c.scheme, c.occ, ws + c.offset,
+                                 (int32_t)c.order.size(), c.total_tiles,
+                                 (unsigned long long *)(ws + c.counter_offset), on);
+    };
+    hipError_t e = hipSuccess;
+    if (plan.classes.size() == 1 || fixed_workspace) {
+        for (const BatchClass &c : plan.classes)
+            if (e == hipSuccess)
+                e = launch_class(c, s);
+    } else if (plan.classes.size() > 1) {
+        // heaviest class first, one side stream per class in turn; a class
+        // whose last tiles leave CUs idle is overlapped by the next class
+        std::lock_guard<std::mutex> lock(g_fan_mutex);
+        Fan *f = nullptr;
+        if ((e = device_fan(f)) != hipSuccess)
+            return device_fail(e, "side stream set-up");
+        const int used = (int)std::min<size_t>(kSideStreams, plan.classes.size());
+        if ((e = hipEventRecord(f->fork, s)) != hipSuccess)
+            return device_fail(e, "hipEventRecord");
+        for (int k = 0; k < used; ++k)
+            if ((e = hipStreamWaitEvent(f->s[k], f->fork, 0)) != hipSuccess)
+                return device_fail(e, "hipStreamWaitEvent");
+        for (size_t i = 0; i < plan.classes.size() && e == hipSuccess; ++i)
+            e = launch_class(plan.classes[i], f->s[i % used]);
+        // join whatever was launched back into the caller's stream
+        for (int k = 0; k < used; ++k) {
+            hipError_t ej = hipEventRecord(f->join[k], f->s[k]);
+            if (ej == hipSuccess)
+                ej = hipStreamWaitEvent(s, f->join[k], 0);
+            if (ej != hipSuccess && e == hipSuccess)
+                e = ej;
+        }
+    }
+    if (e == hipErrorNotSupported)
+        return fail(QCL_ERR_UNSUPPORTED, "no batched kernel for this model class");
+    if (e != hipSuccess)
+        return device_fail(e, "batched propagate launch");
+    for (int32_t i = 0; i < n_items; ++i)
+        items[i].ens->step += items[i].prop.n_steps;
+    return QCL_OK;
+}
+
+}  // namespace qcl
+
 extern "C" {
 
 const char *qcl_last_error(void) { return g_last_error.c_str(); }
@@ -852,9 +973,7 @@ qcl_status qcl_partials_bytes(qcl_model m, int64_t n_traj, int32_t n_out, size_t
         return fail(QCL_ERR_INVALID_ARG, "NULL output");
     if (n_traj < 0 || n_out < 1)
         return fail(QCL_ERR_INVALID_ARG, "n_traj >= 0 and n_out >= 1 required");
-    const int64_t t = qcl::n_tiles(n_traj);
-    const int64_t rows = t + (t + 7) / 8 + (t + 63) / 64;
-    *bytes = (size_t)rows * n_out * qcl::tile_values(m->n) * sizeof(double);
+    *bytes = (partials_rows(n_traj) * n_out * qcl::tile_values(m->n) + n_out) * sizeof(double);
     return QCL_OK;
 }
 
@@ -877,8 +996,8 @@ qcl_status qcl_sample_initial(qcl_model m, const qcl_init_desc *init, uint64_t s
         return fail(QCL_ERR_INVALID_ARG, "non-finite q0");
     if (n_out < 1)
         return fail(QCL_ERR_INVALID_ARG, "n_out must be >= 1");
-    if (ens->n_traj > 0 && (!partials || ((uintptr_t)partials % 8)))
-        return fail(QCL_ERR_INVALID_ARG, "partials is NULL or misaligned");
+    if (ens->n_traj > 0 && (!partials || !aligned256(partials)))
+        return fail(QCL_ERR_INVALID_ARG, "partials is NULL or not 256-byte aligned");
     qcl::SampleArgs sa{};
     for (int j = 0; j < m->m; ++j) {
         const double w = m->omega[j], ms = m->mass[j], hb = m->hbar;
@@ -939,72 +1058,7 @@ qcl_status qcl_batch_workspace_bytes(const qcl_batch_item *items, int32_t n_item
 qcl_status qcl_propagate_batch(const qcl_batch_item *items, int32_t n_items, void *workspace, size_t workspace_bytes,
                                void *stream)
 {
-    BatchPlan plan;
-    if (qcl_status st = plan_batch(items, n_items, plan))
-        return st;
-    if (plan.bytes > 0) {
-        if (!workspace || ((uintptr_t)workspace % 256))
-            return fail(QCL_ERR_INVALID_ARG, "workspace is NULL or not 256-byte aligned");
-        if (workspace_bytes < plan.bytes)
-            return fail(QCL_ERR_INVALID_ARG, "workspace holds %zu bytes, %zu needed", workspace_bytes, plan.bytes);
-    }
-    hipStream_t s = (hipStream_t)stream;
-    uint8_t *ws = (uint8_t *)workspace;
-    std::vector<uint64_t> words(plan.bytes / 8, 0);
-    for (const BatchClass &c : plan.classes) {
-        int64_t tile_begin = 0;
-        for (size_t k = 0; k < c.order.size(); ++k) {
-            const qcl_batch_item &it = items[c.order[k]];
-            qcl::batch_item(*it.model, *it.ens, it.prop, it.partials, tile_begin,
-                            (uint8_t *)words.data() + c.offset + k * c.item_bytes);
-            tile_begin += qcl::n_tiles(it.ens->n_traj);
-        }
-    }
-    if (plan.bytes > 0) {
-        // counters (first word of each class block) are zero in the uploaded image
-        hipError_t e = qcl::upload_words(words.data(), words.size(), (uint64_t *)ws, s);
-        if (e != hipSuccess)
-            return device_fail(e, "batch descriptor upload");
-    }
-    auto launch_class = [&](const BatchClass &c, hipStream_t on) {
-        return qcl::launch_batch(*items[c.order[0]].model, c.prec, c.scheme, c.occ, ws + c.offset,
-                                 (int32_t)c.order.size(), c.total_tiles,
-                                 (unsigned long long *)(ws + c.counter_offset), on);
-    };
-    hipError_t e = hipSuccess;
-    if (plan.classes.size() == 1) {
-        e = launch_class(plan.classes[0], s);
-    } else if (plan.classes.size() > 1) {
-        // heaviest class first, one side stream per class in turn; a class
-        // whose last tiles leave CUs idle is overlapped by the next class
-        std::lock_guard<std::mutex> lock(g_fan_mutex);
-        Fan *f = nullptr;
-        if ((e = device_fan(f)) != hipSuccess)
-            return device_fail(e, "side stream set-up");
-        const int used = (int)std::min<size_t>(kSideStreams, plan.classes.size());
-        if ((e = hipEventRecord(f->fork, s)) != hipSuccess)
-            return device_fail(e, "hipEventRecord");
-        for (int k = 0; k < used; ++k)
-            if ((e = hipStreamWaitEvent(f->s[k], f->fork, 0)) != hipSuccess)
-                return device_fail(e, "hipStreamWaitEvent");
-        for (size_t i = 0; i < plan.classes.size() && e == hipSuccess; ++i)
-            e = launch_class(plan.classes[i], f->s[i % used]);
-        // join whatever was launched back into the caller's stream
-        for (int k = 0; k < used; ++k) {
-            hipError_t ej = hipEventRecord(f->join[k], f->s[k]);
-            if (ej == hipSuccess)
-                ej = hipStreamWaitEvent(s, f->join[k], 0);
-            if (ej != hipSuccess && e == hipSuccess)
-                e = ej;
-        }
-    }
-    if (e == hipErrorNotSupported)
-        return fail(QCL_ERR_UNSUPPORTED, "no batched kernel for this model class");
-    if (e != hipSuccess)
-        return device_fail(e, "batched propagate launch");
-    for (int32_t i = 0; i < n_items; ++i)
-        items[i].ens->step += items[i].prop.n_steps;
-    return QCL_OK;
+    return qcl::propagate_batch_in(items, n_items, workspace, workspace_bytes, stream, false);
 }
 
 qcl_status qcl_resample_workspace_bytes(int64_t n_traj, size_t *bytes)
@@ -1051,20 +1105,52 @@ qcl_status qcl_resample(qcl_model m, const qcl_ensemble *src, qcl_ensemble *dst,
     return QCL_OK;
 }
 
+qcl_status qcl_reduce_observables_async(qcl_model m, double *partials, int64_t n_traj, int32_t n_out, double *out,
+                                        int64_t *excluded, void *stream)
+{
+    if (qcl_status st = check_reduce(m, partials, n_traj, n_out, out))
+        return st;
+    if (excluded && !aligned256(excluded))
+        return fail(QCL_ERR_INVALID_ARG, "excluded is not 256-byte aligned");
+    hipError_t e = qcl::launch_reduce(m->n, partials, n_traj, n_out, out, excluded, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return device_fail(e, "reduce kernel launch");
+    return QCL_OK;
+}
+
 qcl_status qcl_reduce_observables(qcl_model m, double *partials, int64_t n_traj, int32_t n_out, double *out,
                                   void *stream)
 {
-    if (qcl_status st = check_model(m))
+    if (qcl_status st = check_reduce(m, partials, n_traj, n_out, out))
         return st;
-    if (n_traj < 1)
-        return fail(QCL_ERR_INVALID_ARG, "n_traj must be >= 1 to average");
-    if (n_out < 1)
-        return fail(QCL_ERR_INVALID_ARG, "n_out must be >= 1");
-    if (!partials || !out || ((uintptr_t)partials % 8) || ((uintptr_t)out % 8))
-        return fail(QCL_ERR_INVALID_ARG, "partials/out NULL or misaligned");
-    hipError_t e = qcl::launch_reduce(m->n, partials, n_traj, n_out, out, (hipStream_t)stream);
+    // the counts go to the slots after the scratch rows of the partials
+    int64_t *counts = (int64_t *)(partials + partials_rows(n_traj) * n_out * qcl::tile_values(m->n));
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = qcl::launch_reduce(m->n, partials, n_traj, n_out, out, counts, s);
     if (e != hipSuccess)
         return device_fail(e, "reduce kernel launch");
+    int64_t worst = 0, worst_bin = -1, first_bin = -1;
+    int64_t buf[256];  // counts are read back in chunks: nothing is allocated
+    for (int32_t o0 = 0; o0 < n_out; o0 += 256) {
+        const int32_t n = std::min<int32_t>(256, n_out - o0);
+        if ((e = hipMemcpyAsync(buf, counts + o0, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return device_fail(e, "reading the excluded counts");
+        for (int32_t k = 0; k < n; ++k) {
+            if (buf[k] > 0 && first_bin < 0)
+                first_bin = o0 + k;
+            if (buf[k] > worst) {
+                worst = buf[k];
+                worst_bin = o0 + k;
+            }
+        }
+    }
+    if (worst > 0)
+        return fail(QCL_ERR_NONFINITE,
+                    "%lld of %lld walkers excluded from bin %lld (non-finite weight or phase; first excluded at bin "
+                    "%lld); the averages are over the finite walkers, normalised by all %lld",
+                    (long long)worst, (long long)n_traj, (long long)worst_bin, (long long)first_bin,
+                    (long long)n_traj);
     return QCL_OK;
 }
 

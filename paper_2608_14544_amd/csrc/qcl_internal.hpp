@@ -353,8 +353,19 @@ inline hipError_t launch_propagate_general(const qcl_model_s &m, const qcl_ensem
     return with_general(m, hipErrorNotSupported,
                         [&](auto tag) { return launch_propagate_general_n(m, ens, pd, partials, s, tag); });
 }
+// Records the thread's last error (qcl_last_error) and returns st.
+qcl_status set_error(qcl_status st, const char *fmt, ...);
+
+// qcl_propagate_batch with a given workspace; fixed_workspace marks the
+// library's static per-device array (limit reported as such, no side streams).
+qcl_status propagate_batch_in(const qcl_batch_item *items, int32_t n_items, void *workspace, size_t workspace_bytes,
+                              void *stream, bool fixed_workspace);
+
+// Reduces the tile partials to out [n_out][2][N][N][4]; when excluded is
+// not NULL, also writes there the number of walkers excluded from each bin
+// (int64 [n_out]).
 hipError_t launch_reduce(int n_states, double *partials, int64_t n_traj, int32_t n_out, double *out,
-                         hipStream_t stream);
+                         int64_t *excluded, hipStream_t stream);
 
 // workspace of qcl_resample: byte offsets of its parts and the total
 struct ResampleLayout {
@@ -365,6 +376,9 @@ hipError_t launch_resample(const qcl_model_s &m, const qcl_ensemble &src, const 
                            void *workspace, hipStream_t stream);
 
 inline int64_t n_tiles(int64_t n_traj) { return (n_traj + kBlock - 1) / kBlock; }
-inline int64_t tile_values(int n_states) { return 8LL * n_states * n_states; }
+// One bin of one tile's partials: the 8 N^2 sums [2][N][N][Re, Im, Re^2,
+// Im^2], then the number of walkers excluded from the bin (non-finite weight
+// or phase), stored as a double so that the tile reduction adds it exactly.
+__host__ __device__ constexpr int64_t tile_values(int n_states) { return 8LL * n_states * n_states + 1; }
 
 }  // namespace qcl

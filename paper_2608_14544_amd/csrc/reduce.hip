@@ -1,8 +1,9 @@
 // Ensemble averages from tile partials (Sec. II.B: fixed summation order).
 //
 // The partials hold, per tile of QCL_TILE walkers, the sums of every bin
-// value.  They are combined by a perfect pairwise tree over the tile index
-// (zero-padded): each pass adds groups of 8 consecutive rows as
+// value and the number of walkers excluded from each bin.  They are
+// combined by a perfect pairwise tree over the tile index (zero-padded):
+// each pass adds groups of 8 consecutive rows as
 // ((x0+x1)+(x2+x3))+((x4+x5)+(x6+x7)), i.e. three levels of the binary tree,
 // until one row remains.  The final kernel turns the sums into means and
 // standard errors.  The work is HBM-bound and tiny next to propagation.
@@ -32,20 +33,29 @@ __global__ __launch_bounds__(256) void pairwise8_kernel(const double *__restrict
     }
 }
 
-// sums [n_out][2][N][N][4] (Re, Im, Re^2, Im^2) -> (mean Re, mean Im, SE Re, SE Im)
-__global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict__ sums, int64_t n_groups, double T,
-                                                       double *__restrict__ out)
+// sums: per bin 2 N^2 groups (Re, Im, Re^2, Im^2) followed by the excluded
+// count -> out [n_out][2][N][N] (mean Re, mean Im, SE Re, SE Im) and, when
+// excluded is given, the counts [n_out]
+__global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict__ sums, int32_t n_out,
+                                                       int32_t groups_per_bin, double T, double *__restrict__ out,
+                                                       int64_t *__restrict__ excluded)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_groups)
-        return;
-    const double s0 = sums[4 * g + 0], s1 = sums[4 * g + 1], s2 = sums[4 * g + 2], s3 = sums[4 * g + 3];
-    const double vr = (s2 - s0 * s0 / T) / (T * (T - 1.0));
-    const double vi = (s3 - s1 * s1 / T) / (T * (T - 1.0));
-    out[4 * g + 0] = s0 / T;
-    out[4 * g + 1] = s1 / T;
-    out[4 * g + 2] = (T > 1.0 && vr > 0.0) ? sqrt(vr) : 0.0;
-    out[4 * g + 3] = (T > 1.0 && vi > 0.0) ? sqrt(vi) : 0.0;
+    const int64_t n_groups = (int64_t)n_out * groups_per_bin;
+    const int64_t row = 4LL * groups_per_bin + 1;  // doubles per bin
+    if (g < n_groups) {
+        const int64_t o = g / groups_per_bin, k = g - o * groups_per_bin;
+        const double *s = sums + o * row + 4 * k;
+        const double s0 = s[0], s1 = s[1], s2 = s[2], s3 = s[3];
+        const double vr = (s2 - s0 * s0 / T) / (T * (T - 1.0));
+        const double vi = (s3 - s1 * s1 / T) / (T * (T - 1.0));
+        out[4 * g + 0] = s0 / T;
+        out[4 * g + 1] = s1 / T;
+        out[4 * g + 2] = (T > 1.0 && vr > 0.0) ? sqrt(vr) : 0.0;
+        out[4 * g + 3] = (T > 1.0 && vi > 0.0) ? sqrt(vi) : 0.0;
+    }
+    if (excluded && g < n_out)
+        excluded[g] = (int64_t)sums[g * row + row - 1];
 }
 
 // Host words travel inside the kernel arguments (captured at launch), so the
@@ -93,7 +103,8 @@ hipError_t zero_words(uint64_t *dst, size_t n_words, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(int n_states, double *partials, int64_t n_traj, int32_t n_out, double *out, hipStream_t s)
+hipError_t launch_reduce(int n_states, double *partials, int64_t n_traj, int32_t n_out, double *out,
+                         int64_t *excluded, hipStream_t s)
 {
     const int64_t tiles = n_tiles(n_traj);
     const int64_t cols = (int64_t)n_out * tile_values(n_states);
@@ -115,9 +126,10 @@ hipError_t launch_reduce(int n_states, double *partials, int64_t n_traj, int32_t
         rows = rows_out;
         to_a = !to_a;
     }
-    const int64_t groups = cols / 4;
-    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, src, groups,
-                       (double)n_traj, out);
+    const int32_t gpb = 2 * n_states * n_states;
+    const int64_t threads = std::max<int64_t>((int64_t)n_out * gpb, n_out);
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, src, n_out, gpb,
+                       (double)n_traj, out, excluded);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ QCL_ERR_INVALID_ARG = 1
 QCL_ERR_UNSUPPORTED = 2
 QCL_ERR_OUT_OF_MEMORY = 3
 QCL_ERR_DEVICE = 4
+QCL_ERR_NONFINITE = 5
 
 QCL_FP64 = 0
 QCL_FP32_ACC64 = 1
@@ -43,6 +44,7 @@ class QCLError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"qcl status {status}: {msg}")
         self.status = status
+        self.out = None  # QCL_ERR_NONFINITE: the averages, which are written regardless
 
 
 class qcl_model_desc(C.Structure):
@@ -89,7 +91,8 @@ EXPORTS = ("qcl_create_model", "qcl_create_model_poly", "qcl_create_model_biline
            "qcl_model_states", "qcl_model_modes", "qcl_model_rank", "qcl_model_degree", "qcl_model_pairs",
            "qcl_ensemble_bytes", "qcl_ensemble_bind", "qcl_partials_bytes",
            "qcl_sample_initial", "qcl_propagate", "qcl_batch_workspace_bytes", "qcl_propagate_batch",
-           "qcl_reduce_observables", "qcl_resample_workspace_bytes", "qcl_resample", "qcl_last_error")
+           "qcl_reduce_observables", "qcl_reduce_observables_async", "qcl_resample_workspace_bytes", "qcl_resample",
+           "qcl_last_error")
 
 _lock = threading.Lock()
 _lib = None
@@ -129,6 +132,7 @@ def load_library(path: str = LIB_PATH):
         L.qcl_batch_workspace_bytes.argtypes = [C.POINTER(qcl_batch_item), i32, C.POINTER(sz)]
         L.qcl_propagate_batch.argtypes = [C.POINTER(qcl_batch_item), i32, vp, sz, vp]
         L.qcl_reduce_observables.argtypes = [vp, vp, i64, i32, vp, vp]
+        L.qcl_reduce_observables_async.argtypes = [vp, vp, i64, i32, vp, vp, vp]
         L.qcl_resample_workspace_bytes.argtypes = [i64, C.POINTER(sz)]
         L.qcl_resample.argtypes = [vp, C.POINTER(qcl_ensemble), C.POINTER(qcl_ensemble), u64, vp, sz, vp]
         L.qcl_last_error.argtypes = []
@@ -405,8 +409,7 @@ def qcl_propagate_batch(jobs, workspace: Optional[Workspace] = None, stream=None
     return ws
 
 
-def qcl_reduce_observables(model: Model, partials: Partials, n_traj: int, out=None, stream=None):
-    """Returns a device tensor [n_out, 2, N, N, 4]: mean Re, mean Im, SE Re, SE Im."""
+def _reduce_args(model: Model, partials: Partials, n_traj: int, out):
     torch = _torch()
     _match(model, None, partials)
     if int(n_traj) != partials.n_traj:
@@ -420,9 +423,40 @@ def qcl_reduce_observables(model: Model, partials: Partials, n_traj: int, out=No
     elif tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous() \
             or out.device != partials.tensor.device:
         raise ValueError(f"out must be a contiguous float64 tensor of shape {shape} on {partials.tensor.device}")
-    _check(load_library().qcl_reduce_observables(model.handle, partials.ptr, int(n_traj), partials.n_out,
-                                                 C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(stream))))
     return out
+
+
+def qcl_reduce_observables(model: Model, partials: Partials, n_traj: int, out=None, stream=None):
+    """Returns a device tensor [n_out, 2, N, N, 4]: mean Re, mean Im, SE Re, SE Im.
+    Waits for the reduction; raises QCLError (status QCL_ERR_NONFINITE, the
+    result in its ``out``) when walkers with a non-finite weight or phase
+    were left out of a bin."""
+    out = _reduce_args(model, partials, n_traj, out)
+    st = load_library().qcl_reduce_observables(model.handle, partials.ptr, int(n_traj), partials.n_out,
+                                               C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(stream)))
+    if st == QCL_ERR_NONFINITE:
+        err = QCLError(st, load_library().qcl_last_error().decode())
+        err.out = out
+        raise err
+    _check(st)
+    return out
+
+
+def qcl_reduce_observables_async(model: Model, partials: Partials, n_traj: int, out=None, excluded=None,
+                                 stream=None):
+    """Enqueues the reduction without waiting; returns (out, excluded) device
+    tensors, excluded [n_out] int64 holding the walkers left out of each bin."""
+    torch = _torch()
+    out = _reduce_args(model, partials, n_traj, out)
+    if excluded is None:
+        excluded = torch.empty(partials.n_out, dtype=torch.int64, device=out.device)
+    elif tuple(excluded.shape) != (partials.n_out,) or excluded.dtype != torch.int64 or \
+            not excluded.is_contiguous() or excluded.device != out.device:
+        raise ValueError(f"excluded must be a contiguous int64 tensor of shape ({partials.n_out},) on {out.device}")
+    _check(load_library().qcl_reduce_observables_async(model.handle, partials.ptr, int(n_traj), partials.n_out,
+                                                       C.c_void_p(out.data_ptr()), C.c_void_p(excluded.data_ptr()),
+                                                       C.c_void_p(_stream_handle(stream))))
+    return out, excluded
 
 
 def qcl_resample_workspace_bytes(n_traj: int) -> int:

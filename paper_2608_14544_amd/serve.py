@@ -69,6 +69,7 @@ class JobResult:
     finished: float
     walker_steps: int
     error: str = ""
+    excluded: int = 0             # walkers left out of a bin (non-finite weight or phase), largest over bins
 
     @property
     def latency(self) -> float:
@@ -144,12 +145,14 @@ class DeviceBackend:
         torch = self.torch
         m, ens, part = handle
         with torch.cuda.stream(self.stream):
-            out = self.Q.qcl_reduce_observables(m, part, spec.n_traj, stream=self.stream)
+            out, excl = self.Q.qcl_reduce_observables_async(m, part, spec.n_traj, stream=self.stream)
             host = torch.empty(out.shape, dtype=out.dtype, pin_memory=True)
             host.copy_(out, non_blocking=True)
+            host_excl = torch.empty(excl.shape, dtype=excl.dtype, pin_memory=True)
+            host_excl.copy_(excl, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.stream)
-        return _DeviceFuture(ev, host, (out, part, ens))
+        return _DeviceFuture(ev, host, (out, excl, part, ens), host_excl)
 
     def release(self, handle):
         pass  # tensors go back to the stream-ordered caching allocator with the handle
@@ -164,8 +167,8 @@ class DeviceBackend:
 
 
 class _DeviceFuture:
-    def __init__(self, ev, host, keep):
-        self.ev, self.host, self.keep = ev, host, keep
+    def __init__(self, ev, host, keep, host_excluded=None):
+        self.ev, self.host, self.keep, self.host_excluded = ev, host, keep, host_excluded
 
     def ready(self) -> bool:
         if self.ev.query():
@@ -177,6 +180,11 @@ class _DeviceFuture:
         self.ev.synchronize()
         self.keep = None
         return self.host.numpy().copy()
+
+    def excluded(self) -> int:
+        """Largest number of walkers a bin left out (non-finite weight or phase)."""
+        self.ev.synchronize()
+        return int(self.host_excluded.max()) if self.host_excluded is not None else 0
 
 
 class Server:
@@ -293,7 +301,7 @@ class Server:
             if j.pending.ready():
                 self.used -= j.footprint
                 r = JobResult(j.job_id, j.spec.name, j.pending.result(), j.arrival, j.admitted, self.now(),
-                              j.spec.walker_steps)
+                              j.spec.walker_steps, excluded=j.pending.excluded())
                 self.results.append(r)
                 done.append(r)
             else:
@@ -396,3 +404,6 @@ class _SimFuture:
 
     def result(self):
         return np.array([self.handle["steps"]], dtype=np.float64)
+
+    def excluded(self):
+        return 0

@@ -140,9 +140,11 @@ def check_ensemble32(out_g, out_o, n_traj, tol=1e-3, label="", g=None, o=None):
     return flip
 
 
-def gpu_run(P, wl, prec="fp64", n_traj=None, n_steps=None, scheme=0, split=None):
+def gpu_run(P, wl, prec="fp64", n_traj=None, n_steps=None, scheme=0, split=None, expect_excluded=False):
     """Sample, propagate (optionally in several calls) and reduce on the
-    device; returns (out, final state, sampled state, ensemble)."""
+    device; returns (out, final state, sampled state, ensemble).  With
+    ``expect_excluded`` the reduction must report walkers left out of the
+    sums (QCL_ERR_NONFINITE); its averages are returned all the same."""
     import torch
     r = wl.run
     T = r.n_traj if n_traj is None else n_traj
@@ -157,7 +159,17 @@ def gpu_run(P, wl, prec="fp64", n_traj=None, n_steps=None, scheme=0, split=None)
     assert sum(chunks) == S
     for c in chunks:
         P.qcl_propagate(model, ens, r.dt, c, r.cadence, r.seed, part, scheme)
-    out = P.qcl_reduce_observables(model, part, T) if T > 0 else None
+    out = None
+    if T > 0 and expect_excluded:
+        try:
+            P.qcl_reduce_observables(model, part, T)
+        except P.QCLError as e:
+            assert e.status == P.QCL_ERR_NONFINITE, e
+            print("reduce:", e, flush=True)
+            out = e.out
+        assert out is not None, "the reduction did not report the excluded walkers"
+    elif T > 0:
+        out = P.qcl_reduce_observables(model, part, T)
     torch.cuda.synchronize()
     return (out.cpu().numpy() if out is not None else None), ens.to_numpy(), sample_state, ens
 

@@ -234,3 +234,46 @@ def test_binding_rejects_mismatched_buffers_before_any_launch():
         qcl.BatchJob(m2, ens, part, 0.1, 10, 5, 0).item()
     with pytest.raises(ValueError, match="another model"):
         qcl.qcl_sample_initial(m2, None, 0, ens, part)
+
+
+def test_device_pointers_must_be_256_byte_aligned():
+    """Device arrays are validated for 256-byte alignment on the host before
+    any launch (the model handle is not read before that check, so a
+    stand-in handle suffices here)."""
+    qcl, L = _lib()
+    fake_model = C.c_void_p(C.addressof(C.create_string_buffer(64)))
+    base = 1 << 40  # addresses only: nothing is dereferenced
+    ens = qcl.qcl_ensemble()
+    ens.n_traj, ens.ld, ens.prec = 100, 128, 0
+    for i, f in enumerate(("q", "p", "u", "w", "phase", "a", "b", "flags")):
+        setattr(ens, f, base + 4096 * i)
+    pd = qcl.qcl_prop_desc(0.1, 10, 5, 3, 0, 0, 0, 0)
+    # every array aligned, partials misaligned
+    assert L.qcl_propagate(fake_model, C.byref(ens), C.byref(pd), C.c_void_p(base + 8), None) == \
+        qcl.QCL_ERR_INVALID_ARG
+    assert b"256-byte" in L.qcl_last_error()
+    for f in ("q", "w", "a", "flags"):
+        setattr(ens, f, getattr(ens, f) + 64)
+        assert L.qcl_propagate(fake_model, C.byref(ens), C.byref(pd), C.c_void_p(base + 1 << 20), None) == \
+            qcl.QCL_ERR_INVALID_ARG, f
+        assert b"256-byte" in L.qcl_last_error()
+        setattr(ens, f, getattr(ens, f) - 64)
+    out = C.c_void_p(base + (2 << 20))
+    assert L.qcl_reduce_observables(fake_model, C.c_void_p(base + 16), 10, 3, out, None) == qcl.QCL_ERR_INVALID_ARG
+    assert b"256-byte" in L.qcl_last_error()
+    assert L.qcl_reduce_observables_async(fake_model, C.c_void_p(base), 10, 3, C.c_void_p(base + 520), None,
+                                          None) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_reduce_observables_async(fake_model, C.c_void_p(base), 10, 3, out, C.c_void_p(base + 8),
+                                          None) == qcl.QCL_ERR_INVALID_ARG
+    assert b"excluded" in L.qcl_last_error()
+
+
+def test_nonfinite_status_in_header_and_binding():
+    """QCL_ERR_NONFINITE is declared with its value in include/qcl.h and the
+    binding raises it with the averages attached."""
+    from paper_2608_14544_amd import qcl
+    txt = open(os.path.join(ROOT, "include", "qcl.h")).read()
+    assert re.search(r"QCL_ERR_NONFINITE\s*=\s*5", txt)
+    assert qcl.QCL_ERR_NONFINITE == 5
+    e = qcl.QCLError(5, "3 of 10 walkers excluded")
+    assert e.status == 5 and e.out is None

@@ -24,16 +24,29 @@ def P():
 @pytest.mark.parametrize("n_states,n_modes", [(2, 1), (3, 2), (4, 12)])
 def test_exactly_degenerate_model(P, n_states, n_modes):
     """V = 0 everywhere: every walker meets a zero gap, is flagged degenerate
-    and non-finite, and is left out of the sums, as in the oracle."""
+    and non-finite, and is left out of the sums, as in the oracle; the
+    reduction reports them (QCL_ERR_NONFINITE, with the count per bin from
+    the asynchronous call)."""
+    import torch
     lvc = W.LVCModel(name="flat", mass=np.ones(n_modes), omega=np.ones(n_modes),
                      v0=np.zeros((n_states, n_states)), k=np.zeros((n_modes, n_states, n_states)))
     wl = W.Workload(lvc, W.InitSpec(kT=0.5, q0=np.zeros(n_modes), state=0), W.RunSpec(300, 20, 0.05, 10, 5))
     for prec in ("fp64", "fp32"):
-        out_g, st_g, _, _ = gpu_run(P, wl, prec=prec)
+        out_g, st_g, _, ens = gpu_run(P, wl, prec=prec, expect_excluded=True)
         out_o, st_o, _, fl_o = oracle_run(wl)
         assert np.array_equal(st_g["flags"] & 3, np.asarray(fl_o) & 3), prec
         assert np.all(np.isfinite(out_g)), prec
         assert np.array_equal(out_g[1:], out_o[1:]), prec  # all walkers excluded: zeros
+        # the per-bin counts: bin 0 (sampled state, finite) none, every later bin all 300
+        r = wl.run
+        model = P.Model(wl.model)
+        e2 = P.Ensemble(model, r.n_traj, prec)
+        part = P.Partials(model, r.n_traj, r.n_out)
+        P.qcl_sample_initial(model, wl.init, r.seed, e2, part)
+        P.qcl_propagate(model, e2, r.dt, r.n_steps, r.cadence, r.seed, part)
+        _, excl = P.qcl_reduce_observables_async(model, part, r.n_traj)
+        torch.cuda.synchronize()
+        assert excl.cpu().tolist() == [0] + [r.n_traj] * (r.n_out - 1), (prec, excl.cpu().tolist())
 
 
 @pytest.mark.parametrize("n_states,n_modes", [(3, 100), (4, 128)])

@@ -23,13 +23,14 @@ def test_captured_step_replays_bitwise():
         ens = P.Ensemble(model, r.n_traj, prec)
         part = P.Partials(model, r.n_traj, r.n_out)
         out = torch.empty((r.n_out, 2, N, N, 4), dtype=torch.float64, device="cuda")
+        excl = torch.empty(r.n_out, dtype=torch.int64, device="cuda")
         side = torch.cuda.Stream()  # default priority
 
         def step(stream):
             P.qcl_sample_initial(model, wl.init, r.seed, ens, part, stream)
             ens.c.step = 0  # the host-side counter is what the next call reads
             P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part, stream=stream)
-            P.qcl_reduce_observables(model, part, r.n_traj, out, stream)
+            P.qcl_reduce_observables_async(model, part, r.n_traj, out, excl, stream)
 
         with torch.cuda.stream(side):
             step(side)
@@ -45,4 +46,5 @@ def test_captured_step_replays_bitwise():
             g.replay()
             torch.cuda.synchronize()
             assert np.array_equal(out.cpu().numpy(), eager), (prec, rep)
+            assert int(excl.max()) == 0
             del junk
