@@ -344,6 +344,27 @@ qcl_status qcl_batch_workspace_bytes(const qcl_batch_item *items, int32_t n_item
 qcl_status qcl_propagate_batch(const qcl_batch_item *items, int32_t n_items, void *workspace,
                                size_t workspace_bytes, void *stream);
 
+/* Size of the library's own per-device workspace used by
+ * qcl_propagate_batch_static: room for the descriptors of about 2000
+ * batch items (each GPU the library runs on holds it until the process
+ * ends). */
+#define QCL_STATIC_WORKSPACE_BYTES (4u << 20)
+
+/* qcl_propagate_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same propagation, bitwise, with the descriptors and tile
+ * counters in a library-owned static device array of
+ * QCL_STATIC_WORKSPACE_BYTES per device instead of a caller workspace.  It
+ * calls no hipMalloc, hipFree or other device allocation; its classes run
+ * one after another on the given stream (no side streams).  Every call on a
+ * device rewrites that device's array (descriptors and zeroed counters);
+ * calls whose execution overlaps on one device race on it, so they must be
+ * ordered (one stream, or events).  Errors: as qcl_propagate_batch;
+ * INVALID_ARG also when the batch's descriptors exceed
+ * QCL_STATIC_WORKSPACE_BYTES (qcl_batch_workspace_bytes gives the size
+ * needed), DEVICE when the array's address cannot be obtained. */
+qcl_status qcl_propagate_batch_static(const qcl_batch_item *items, int32_t n_items, void *stream);
+
 /* Ensemble averages (Sec. II.B: deterministic-order reduction).  Sums the
  * tile partials over tiles in a fixed pairwise tree and writes, to device
  * memory out [n_out][2][N][N][4]:

@@ -19,7 +19,8 @@ SOURCES = ["qcl_api.cpp", "kernels_n2.hip", "kernels_gen2.hip", "kernels_gen3.hi
            "kernels_gen5.hip", "kernels_gen6.hip", "kernels_gen7.hip", "kernels_gen8.hip",
            "kernels_poly2.hip", "kernels_poly3.hip", "kernels_poly4.hip", "kernels_bil2.hip", "kernels_bil3.hip",
            "kernels_bil4.hip", "kernels_bilh2.hip", "kernels_bilh3.hip", "kernels_bilh4.hip",
-           "kernels_bilw2.hip", "kernels_bilw3.hip", "kernels_bilw4.hip", "reduce.hip", "resample.hip"]
+           "kernels_bilw2.hip", "kernels_bilw3.hip", "kernels_bilw4.hip", "reduce.hip", "resample.hip",
+           "batch_static.hip"]
 
 # Packed-FP32 instructions are disabled on purpose: the step code is
 # written in scalar FP32/FP64 and relies on plain IEEE results.

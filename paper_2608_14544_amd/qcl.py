@@ -91,6 +91,7 @@ EXPORTS = ("qcl_create_model", "qcl_create_model_poly", "qcl_create_model_biline
            "qcl_model_states", "qcl_model_modes", "qcl_model_rank", "qcl_model_degree", "qcl_model_pairs",
            "qcl_ensemble_bytes", "qcl_ensemble_bind", "qcl_partials_bytes",
            "qcl_sample_initial", "qcl_propagate", "qcl_batch_workspace_bytes", "qcl_propagate_batch",
+           "qcl_propagate_batch_static",
            "qcl_reduce_observables", "qcl_reduce_observables_async", "qcl_resample_workspace_bytes", "qcl_resample",
            "qcl_last_error")
 
@@ -131,6 +132,7 @@ def load_library(path: str = LIB_PATH):
         L.qcl_propagate.argtypes = [vp, C.POINTER(qcl_ensemble), C.POINTER(qcl_prop_desc), vp, vp]
         L.qcl_batch_workspace_bytes.argtypes = [C.POINTER(qcl_batch_item), i32, C.POINTER(sz)]
         L.qcl_propagate_batch.argtypes = [C.POINTER(qcl_batch_item), i32, vp, sz, vp]
+        L.qcl_propagate_batch_static.argtypes = [C.POINTER(qcl_batch_item), i32, vp]
         L.qcl_reduce_observables.argtypes = [vp, vp, i64, i32, vp, vp]
         L.qcl_reduce_observables_async.argtypes = [vp, vp, i64, i32, vp, vp, vp]
         L.qcl_resample_workspace_bytes.argtypes = [i64, C.POINTER(sz)]
@@ -424,6 +426,13 @@ def _reduce_args(model: Model, partials: Partials, n_traj: int, out):
             or out.device != partials.tensor.device:
         raise ValueError(f"out must be a contiguous float64 tensor of shape {shape} on {partials.tensor.device}")
     return out
+
+
+def qcl_propagate_batch_static(jobs, stream=None):
+    """qcl_propagate_batch with the library's own per-device workspace (no
+    device allocation by the library or here)."""
+    arr = (qcl_batch_item * len(jobs))(*[j.item() for j in jobs])
+    _check(load_library().qcl_propagate_batch_static(arr, len(jobs), C.c_void_p(_stream_handle(stream))))
 
 
 def qcl_reduce_observables(model: Model, partials: Partials, n_traj: int, out=None, stream=None):
