@@ -36,8 +36,18 @@
 #include "philox.hpp"
 #include "qcl_internal.hpp"
 
+// Floating-point contraction is off in this file: every fused multiply-add
+// is written out (fma2), so each copy of the step body in the unrolled loop
+// below computes exactly the same operations, and a walker's result does
+// not depend on which copy ran a given step (calls split anywhere give the
+// same bits).
+#pragma clang fp contract(off)
+
 namespace qcl {
 namespace {
+
+__device__ __forceinline__ float fma2(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma2(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // 1/sqrt.  binary32: the hardware v_rsq_f32 (about 1 ulp); arguments are
 // squared gaps that are either well above the binary32 denormal range or
@@ -55,7 +65,7 @@ struct Geo2 {
 template <typename R>
 __device__ __forceinline__ void geo2(R dl, R cc, Geo2<R> &g)
 {
-    const R r2 = dl * dl + cc * cc;
+    const R r2 = fma2(dl, dl, cc * cc);
     const R rinv = rsq(r2);
     const R r = r2 * rinv;
     const bool pos = dl >= R(0);
@@ -63,15 +73,15 @@ __device__ __forceinline__ void geo2(R dl, R cc, Geo2<R> &g)
     g.cc = cc;
     g.r = r;
     g.rinv = rinv;
-    g.x0 = pos ? r + dl : cc;
-    g.x1 = pos ? cc : r - dl;
+    g.x0 = pos ? fma2(r2, rinv, dl) : cc;   // r + dl
+    g.x1 = pos ? cc : fma2(r2, rinv, -dl);  // r - dl
 }
 
 // normalised canonical upper eigenvector (c0, c1); the lower one is (-c1, c0)
 template <typename R>
 __device__ __forceinline__ void canon2(const Geo2<R> &g, R &c0, R &c1)
 {
-    const R n = rsq(g.x0 * g.x0 + g.x1 * g.x1);
+    const R n = rsq(fma2(g.x0, g.x0, g.x1 * g.x1));
     c0 = g.x0 * n;
     c1 = g.x1 * n;
 }
@@ -83,13 +93,10 @@ __device__ __forceinline__ void coupling_coords(const N2Const<M, R> &C, const R 
     cc = C.c0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        dl += C.dlt[j] * q[j];
-        cc += C.cpl[j] * q[j];
+        dl = fma2(C.dlt[j], q[j], dl);
+        cc = fma2(C.cpl[j], q[j], cc);
     }
 }
-
-__device__ __forceinline__ float fma2(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fma2(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // c1 + x (c2 + x (c3 + x c4)): phi(x) = x times this for value coefficients,
 // phi'(x) itself for slope coefficients
@@ -133,8 +140,8 @@ __device__ __forceinline__ Geo2<float> resolve64(const double *__restrict__ c64,
     double dl = c64[0], cc = c64[1];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        dl += c64[2 + j] * (double)q[j];
-        cc += c64[2 + M + j] * (double)q[j];
+        dl = fma2(c64[2 + j], (double)q[j], dl);
+        cc = fma2(c64[2 + M + j], (double)q[j], cc);
     }
     Geo2<double> d;
     geo2<double>(dl, cc, d);
@@ -157,6 +164,9 @@ __device__ __forceinline__ Geo2<float> resolve64_poly(const double *__restrict__
     return Geo2<float>{(float)d.dl, (float)d.cc, (float)d.r, (float)d.rinv, (float)d.x0, (float)d.x1};
 }
 
+// Geometry at q.  binary32: a gap 2r below the model threshold is re-solved
+// in binary64 (a rare, divergent branch); an exact degeneracy can only
+// occur there, so it is checked there.  binary64: checked at every point.
 template <int M, typename R, bool POLY>
 __device__ __forceinline__ void geo_at(const N2Const<M, R> &C, const N2Extra<M, R, POLY> &Q, const R (&q)[M],
                                        Geo2<R> &g, uint32_t &flag)
@@ -174,10 +184,13 @@ __device__ __forceinline__ void geo_at(const N2Const<M, R> &C, const N2Extra<M, 
             else
                 g = resolve64<M>(C.c64, q);
             flag |= kFlagResolved;
+            if (!(R(2) * g.r > R(0)))
+                flag |= kFlagDegenerate;
         }
+    } else {
+        if (!(R(2) * g.r > R(2.2250738585072014e-308)))
+            flag |= kFlagDegenerate;
     }
-    if (!(R(2) * g.r > R(2.2250738585072014e-308)))
-        flag |= kFlagDegenerate;
 }
 
 // One output bin of the workgroup's tile, reduced into dst (tile_values(2)
@@ -346,53 +359,155 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
 
 // ---------------------------------------------------------------- propagation
 
-// Element-independent part of the Hellmann-Feynman force at the current
-// point: G_j = dl dlt_j + cc cpl_j, so that dE_{0,1}/dq_j = kbar_j -+ G_j/r.
-template <int M, typename R>
-__device__ __forceinline__ void force_terms(const N2Const<M, R> &C, const Geo2<R> &g, R (&G)[M])
+// One walker between steps, in registers.  G_j = dl dlt_j + cc cpl_j (or,
+// with higher powers, dl phi^d'_j + cc phi^c'_j) is the element-independent
+// part of the Hellmann-Feynman force at the current point, so that
+// dE_{0,1}/dq_j = kbar_j -+ G_j/r; hr = (dt/2)/r and kx = s0 s1/(2 r^2) are
+// kept with it for the two kicks and the next coupling.
+template <int M, typename R, bool POLY>
+struct WalkerN2 {
+    static constexpr int MP = POLY ? M : 1;
+    R q[M], p[M];
+    Geo2<R> g;
+    R G[M];
+    R SD[MP], SC[MP], SB[MP];  // polynomial slopes at the current point (POLY)
+    R hr, kx, hsig, s1;
+    double w, phase, r_old;
+    int a, b;
+    uint32_t flag;
+};
+
+// geometry, force terms and the per-point factors at the walker's q
+template <int M, typename R, bool POLY>
+__device__ __forceinline__ void point_n2(const N2Const<M, R> &C, const N2Extra<M, R, POLY> &Q, WalkerN2<M, R, POLY> &k)
 {
+    geo_at<M, R, POLY>(C, Q, k.q, k.g, k.flag);
+    if constexpr (POLY) {
+        poly_slopes<M, R>(Q, k.q, k.SD, k.SC, k.SB);
 #pragma unroll
-    for (int j = 0; j < M; ++j)
-        G[j] = g.dl * C.dlt[j] + g.cc * C.cpl[j];
+        for (int j = 0; j < M; ++j)
+            k.G[j] = fma2(k.g.dl, k.SD[j], k.g.cc * k.SC[j]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            k.G[j] = fma2(k.g.dl, C.dlt[j], k.g.cc * C.cpl[j]);
+    }
+    k.hr = C.hdt * k.g.rinv;
+    k.kx = k.hsig * (k.g.rinv * k.g.rinv);
 }
 
-// the same for a model with higher powers: G_j = dl phi^d'_j + cc phi^c'_j
-template <int M, typename R>
-__device__ __forceinline__ void poly_force_terms(const Geo2<R> &g, const R (&SD)[M], const R (&SC)[M], R (&G)[M])
+// p += (dt/2) * mean force of element (a,b), h = (a + b - 1) (dt/2)/r:
+// (dt/2)(F_a + F_b)/2 = -hk q - hb - h G  (hb_j = (dt/2) phi^b'_j with
+// higher powers)
+template <int M, typename R, bool POLY>
+__device__ __forceinline__ void kick_n2(const N2Const<M, R> &C, WalkerN2<M, R, POLY> &k, R h)
 {
 #pragma unroll
-    for (int j = 0; j < M; ++j)
-        G[j] = fma2(g.dl, SD[j], g.cc * SC[j]);
+    for (int j = 0; j < M; ++j) {
+        R t;
+        if constexpr (POLY)
+            t = fma2(-C.hdt, k.SB[j], k.p[j]);
+        else
+            t = k.p[j] - C.hb[j];
+        k.p[j] = fma2(-h, k.G[j], fma2(-C.hk[j], k.q[j], t));
+    }
 }
 
-// p += (dt/2) * mean force of element (a,b), lam = a + b - 1:
-// (dt/2)(F_a + F_b)/2 = -hk q - hb - (dt/2) lam G/r
-template <int M, typename R>
-__device__ __forceinline__ void mean_force_kick(const N2Const<M, R> &C, const R (&G)[M], R h, const R (&q)[M],
-                                                R (&p)[M])
+// One step n -> n+1 of one walker; word is its Philox output for step n.
+template <int M, typename R, int SCHEME, bool POLY>
+__device__ __forceinline__ void step_n2(const N2Const<M, R> &C, const N2Extra<M, R, POLY> &Q, WalkerN2<M, R, POLY> &k,
+                                        uint32_t word)
 {
-#pragma unroll
-    for (int j = 0; j < M; ++j)
-        p[j] = (p[j] - C.hb[j]) - C.hk[j] * q[j] - h * G[j];
-}
+    R u;
+    if constexpr (sizeof(R) == 4) u = u24f(word); else u = u24d(word);
 
-// the same with hb_j = (dt/2) phi^b'_j(q_j) (models with higher powers)
-template <int M, typename R>
-__device__ __forceinline__ void poly_mean_force_kick(const N2Const<M, R> &C, const R (&SB)[M], const R (&G)[M], R h,
-                                                     const R (&q)[M], R (&p)[M])
-{
+    // 1. Monte Carlo move between elements at (q_n, p_n).
+    // dt v.d_01 = s0 s1 (dl c_v - cc dl_v) / (2 r^2); the two candidates
+    // (1-a, b) and (a, 1-b) carry f0 = +-x, f1 = +-x.
+    R dlv, cv;
+    if constexpr (POLY) {
+        const R v0 = k.p[0] * C.dtm[0];
+        dlv = v0 * k.SD[0];
+        cv = v0 * k.SC[0];
+#pragma unroll
+        for (int j = 1; j < M; ++j) {
+            const R vj = k.p[j] * C.dtm[j];
+            dlv = fma2(vj, k.SD[j], dlv);
+            cv = fma2(vj, k.SC[j], cv);
+        }
+    } else {
+        dlv = k.p[0] * C.vdl[0];
+        cv = k.p[0] * C.vcp[0];
+#pragma unroll
+        for (int j = 1; j < M; ++j) {
+            dlv = fma2(k.p[j], C.vdl[j], dlv);
+            cv = fma2(k.p[j], C.vcp[j], cv);
+        }
+    }
+    const R x = fma2(k.g.dl, cv, -(k.g.cc * dlv)) * k.kx;
+    const R ax = __builtin_fabs(x);
+    const R S = ax + ax;
+    const bool xpos = x > R(0);
+    int pick;     // -1 stay, 0 -> (1-a, b), 1 -> (a, 1-b)
+    double mul;   // weight factor (normalized rule) or divisor (linear rule, staying)
+    if (SCHEME == QCL_TRANS_LINEAR && S < R(1)) {
+        pick = (u < ax) ? 0 : ((u < S) ? 1 : -1);
+        mul = (double)(R(1) - S);
+    } else {
+        if (SCHEME == QCL_TRANS_LINEAR)
+            k.flag |= kFlagFallback;
+        const R one_s = R(1) + S;
+        const R t = u * one_s;
+        pick = (t < R(1)) ? -1 : ((t < R(1) + ax) ? 0 : 1);
+        mul = (double)one_s;
+    }
+    // sign of the chosen candidate's factor: f0 = (a ? -x : x), f1 = (b ? -x : x)
+    const bool fpos = (pick == 0) ? (xpos != (k.a != 0)) : (xpos != (k.b != 0));
+    if (SCHEME == QCL_TRANS_LINEAR && S < R(1)) {
+        if (pick < 0) k.w = k.w / mul;
+        else k.w = fpos ? k.w : -k.w;
+    } else {
+        k.w = k.w * mul;
+        k.w = (pick < 0 || fpos) ? k.w : -k.w;
+    }
+    k.a = (pick == 0) ? 1 - k.a : k.a;
+    k.b = (pick == 1) ? 1 - k.b : k.b;
+
+    // 2. velocity Verlet on the mean force of the current element
+    const R lam = R(k.a + k.b - 1);
+    const R xo0 = k.g.x0, xo1 = k.g.x1;
+    kick_n2<M, R, POLY>(C, k, lam * k.hr);
 #pragma unroll
     for (int j = 0; j < M; ++j)
-        p[j] = fma2(-C.hdt, SB[j], p[j]) - C.hk[j] * q[j] - h * G[j];
+        k.q[j] = fma2(C.dtm[j], k.p[j], k.q[j]);
+    point_n2<M, R, POLY>(C, Q, k);
+    k.s1 = (fma2(xo0, k.g.x0, xo1 * k.g.x1) < R(0)) ? -k.s1 : k.s1;  // frame continuity
+    kick_n2<M, R, POLY>(C, k, lam * k.hr);
+
+    // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar = 2 (a - b) r / hbar
+    const double r_new = (double)k.g.r;
+    k.phase = fma2((double)(k.a - k.b), C.dt_hbar * (k.r_old + r_new), k.phase);
+    k.r_old = r_new;
 }
 
 // All steps of one tile of kBlock walkers (the whole workgroup calls it).
+// The steps run four at a time, aligned to the Philox blocks (one block of
+// four words per four steps), so that each copy of the step reads its word
+// directly; steps before the first aligned step and after the last whole
+// block run one at a time with the word selected at run time.  Every copy
+// performs the same operations (no contraction), so the bits do not depend
+// on the copy.  Bins fall between stretches.
 template <int M, typename R, int SCHEME, bool POLY>
-__device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const N2Extra<M, R, POLY> &Q,
+__device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C_in, const N2Extra<M, R, POLY> &Q,
                                                   const PropArgs &P, const EnsDev<R> &E,
                                                   double *__restrict__ partials, int64_t tile, BinLds &lds,
                                                   int &parity)
 {
+    // dlt0 and c0 start the two coupling coordinates at every point; held in
+    // vector registers (the empty asm pins them there), the first fused
+    // multiply-add of each needs no copy of a second scalar operand
+    N2Const<M, R> C = C_in;
+    asm volatile("" : "+v"(C.dlt0), "+v"(C.c0));
     const int64_t i = tile * kBlock + threadIdx.x;
     const bool live = i < E.n_traj;
     const int64_t li = live ? i : E.n_traj - 1;  // idle lanes shadow a valid walker
@@ -400,158 +515,98 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C, const 
     const uint64_t gid = (uint64_t)(E.traj_offset + li);
     const uint32_t g_lo = (uint32_t)gid, g_hi = (uint32_t)(gid >> 32);
 
-    R q[M], p[M];
+    WalkerN2<M, R, POLY> k;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        q[j] = E.q[j * ld + li];
-        p[j] = E.p[j * ld + li];
+        k.q[j] = E.q[j * ld + li];
+        k.p[j] = E.p[j * ld + li];
     }
     const R p00 = E.u[0 * ld + li], p01 = E.u[1 * ld + li], p10 = E.u[2 * ld + li], p11 = E.u[3 * ld + li];
-    double w = E.w[li];
-    double phase = E.phase[li];
-    int a = E.a[li];
-    int b = E.b[li];
-    uint32_t flag = 0;
-
-    Geo2<R> g;
-    geo_at<M, R, POLY>(C, Q, q, g, flag);
+    k.w = E.w[li];
+    k.phase = E.phase[li];
+    k.a = E.a[li];
+    k.b = E.b[li];
+    k.flag = 0;
+    k.hsig = R(0.5);
+    point_n2<M, R, POLY>(C, Q, k);
     // column signs of the stored frame relative to the canonical one; the
     // product s0 s1 is invariant along the walker, s1 is tracked
-    const R s0_in = (p00 * (-g.x1) + p10 * g.x0) < R(0) ? R(-1) : R(1);
-    R s1 = (p01 * g.x0 + p11 * g.x1) < R(0) ? R(-1) : R(1);
-    const R sig = s0_in * s1;
-    R G[M];
-    R SD[M], SC[M], SB[M];  // polynomial slopes at the current point (POLY)
-    if constexpr (POLY) {
-        poly_slopes<M, R>(Q, q, SD, SC, SB);
-        poly_force_terms<M, R>(g, SD, SC, G);
-    } else {
-        force_terms<M, R>(C, g, G);
-    }
-    double r_old = (double)g.r;
+    const R s0_in = fma2(p00, -k.g.x1, p10 * k.g.x0) < R(0) ? R(-1) : R(1);
+    k.s1 = fma2(p01, k.g.x0, p11 * k.g.x1) < R(0) ? R(-1) : R(1);
+    const R sig = s0_in * k.s1;
+    k.hsig = R(0.5) * sig;
+    k.kx = k.hsig * (k.g.rinv * k.g.rinv);
+    k.r_old = (double)k.g.r;
 
     int64_t step = P.step0;
     const int64_t end = P.step0 + P.n_steps;
+    int64_t obin = step / P.cadence + 1;  // next bin and its global step
+    int64_t next_bin = obin * P.cadence;
     U4 rnd{0, 0, 0, 0};
     if (step & 3)
         rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
     while (step < end) {
-        const int64_t next_bin = (step / P.cadence + 1) * P.cadence;
         const int64_t stop = next_bin < end ? next_bin : end;
-        for (; step < stop; ++step) {
+        int n = (int)(stop - step);
+        for (; n > 0 && (step & 3); --n, ++step)
+            step_n2<M, R, SCHEME, POLY>(C, Q, k, pick_word(rnd, (uint32_t)(step & 3)));
+        for (; n >= 4; n -= 4, step += 4) {
+            rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
+            step_n2<M, R, SCHEME, POLY>(C, Q, k, rnd.x);
+            step_n2<M, R, SCHEME, POLY>(C, Q, k, rnd.y);
+            step_n2<M, R, SCHEME, POLY>(C, Q, k, rnd.z);
+            step_n2<M, R, SCHEME, POLY>(C, Q, k, rnd.w);
+        }
+        for (; n > 0; --n, ++step) {
             if ((step & 3) == 0)
                 rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
-            const uint32_t word = pick_word(rnd, (uint32_t)(step & 3));
-            R u;
-            if constexpr (sizeof(R) == 4) u = u24f(word); else u = u24d(word);
-
-            // 1. Monte Carlo move between elements at (q_n, p_n).
-            // dt v.d_01 = s0 s1 (dl c_v - cc dl_v) / (2 r^2); the two
-            // candidates (1-a, b) and (a, 1-b) carry f0 = +-x, f1 = +-x.
-            R dlv = R(0), cv = R(0);
-            if constexpr (POLY) {
-#pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    const R vj = p[j] * C.dtm[j];
-                    dlv = fma2(vj, SD[j], dlv);
-                    cv = fma2(vj, SC[j], cv);
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    dlv += p[j] * C.vdl[j];
-                    cv += p[j] * C.vcp[j];
-                }
-            }
-            const R x = sig * (g.dl * cv - g.cc * dlv) * (R(0.5) * (g.rinv * g.rinv));
-            const R ax = x < R(0) ? -x : x;
-            const R S = ax + ax;
-            const bool xpos = x > R(0);
-            int pick;     // -1 stay, 0 -> (1-a, b), 1 -> (a, 1-b)
-            double mul;   // weight factor
-            if (SCHEME == QCL_TRANS_LINEAR && S < R(1)) {
-                pick = (u < ax) ? 0 : ((u < S) ? 1 : -1);
-                mul = (double)(R(1) / (R(1) - S));
-            } else {
-                if (SCHEME == QCL_TRANS_LINEAR)
-                    flag |= kFlagFallback;
-                const R t = u * (R(1) + S);
-                pick = (t < R(1)) ? -1 : ((t < R(1) + ax) ? 0 : 1);
-                mul = (double)(R(1) + S);
-            }
-            // sign of the chosen candidate's factor: f0 = (a ? -x : x), f1 = (b ? -x : x)
-            const bool fpos = (pick == 0) ? (xpos != (a != 0)) : (xpos != (b != 0));
-            if (SCHEME == QCL_TRANS_LINEAR && S < R(1)) {
-                if (pick < 0) w = w / (double)(R(1) - S);
-                else w = fpos ? w : -w;
-            } else {
-                w = w * mul;
-                w = (pick < 0 || fpos) ? w : -w;
-            }
-            a = (pick == 0) ? 1 - a : a;
-            b = (pick == 1) ? 1 - b : b;
-
-            // 2. velocity Verlet on the mean force of the current element
-            const R lam = R(a + b - 1);
-            const R xo0 = g.x0, xo1 = g.x1;
-            if constexpr (POLY)
-                poly_mean_force_kick<M, R>(C, SB, G, lam * (C.hdt * g.rinv), q, p);
-            else
-                mean_force_kick<M, R>(C, G, lam * (C.hdt * g.rinv), q, p);
-#pragma unroll
-            for (int j = 0; j < M; ++j)
-                q[j] += C.dtm[j] * p[j];
-            geo_at<M, R, POLY>(C, Q, q, g, flag);
-            s1 = (xo0 * g.x0 + xo1 * g.x1 < R(0)) ? -s1 : s1;  // frame continuity
-            if constexpr (POLY) {
-                poly_slopes<M, R>(Q, q, SD, SC, SB);
-                poly_force_terms<M, R>(g, SD, SC, G);
-                poly_mean_force_kick<M, R>(C, SB, G, lam * (C.hdt * g.rinv), q, p);
-            } else {
-                force_terms<M, R>(C, g, G);
-                mean_force_kick<M, R>(C, G, lam * (C.hdt * g.rinv), q, p);
-            }
-
-            // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar = 2 (a - b) r / hbar
-            const double r_new = (double)g.r;
-            phase = fma((double)(a - b), C.dt_hbar * (r_old + r_new), phase);
-            r_old = r_new;
+            step_n2<M, R, SCHEME, POLY>(C, Q, k, pick_word(rnd, (uint32_t)(step & 3)));
         }
         // 4. output bin at global step next_bin
-        if (step == next_bin && next_bin / P.cadence < P.n_out) {
-            R c0, c1;
-            canon2<R>(g, c0, c1);
-            bin_n2<R>(lds, parity, live, a, b, w, phase, c0, c1, sig,
-                      partials + (tile * P.n_out + next_bin / P.cadence) * tile_values(2));
+        if (step == next_bin) {
+            if (obin < P.n_out) {
+                R c0, c1;
+                canon2<R>(k.g, c0, c1);
+                bin_n2<R>(lds, parity, live, k.a, k.b, k.w, k.phase, c0, c1, sig,
+                          partials + (tile * P.n_out + obin) * tile_values(2));
+            }
+            ++obin;
+            next_bin += P.cadence;
         }
     }
-    if (!(isfinite(w) && isfinite(phase)))
-        flag |= kFlagNonfinite;
+    if (!(isfinite(k.w) && isfinite(k.phase)))
+        k.flag |= kFlagNonfinite;
 
     if (live) {
         R c0, c1;
-        canon2<R>(g, c0, c1);
-        const R s0 = sig * s1;
+        canon2<R>(k.g, c0, c1);
+        const R s0 = sig * k.s1;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            E.q[j * ld + i] = q[j];
-            E.p[j * ld + i] = p[j];
+            E.q[j * ld + i] = k.q[j];
+            E.p[j * ld + i] = k.p[j];
         }
         E.u[0 * ld + i] = -s0 * c1;
-        E.u[1 * ld + i] = s1 * c0;
+        E.u[1 * ld + i] = k.s1 * c0;
         E.u[2 * ld + i] = s0 * c0;
-        E.u[3 * ld + i] = s1 * c1;
-        E.w[i] = w;
-        E.phase[i] = phase;
-        E.a[i] = (uint8_t)a;
-        E.b[i] = (uint8_t)b;
+        E.u[3 * ld + i] = k.s1 * c1;
+        E.w[i] = k.w;
+        E.phase[i] = k.phase;
+        E.a[i] = (uint8_t)k.a;
+        E.b[i] = (uint8_t)k.b;
         if (E.flags)
-            E.flags[i] |= flag;
+            E.flags[i] |= k.flag;
     }
 }
 
+// Resident workgroups per CU the propagation kernels are built for: five
+// for the binary32 linear models up to 4 modes (the step loop and the bins
+// fit 96 registers, five waves per SIMD), no constraint otherwise.
+template <int M, typename R, bool POLY>
+constexpr int kN2Occupancy = (sizeof(R) == 4 && !POLY && M <= 4) ? 5 : 1;
+
 template <int M, typename R, int SCHEME, bool POLY>
-__global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, N2Extra<M, R, POLY> Q, PropArgs P,
+__global__ __launch_bounds__(kBlock, (kN2Occupancy<M, R, POLY>)) void propagate_n2_kernel(N2Const<M, R> C, N2Extra<M, R, POLY> Q, PropArgs P,
                                                               EnsDev<R> E, double *__restrict__ partials)
 {
     __shared__ BinLds lds;
@@ -563,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void propagate_n2_kernel(N2Const<M, R> C, N
 // instances of one kernel class; items are taken from an atomic counter
 // (descriptors are sorted by decreasing work per tile).
 template <int M, typename R, int SCHEME, bool POLY>
-__global__ __launch_bounds__(kBlock) void batch_n2_kernel(const BatchItemN2<M, R, POLY> *__restrict__ items,
+__global__ __launch_bounds__(kBlock, (kN2Occupancy<M, R, POLY>)) void batch_n2_kernel(const BatchItemN2<M, R, POLY> *__restrict__ items,
                                                           int32_t n_items, int64_t total_tiles,
                                                           unsigned long long *counter)
 {

@@ -36,13 +36,15 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
 
 // (2 floor(x / 2^9) + 1) / 2^24: a uniform in (0,1) that is exact in both
 // binary32 and binary64, so both precisions see the same threshold value.
+// Formed as floor(x / 2^9) 2^-23 + 2^-24 in one fused multiply-add, exact
+// because the result has at most 24 significant bits.
 __device__ __forceinline__ float u24f(uint32_t x)
 {
-    return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
+    return __builtin_fmaf((float)(x >> 9), 0x1p-23f, 0x1p-24f);
 }
 __device__ __forceinline__ double u24d(uint32_t x)
 {
-    return (double)(2u * (x >> 9) + 1u) * 0x1p-24;
+    return __builtin_fma((double)(x >> 9), 0x1p-23, 0x1p-24);
 }
 
 // 52-bit uniform in (0,1): k = hi * 2^20 + floor(lo / 2^12), (2k + 1) / 2^53.

@@ -41,3 +41,23 @@ def test_oracle_beside_the_other_legs():
     assert set(legs) == {"pyrazine_bilinear", "resample"}
     for v in legs.values():
         assert v["value"] > 0 and v["cores"] >= 1 and v["sample"]
+
+
+def test_oracle_accuracy_against_the_stored_oracle_run():
+    """The bench's accuracy block compares a full-size result with the
+    oracle's stored run: the stored result itself has no error, a result
+    off by 2e-3 in one bin's population is reported as such."""
+    import json
+    import numpy as np
+    import bench
+    import workloads as W
+    wl = W.pyrazine_ci()
+    ref = np.array(json.load(open(bench.GOLDEN))["out"])
+    acc = bench.oracle_accuracy(ref, wl, wl.run.n_traj, "fp32")
+    assert acc["max_abs_upper_population_diff"] == 0.0 and acc["bins_within_1e-3"] == acc["bins"] == 101
+    off = ref.copy()
+    off[3, 0, 1, 1, 0] += 2e-3
+    acc = bench.oracle_accuracy(off, wl, wl.run.n_traj, "fp32")
+    assert abs(acc["max_abs_upper_population_diff"] - 2e-3) < 1e-12 and acc["bins_within_1e-3"] == 100
+    assert bench.oracle_accuracy(ref, wl, 12345, "fp32") is None
+    assert abs(bench.flops_per_traj_step(2, 3, bench.coupling_slots(wl.model)) - 124.0) < 1e-9
