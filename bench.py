@@ -451,6 +451,46 @@ def batched_leg(P, torch, n_instances=256):
                 1 for v in table.choice.values() if v != 0), "seconds": tune_s}}, table
 
 
+GENERAL_CLASSES = ((4, 64), (4, 32), (3, 64))
+
+
+def general_leg(P, torch, n_traj=1 << 20, n_steps=200):
+    """The general-N kernel classes that dominate the batched workload, each
+    on one of its instances run alone (binary32 at the tuner's register
+    budget, and binary64): walker-steps/s of one qcl_propagate call."""
+    import workloads as W
+    from paper_2608_14544_amd.tune import TuningTable, padded_modes
+    wls = W.batched_instances(256)
+    table = TuningTable()
+    rows = []
+    for n, mp in GENERAL_CLASSES:
+        cands = [wl for wl in wls if wl.model.n_states == n and padded_modes(wl.model.n_modes) == mp]
+        wl = max(cands, key=lambda w: w.model.n_modes)
+        r = wl.run
+        model = P.Model(wl.model)
+        row = {"class": f"N={n} padded modes {mp}", "instance": wl.model.name, "n_modes": wl.model.n_modes,
+               "n_traj": n_traj, "n_steps": n_steps}
+        for prec in ("fp32", "fp64"):
+            occ = table.tune(wl, prec, model=model) if prec == "fp32" else 0
+            ens = P.Ensemble(model, n_traj, prec, zero=False)
+            part = P.Partials(model, n_traj, n_steps // r.cadence + 1)
+            P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
+            P.qcl_propagate(model, ens, r.dt, r.cadence, r.cadence, r.seed, part, occupancy=occ)  # warm-up
+            torch.cuda.synchronize()
+            s = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            P.qcl_propagate(model, ens, r.dt, n_steps - r.cadence, r.cadence, r.seed, part, 0, s, occupancy=occ)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            row[prec] = {"ms": ms, "value": n_traj * (n_steps - r.cadence) / (ms / 1e3), "occupancy": occ}
+            del ens, part
+            torch.cuda.empty_cache()
+        rows.append(row)
+    return rows
+
+
 def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=None, quantum_work=2e8):
     """The served stream through the continuous-batching server.  Default:
     the sub-saturation variant (walkers log-uniform over 1e5-1e7); ``full``
@@ -547,7 +587,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling,convergence,poly,many_states,"
-                    "resample",
+                    "resample,general",
                     help="comma-separated subset of the default legs")
     ap.add_argument("--resample-replicas", type=int, default=64,
                     help="replicas of the resampling study (0: time the resampling only)")
@@ -673,6 +713,10 @@ def main():
                                     quantum_work=args.served_quantum_work)
         print(f"[bench] served: {line['served']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
+    if "general" in legs:
+        line["general"] = general_leg(P, torch)
+        print("[bench] general: " + "; ".join(f"{x['class']} fp32 {x['fp32']['value']:.3e}, fp64 {x['fp64']['value']:.3e}"
+                                              for x in line["general"]), file=sys.stderr, flush=True)
     if "scaling" in legs:
         line["scaling_sweep"] = scaling_leg(P, torch, wl)
         print(f"[bench] scaling sweep: " + ", ".join(f"{x['prec']} {x['n_traj']:.0e}: {x['ms']:.1f} ms"
