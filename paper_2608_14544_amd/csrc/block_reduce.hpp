@@ -78,6 +78,24 @@ __device__ __forceinline__ double add_swap32(double a, double b)
     return mkd(l[0], h[0]) + mkd(l[1], h[1]);
 }
 
+// x(lane) + x(lane ^ 16): v_permlane16_swap of x with itself leaves rows
+// (r0, r0, r2, r2) in the first result and (r1, r1, r3, r3) in the second,
+// so every lane adds the even row's value to the odd row's, in that order
+__device__ __forceinline__ double add_xor16(double x)
+{
+    const auto l = __builtin_amdgcn_permlane16_swap(lo32(x), lo32(x), false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi32(x), hi32(x), false, false);
+    return mkd(l[0], h[0]) + mkd(l[1], h[1]);
+}
+
+// x(lane) + x(lane ^ 32), the same with the two halves of the wavefront
+__device__ __forceinline__ double add_xor32(double x)
+{
+    const auto l = __builtin_amdgcn_permlane32_swap(lo32(x), lo32(x), false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi32(x), hi32(x), false, false);
+    return mkd(l[0], h[0]) + mkd(l[1], h[1]);
+}
+
 }  // namespace rdetail
 
 // Reduction state of one bin (or one block of up to kFlushValues values of
@@ -161,6 +179,78 @@ struct BinReducer {
             L.wsum[k][wave][(lane >> 4) * kPassValues + (lane & 7)] = t;
         __syncthreads();
         const int i = threadIdx.x;
+        if (i < n)
+            dst[i] = (L.wsum[k][0][i] + L.wsum[k][1][i]) + (L.wsum[k][2][i] + L.wsum[k][3][i]);
+        if (count_dst && i == kFlushValues)
+            *count_dst = (double)((L.excluded[k][0] + L.excluded[k][1]) + (L.excluded[k][2] + L.excluded[k][3]));
+        npass = 0;
+        parity ^= 1;
+    }
+};
+
+
+// The same reduction with each pass combined across lanes on its own (the
+// butterfly x + x(l ^ 8), + x(l ^ 16), + x(l ^ 32) on every lane) and its 8
+// wavefront totals written to LDS at once: the same additions in the same
+// tree as BinReducer, so the sums are bitwise equal, at more crossbar moves
+// per pass but with no pass sums held in registers until the flush.  The
+// general kernels, whose step code already holds many registers, use this
+// form.
+struct BinReducerPerPass {
+    BinLds &L;
+    int &parity;  // the workgroup's flush counter (kept by the caller across bins)
+    int lane, wave;
+    double *row;
+    int npass = 0;
+
+    __device__ __forceinline__ BinReducerPerPass(BinLds &lds, int &flush_parity)
+        : L(lds), parity(flush_parity), lane(threadIdx.x & 63), wave(threadIdx.x >> 6)
+    {
+        row = &L.stage[wave][lane * kStageStride];
+    }
+
+    __device__ __forceinline__ void zero_row()
+    {
+#pragma unroll
+        for (int j = 0; j < kPassValues; ++j)
+            row[j] = 0.0;
+    }
+
+    __device__ __forceinline__ void put(int col, double x) { row[col] = x; }
+
+    // the wavefront totals of the 8 staged values, into the LDS totals
+    __device__ __forceinline__ void pass()
+    {
+        using namespace rdetail;
+        __builtin_amdgcn_wave_barrier();
+        const double *c = &L.stage[wave][(lane >> 3) * 8 * kStageStride + (lane & 7)];
+        const double s01 = c[0 * kStageStride] + c[1 * kStageStride];
+        const double s23 = c[2 * kStageStride] + c[3 * kStageStride];
+        const double s45 = c[4 * kStageStride] + c[5 * kStageStride];
+        const double s67 = c[6 * kStageStride] + c[7 * kStageStride];
+        double s = (s01 + s23) + (s45 + s67);
+        s = add_xor8(s);
+        s = add_xor16(s);
+        s = add_xor32(s);
+        if (lane < kPassValues)
+            L.wsum[parity & 1][wave][npass * kPassValues + lane] = s;
+        __builtin_amdgcn_wave_barrier();
+        ++npass;
+    }
+
+    __device__ __forceinline__ void count_excluded(bool excluded)
+    {
+        const unsigned long long m = __ballot(excluded);
+        if (lane == 0)
+            L.excluded[parity & 1][wave] = (uint32_t)__popcll(m);
+    }
+
+    // as BinReducer::flush
+    __device__ __forceinline__ void flush(double *__restrict__ dst, int n, double *__restrict__ count_dst)
+    {
+        __syncthreads();
+        const int i = threadIdx.x;
+        const int k = parity & 1;
         if (i < n)
             dst[i] = (L.wsum[k][0][i] + L.wsum[k][1][i]) + (L.wsum[k][2][i] + L.wsum[k][3][i]);
         if (count_dst && i == kFlushValues)
