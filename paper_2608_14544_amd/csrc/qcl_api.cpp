@@ -672,6 +672,13 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, cons
                     kmat[(size_t)j * T + s] = m->k[(size_t)j * n * n + k * n + l];
         m->rank = factor_couplings(M, T, kmat, basis, coef);
         m->rank_pad = qcl::rank_bucket(m->rank, n);
+        if (m->rank_pad == 1) {  // exact zeros off the diagonal: the kernels skip those products
+            bool diag = true;
+            for (int k = 0, sl = 0; k < n; ++k)
+                for (int l = k; l < n; ++l, ++sl)
+                    diag = diag && (k == l || m->rank == 0 || basis[sl] == 0.0);
+            m->basis_diag = diag;
+        }
         const int RB = m->rank_pad;
         // every direction kept: the slot basis (unit matrices), coefficients
         // the slot values themselves; the kernels skip its contractions

@@ -75,6 +75,7 @@ struct GenConst {
     double dt_hbar;
     R gap_thr;  // binary32 path: gaps below this are re-solved in binary64
     R rot_eps;  // Jacobi: rotate while |a_pq| > rot_eps * ||A||_F
+    int32_t basis_diag;  // rank one: the one coupling direction is diagonal
 };
 
 // squared mode combinations of a bilinear model: the kernels are built for
@@ -190,6 +191,7 @@ struct qcl_model_s {
     size_t gen32_byte_offset = 0;  // byte offset of the general-N binary32 constants
     int32_t rank = 0;           // rank of the mode couplings (general-N factorisation)
     int32_t rank_pad = 1;       // rank bucket RB the general kernels are specialised on
+    int32_t basis_diag = 0;     // rank one: the coupling direction has no off-diagonal slots
     int32_t degree = 1;         // highest power of q_j in V(q) (> 1: kernels_poly{N}.hip)
     std::vector<double> poly;   // [M][degree-1][N][N] higher-power matrices A_jk (k >= 2)
     int32_t n_pairs = 0;        // bilinear terms (> 0: kernels_bil{,h,w}{N}.hip)
