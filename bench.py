@@ -51,7 +51,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X published dense vector pea
 # HBM bytes of one propagate launch, from the committed rocprofv3 counter
 # summary; valid only while the kernel's sources are the ones it measured.
 HBM_PROFILE = os.path.join(ROOT, "profiles", "propagate_n2_pyrazine_1e7_hbm_counters.md")
-KERNEL_SOURCES = ["kernels_n2.hip", "block_reduce.hpp", "phase_math.hpp", "philox.hpp", "qcl_internal.hpp"]
+KERNEL_SOURCES = ["kernels_n2.hip", "block_reduce.hpp", "phase_math.hpp", "philox.hpp", "qcl_internal.hpp",
+                  "qcl_device.hpp"]
 
 
 def kernel_sources_sha256() -> str:

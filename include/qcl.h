@@ -239,6 +239,56 @@ qcl_status qcl_create_model_bilinear(const qcl_model_desc *desc, const qcl_poly_
 /* Number of bilinear terms of a model (0 for NULL or none). */
 int32_t qcl_model_pairs(qcl_model model);
 
+/* A model with a supplied potential.  Eq. 1 holds for any potential
+ * V(R), and the paper's closing section (Sec. IV) names on-the-fly
+ * potentials, forces and couplings (molecular dynamics, QM/MM) as the next
+ * step; this entry point takes the diabatic potential matrix as device
+ * source code, compiled for the current device with the library's kernels
+ * when the model is built (hipRTC).  The Hamiltonian is
+ *   H = sum_j p_j^2 / (2 m_j) + V(q),
+ * V(q) a real symmetric N x N matrix holding every q-dependent term (the
+ * nuclear potential on its diagonal too).  The source defines three
+ * binary64 device functions, in the global namespace:
+ *
+ *   __device__ void qcl_potential(const double *q, double *V);
+ *       V[s], s = 0 .. N(N+1)/2 - 1: V_kl (k <= l) at q, row by row
+ *   __device__ void qcl_force(const double *q, const double *w, double *f);
+ *       f[j] = -sum_s w[s] dV_s/dq_j, j = 0 .. M-1
+ *   __device__ void qcl_coupling(const double *q, const double *v, double *K);
+ *       K[s] = sum_j v[j] dV_s/dq_j
+ *
+ * and may use QCL_N, QCL_M (integer constants) and qcl_param[i] (the
+ * given parameter values, compile-time constants).  The kernels call
+ * qcl_force with the slot weights of a walker's element (a, b), giving the
+ * mean force -[(U^T dV/dq_j U)_aa + (U^T dV/dq_j U)_bb] / 2, and
+ * qcl_coupling with v = p/m, giving D = U^T K U for the Monte Carlo move.
+ * The three must agree (f and K are contractions of the same gradient).
+ * The program is compiled without contraction of separate multiplies and
+ * adds (write fma() where a fused operation is wanted), so that a run split
+ * over calls reproduces the uninterrupted one bit for bit.
+ * desc supplies N (2..4), M (1..QCL_MAX_MODES_SOURCE), the masses, hbar and
+ * the frequencies omega of the harmonic reference that the Wigner initial
+ * state is drawn from (qcl_sample_initial); v0 and k are not read.  Such a
+ * model propagates binary64 ensembles only (UNSUPPORTED for binary32) and
+ * is not accepted in batches.  Errors: INVALID_ARG (as qcl_create_model
+ * for the sizes and the masses and frequencies; NULL source; n_params
+ * outside [0, QCL_MAX_PARAMS] or a non-finite parameter; a source that does
+ * not compile, with the compiler's log in qcl_last_error), DEVICE (no
+ * usable device, or the compiled code does not load). */
+#define QCL_MAX_MODES_SOURCE 32
+#define QCL_MAX_PARAMS 256
+typedef struct {
+    const char *source;    /* NUL-terminated device source (host) */
+    const double *params;  /* [n_params] host, or NULL when n_params is 0 */
+    int32_t n_params;
+    int32_t reserved;
+} qcl_source_desc;
+
+qcl_status qcl_create_model_source(const qcl_model_desc *desc, const qcl_source_desc *src, qcl_model *out);
+
+/* 1 when the model was built by qcl_create_model_source, else 0. */
+int32_t qcl_model_is_source(qcl_model model);
+
 /* Highest power of q_j in the model's potential: 1 for a linear-vibronic
  * model, 2..4 for one built by qcl_create_model_poly (at least 2 for one
  * built by qcl_create_model_bilinear), 0 for NULL. */

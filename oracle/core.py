@@ -46,7 +46,31 @@ class _Model(C.Structure):
                 ("mass", C.POINTER(C.c_double)), ("omega", C.POINTER(C.c_double)),
                 ("v0", C.POINTER(C.c_double)), ("k", C.POINTER(C.c_double)),
                 ("hbar", C.c_double), ("degree", C.c_int32), ("a", C.POINTER(C.c_double)),
-                ("n_pairs", C.c_int32), ("pairs", C.POINTER(C.c_int32)), ("bpair", C.POINTER(C.c_double))]
+                ("n_pairs", C.c_int32), ("pairs", C.POINTER(C.c_int32)), ("bpair", C.POINTER(C.c_double)),
+                ("user_v", C.c_void_p), ("user_dv", C.c_void_p), ("user_prm", C.POINTER(C.c_double))]
+
+
+_USER_DIR = os.path.join(_HERE, "_user")
+
+
+def user_library(c_source: str) -> C.CDLL:
+    """Compiles the C transcription of a supplied potential (functions
+    ``qcl_oracle_potential(q, prm, V)``, V the full N x N matrix, and
+    ``qcl_oracle_gradient(j, q, prm, G)``, G = dV/dq_j) with the oracle's
+    floating-point options, cached by the source's hash."""
+    import hashlib
+    h = hashlib.sha256(c_source.encode()).hexdigest()[:16]
+    os.makedirs(_USER_DIR, exist_ok=True)
+    so = os.path.join(_USER_DIR, f"potential_{h}.so")
+    if not os.path.exists(so):
+        src = os.path.join(_USER_DIR, f"potential_{h}.c")
+        with open(src, "w") as f:
+            f.write("#include <math.h>\n" + c_source)
+        tmp = so + f".{os.getpid()}.tmp"
+        subprocess.run(["gcc", "-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+                        src, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, so)
+    return C.CDLL(so)
 
 
 _dp = C.POINTER(C.c_double)
@@ -102,7 +126,8 @@ def _i(a: np.ndarray):
 
 
 class Model:
-    """Keeps the numpy buffers of a ``workloads.LVCModel`` alive for C."""
+    """Keeps the numpy buffers of a ``workloads.LVCModel`` (or
+    ``workloads.SourceModel``) alive for C."""
 
     def __init__(self, m):
         self.src = m
@@ -120,10 +145,19 @@ class Model:
         self.pairs = np.ascontiguousarray([[int(i), int(j)] for i, j, _ in bil] or np.zeros((0, 2)), np.int32)
         self.bpair = np.ascontiguousarray([np.asarray(B, np.float64) for _, _, B in bil]
                                           or np.zeros((0, self.n, self.n)), np.float64)
+        # a supplied potential: the model's C transcription, compiled here
+        c_src = getattr(m, "c_source", None)
+        self.user = user_library(c_src) if c_src else None
+        self.params = np.ascontiguousarray(np.append(np.asarray(getattr(m, "params", ()), np.float64), 0.0))
+        user_v = user_dv = prm = None
+        if self.user is not None:
+            user_v = C.cast(self.user.qcl_oracle_potential, C.c_void_p)
+            user_dv = C.cast(self.user.qcl_oracle_gradient, C.c_void_p)
+            prm = _d(self.params)
         self.c = _Model(self.n, self.M, _d(self.mass), _d(self.omega), _d(self.v0), _d(self.k),
                         float(m.hbar), self.degree, _d(self.a) if self.a is not None else None,
                         self.n_pairs, _i(self.pairs) if self.n_pairs else None,
-                        _d(self.bpair) if self.n_pairs else None)
+                        _d(self.bpair) if self.n_pairs else None, user_v, user_dv, prm)
 
     @property
     def ref(self):

@@ -64,6 +64,14 @@ typedef struct {
     int32_t n_pairs;      /* bilinear terms q_i q_j B_p, i != j (0: none) */
     const int32_t *pairs; /* [n_pairs][2]: the modes (i, j) of each term */
     const double *bpair;  /* [n_pairs][N][N]: B_p */
+    /* A supplied potential (the general form of Eq. 1): when user_v is set,
+     * V(q) and dV/dq_j come from these functions of (q, user_prm) and are
+     * the whole q-dependent Hamiltonian -- v0, k, the higher powers, the
+     * bilinear terms and the harmonic bath term m w^2 q^2 / 2 are not used
+     * (mass and omega still give the kinetic term and the Wigner widths). */
+    void (*user_v)(const double *q, const double *prm, double *V);           /* V [N][N] */
+    void (*user_dv)(int j, const double *q, const double *prm, double *Gj);  /* dV/dq_j [N][N] */
+    const double *user_prm;
 } or_model;
 
 /* ------------------------------------------------------------------ */
@@ -225,6 +233,10 @@ static double poly_entry(const or_model *m, int j, int k, int i)
 void or_potential(const or_model *m, const double *q, double *V)
 {
     int n = m->n_states, M = m->n_modes;
+    if (m->user_v) {
+        m->user_v(q, m->user_prm, V);
+        return;
+    }
     for (int i = 0; i < n * n; ++i) {
         double v = m->v0[i];
         for (int j = 0; j < M; ++j) {
@@ -247,6 +259,10 @@ void or_potential(const or_model *m, const double *q, double *V)
 static void mode_gradient(const or_model *m, int j, const double *q, double *Gj)
 {
     int n = m->n_states;
+    if (m->user_dv) {
+        m->user_dv(j, q, m->user_prm, Gj);
+        return;
+    }
     const double qj = q ? q[j] : 0.0;
     for (int i = 0; i < n * n; ++i) {
         double g = m->k[(size_t)j * n * n + i];
@@ -296,7 +312,8 @@ static void rotate_to_adiabatic(int n, const double *U, const double *Amat, doub
 }
 
 /* Mean classical force on element (a,b):
- * F_j = -m_j w_j^2 q_j - [ (U^T dV/dq_j U)_aa + (U^T dV/dq_j U)_bb ] / 2,
+ * F_j = -m_j w_j^2 q_j - [ (U^T dV/dq_j U)_aa + (U^T dV/dq_j U)_bb ] / 2
+ * (without the first term for a supplied potential, whose V holds it),
  * i.e. (F_a + F_b)/2 with Hellmann-Feynman F_alpha (Eq. 1, last term). */
 void or_mean_force(const or_model *m, const double *q, const double *U, int a, int b, double *F)
 {
@@ -305,8 +322,8 @@ void or_mean_force(const or_model *m, const double *q, const double *U, int a, i
     for (int j = 0; j < m->n_modes; ++j) {
         mode_gradient(m, j, q, Gj);
         rotate_to_adiabatic(n, U, Gj, G);
-        F[j] = -m->mass[j] * m->omega[j] * m->omega[j] * q[j]
-               - 0.5 * (G[a * n + a] + G[b * n + b]);
+        const double bath = m->user_v ? 0.0 : m->mass[j] * m->omega[j] * m->omega[j] * q[j];
+        F[j] = -bath - 0.5 * (G[a * n + a] + G[b * n + b]);
     }
 }
 

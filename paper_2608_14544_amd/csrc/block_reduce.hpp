@@ -25,9 +25,11 @@
 // gathered with a wavefront ballot and stored after the bin's values.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#endif
 
 namespace qcl {
 

@@ -19,7 +19,9 @@
 //                  carry binary32 phase factors.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 namespace qcl {
 

@@ -6,9 +6,11 @@
 // 32x32->64 product is one v_mad_u64_u32.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#endif
 
 namespace qcl {
 

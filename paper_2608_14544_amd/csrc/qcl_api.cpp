@@ -173,7 +173,8 @@ qcl_status check_ensemble(const qcl_model_s &m, const qcl_ensemble *e)
             !aligned256(e->phase) || !aligned256(e->a) || !aligned256(e->b) || !aligned256(e->flags))
             return fail(QCL_ERR_INVALID_ARG, "ensemble arrays must be 256-byte aligned");
     }
-    (void)m;
+    if (m.source && e->prec != QCL_FP64)
+        return fail(QCL_ERR_UNSUPPORTED, "a model with a supplied potential runs binary64 ensembles only");
     return QCL_OK;
 }
 
@@ -292,6 +293,8 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
         if (it.ens->n_traj == 0 || it.prop.n_steps == 0)
             continue;
         const qcl_model_s &m = *it.model;
+        if (m.source)
+            return fail(QCL_ERR_UNSUPPORTED, "item %d: a model with a supplied potential runs only in qcl_propagate", i);
         // general kernels are specialised on padded modes and rank bucket
         const int poly = m.degree > 1 ? 1 : 0;
         const int modes = m.fast2 ? m.m + 16 * poly
@@ -769,6 +772,62 @@ qcl_status create_model(const qcl_model_desc *d, const qcl_poly_desc *poly, cons
     return QCL_OK;
 }
 
+// A model with a supplied potential (qcl_create_model_source): the source
+// is compiled first (no device needed), then loaded on the current device.
+qcl_status create_model_source(const qcl_model_desc *d, const qcl_source_desc *src, qcl_model *out)
+{
+    if (!d || !src || !out)
+        return fail(QCL_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    const int n = d->n_states, M = d->n_modes;
+    if (n < 2 || n > 4)
+        return fail(QCL_ERR_INVALID_ARG, "n_states %d outside [2, 4] for a supplied potential", n);
+    if (M < 1 || M > QCL_MAX_MODES_SOURCE)
+        return fail(QCL_ERR_INVALID_ARG, "n_modes %d outside [1, %d] for a supplied potential", M,
+                    QCL_MAX_MODES_SOURCE);
+    if (!d->mass || !d->omega)
+        return fail(QCL_ERR_INVALID_ARG, "mass or omega is NULL");
+    if (!(d->hbar > 0.0) || !std::isfinite(d->hbar))
+        return fail(QCL_ERR_INVALID_ARG, "hbar must be finite and > 0");
+    if (!finite_all(d->mass, M) || !finite_all(d->omega, M))
+        return fail(QCL_ERR_INVALID_ARG, "non-finite model parameter");
+    for (int j = 0; j < M; ++j)
+        if (!(d->mass[j] > 0.0) || !(d->omega[j] > 0.0))
+            return fail(QCL_ERR_INVALID_ARG, "mass and omega must be > 0 (mode %d)", j);
+    if (!src->source)
+        return fail(QCL_ERR_INVALID_ARG, "source is NULL");
+    if (src->n_params < 0 || src->n_params > QCL_MAX_PARAMS)
+        return fail(QCL_ERR_INVALID_ARG, "n_params %d outside [0, %d]", src->n_params, QCL_MAX_PARAMS);
+    if (src->n_params > 0 && (!src->params || !finite_all(src->params, src->n_params)))
+        return fail(QCL_ERR_INVALID_ARG, "params is NULL or not finite");
+    qcl_model_s *m = new (std::nothrow) qcl_model_s();
+    if (!m)
+        return fail(QCL_ERR_OUT_OF_MEMORY, "host allocation failed");
+    m->n = n;
+    m->m = M;
+    m->hbar = d->hbar;
+    m->mass.assign(d->mass, d->mass + M);
+    m->omega.assign(d->omega, d->omega + M);
+    m->v0.assign((size_t)n * n, 0.0);
+    m->k.assign((size_t)M * n * n, 0.0);
+    m->source = true;
+    if (qcl_status st = qcl::user_compile(*m, src->source, src->params, src->n_params)) {
+        delete m;
+        return st;
+    }
+    hipError_t e = hipGetDevice(&m->device);
+    if (e != hipSuccess) {
+        delete m;
+        return device_fail(e, "hipGetDevice");
+    }
+    if (qcl_status st = qcl::user_load(*m)) {
+        delete m;
+        return st;
+    }
+    *out = m;
+    return QCL_OK;
+}
+
 }  // namespace
 
 namespace qcl {
@@ -875,6 +934,13 @@ const char *qcl_last_error(void) { return g_last_error.c_str(); }
 
 qcl_status qcl_create_model(const qcl_model_desc *d, qcl_model *out) { return create_model(d, nullptr, nullptr, out); }
 
+qcl_status qcl_create_model_source(const qcl_model_desc *d, const qcl_source_desc *src, qcl_model *out)
+{
+    return create_model_source(d, src, out);
+}
+
+int32_t qcl_model_is_source(qcl_model m) { return m && m->source ? 1 : 0; }
+
 qcl_status qcl_create_model_poly(const qcl_model_desc *d, const qcl_poly_desc *poly, qcl_model *out)
 {
     if (!poly) {
@@ -906,6 +972,7 @@ qcl_status qcl_destroy_model(qcl_model m)
         return QCL_OK;
     if (m->d_model)
         (void)hipFree(m->d_model);
+    qcl::user_release(*m);
     delete m;
     return QCL_OK;
 }
@@ -1023,8 +1090,9 @@ qcl_status qcl_sample_initial(qcl_model m, const qcl_init_desc *init, uint64_t s
     }
     if (qcl_status st = check_device(*m))
         return st;
-    hipError_t e = m->fast2 ? qcl::launch_sample_n2(*m, sa, *ens, partials, n_out, (hipStream_t)stream)
-                            : qcl::launch_sample_general(*m, sa, *ens, partials, n_out, (hipStream_t)stream);
+    hipError_t e = m->source  ? qcl::launch_user_sample(*m, sa, *ens, partials, n_out, (hipStream_t)stream)
+                   : m->fast2 ? qcl::launch_sample_n2(*m, sa, *ens, partials, n_out, (hipStream_t)stream)
+                              : qcl::launch_sample_general(*m, sa, *ens, partials, n_out, (hipStream_t)stream);
     if (e == hipErrorNotSupported)
         return fail(QCL_ERR_UNSUPPORTED, "no sampling kernel for this model");
     if (e != hipSuccess)
@@ -1041,8 +1109,9 @@ qcl_status qcl_propagate(qcl_model m, qcl_ensemble *ens, const qcl_prop_desc *pd
         ens->step += pd->n_steps;
         return QCL_OK;
     }
-    hipError_t e = m->fast2 ? qcl::launch_propagate_n2(*m, *ens, *pd, partials, (hipStream_t)stream)
-                            : qcl::launch_propagate_general(*m, *ens, *pd, partials, (hipStream_t)stream);
+    hipError_t e = m->source  ? qcl::launch_user_propagate(*m, *ens, *pd, partials, (hipStream_t)stream)
+                   : m->fast2 ? qcl::launch_propagate_n2(*m, *ens, *pd, partials, (hipStream_t)stream)
+                              : qcl::launch_propagate_general(*m, *ens, *pd, partials, (hipStream_t)stream);
     if (e == hipErrorNotSupported)
         return fail(QCL_ERR_UNSUPPORTED, "no propagation kernel for this model");
     if (e != hipSuccess)

@@ -4,22 +4,15 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 #include <type_traits>
 #include <vector>
 
 #include "qcl.h"
+#include "qcl_device.hpp"
 
 namespace qcl {
 
-constexpr int kBlock = QCL_TILE;           // walkers per workgroup == reduction tile
-constexpr int kWave = 64;                  // CDNA wavefront
-constexpr int kMaxFastModes = 8;           // N = 2 kernels specialised on M = 1..8
-
-// Per-walker flag bits (mirrors the public QCL_FLAG_* values).
-constexpr uint32_t kFlagNonfinite = QCL_FLAG_NONFINITE;
-constexpr uint32_t kFlagDegenerate = QCL_FLAG_DEGENERATE;
-constexpr uint32_t kFlagResolved = QCL_FLAG_RESOLVED64;
-constexpr uint32_t kFlagFallback = QCL_FLAG_FALLBACK;
 
 // Two-state model in the form the analytic kernels use: with
 // V(q) = Vbar(q) I + [[dl, cc], [cc, -dl]],
@@ -83,6 +76,8 @@ struct GenConst {
 constexpr int kSq = 16;
 inline int sq_pad(int n_sq) { return n_sq <= 4 ? 4 : n_sq <= 8 ? 8 : kSq; }
 
+inline int64_t n_tiles(int64_t n_traj) { return (n_traj + kBlock - 1) / kBlock; }
+
 inline int padded_modes(int m)
 {
     return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 128;
@@ -94,40 +89,6 @@ inline int rank_bucket(int rank, int n)
     return rank <= 1 ? 1 : (rank <= n && n <= 4) ? n : n * (n + 1) / 2;
 }
 
-template <typename R>
-struct EnsDev {
-    R *q;
-    R *p;
-    R *u;
-    double *w;
-    double *phase;
-    uint8_t *a;
-    uint8_t *b;
-    uint32_t *flags;
-    int64_t ld;
-    int64_t n_traj;
-    int64_t traj_offset;
-};
-
-struct SampleArgs {
-    double q0[QCL_MAX_MODES];
-    double sq[QCL_MAX_MODES];
-    double sp[QCL_MAX_MODES];
-    int32_t state;
-    int32_t basis;
-    uint32_t key0, key1;
-    int32_t m;  // modes actually present (general kernels)
-};
-
-struct PropArgs {
-    int64_t step0;
-    int32_t n_steps;
-    int32_t cadence;
-    int32_t n_out;
-    int32_t scheme;
-    uint32_t key0, key1;
-    int32_t m;  // modes actually present (general kernels)
-};
 
 // Two-state model with higher powers of each mode: per mode j the
 // polynomials (no constant term) of dl, of cc and of Vbar, each in four
@@ -182,6 +143,13 @@ struct qcl_model_s {
     double dlt0 = 0.0, c0 = 0.0;
     double energy_scale = 1.0;
     int device = 0;
+    // built from device source (qcl_create_model_source): the code object
+    // compiled for it and its two kernels (hipModule_t, hipFunction_t)
+    bool source = false;
+    std::vector<char> user_code;
+    void *user_module = nullptr;
+    void *user_sample = nullptr;
+    void *user_propagate = nullptr;
     double *d_model = nullptr;  // device: V0 [N*N], K [M*N*N], then two-state binary64
                                 // constants [dlt0, c0, dlt[M], cpl[M]]
     size_t c64_offset = 0;      // element offset of the two-state constants
@@ -331,6 +299,17 @@ inline int occupancy_variant(const qcl_model_s &m, int prec, int requested)
     return 0;
 }
 
+// Models with a supplied potential (user_model.cpp): compilation of the
+// caller's source with the library's kernels, loading on the current
+// device, launches and release.
+qcl_status user_compile(qcl_model_s &m, const char *source, const double *params, int n_params);
+qcl_status user_load(qcl_model_s &m);
+void user_release(qcl_model_s &m);
+hipError_t launch_user_sample(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemble &ens, double *partials,
+                              int32_t n_out, hipStream_t s);
+hipError_t launch_user_propagate(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
+                                 double *partials, hipStream_t s);
+
 inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, int occ, const void *items,
                                int32_t n_items, int64_t total_tiles, unsigned long long *counter, hipStream_t s)
 {
@@ -377,10 +356,5 @@ ResampleLayout resample_layout(int64_t n_traj);
 hipError_t launch_resample(const qcl_model_s &m, const qcl_ensemble &src, const qcl_ensemble &dst, uint64_t seed,
                            void *workspace, hipStream_t stream);
 
-inline int64_t n_tiles(int64_t n_traj) { return (n_traj + kBlock - 1) / kBlock; }
-// One bin of one tile's partials: the 8 N^2 sums [2][N][N][Re, Im, Re^2,
-// Im^2], then the number of walkers excluded from the bin (non-finite weight
-// or phase), stored as a double so that the tile reduction adds it exactly.
-__host__ __device__ constexpr int64_t tile_values(int n_states) { return 8LL * n_states * n_states + 1; }
 
 }  // namespace qcl

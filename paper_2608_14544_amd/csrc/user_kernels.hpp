@@ -1,0 +1,255 @@
+// Kernels for a model with a supplied potential (the general form of Eq. 1:
+// any real symmetric N x N diabatic matrix V(q) of the classical modes,
+// H = sum_j p_j^2 / (2 m_j) + V(q)), compiled at run time with the caller's
+// device source in front.  That source defines
+//
+//   __device__ void qcl_potential(const double *q, double *V);
+//       V(q): the N(N+1)/2 upper-triangle entries V_kl (k <= l), row by row
+//   __device__ void qcl_force(const double *q, const double *w, double *f);
+//       f_j = -sum_s w_s dV_s/dq_j for the M modes (w: one weight per slot)
+//   __device__ void qcl_coupling(const double *q, const double *v, double *K);
+//       K_s = sum_j v_j dV_s/dq_j (v: one value per mode)
+//
+// and may read QCL_N, QCL_M and the caller's parameters qcl_param[], which
+// the compilation defines before it.  Everything is binary64.  The step is
+// the one of the built-in models (Monte Carlo move from rows a and b of
+// D = U^T K(v) U at (q_n, p_n), velocity Verlet on the mean force of the
+// new element, eigen-solve at q_{n+1} warm-started from the previous
+// frame, trapezoid phase, bins every cadence steps), with the force and the
+// velocity coupling taken from the caller's functions: the mean force is
+// qcl_force with the slot weights of element (a, b), so that it equals
+// -[(U^T dV/dq_j U)_aa + (U^T dV/dq_j U)_bb] / 2.
+#pragma once
+
+#include "nstate_frame.hpp"
+
+namespace qcl {
+
+// p_j += dt/2 f_j with the mean force of element (a, b) in frame f at q
+template <int N, int M>
+__device__ __forceinline__ void user_kick(const double (&q)[M], const Frame<N, double> &f, int a, int b, double hdt,
+                                          double (&p)[M])
+{
+    double P[kTri<N>], F[M];
+    pair_weights<N, double>(f, a, b, P);
+    qcl_force(q, P, F);
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        p[j] = fma_g(hdt, F[j], p[j]);
+}
+
+// K(v) = sum_j v_j dV/dq_j at q, v = p/m
+template <int N, int M>
+__device__ __forceinline__ void user_velocity_coupling(const double (&q)[M], const double (&p)[M],
+                                                       const double (&inv_mass)[M], double (&K)[kTri<N>])
+{
+    double v[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        v[j] = p[j] * inv_mass[j];
+    qcl_coupling(q, v, K);
+}
+
+// rows a and b of D = U^T K U
+template <int N>
+__device__ __forceinline__ void coupling_rows(const double (&K)[kTri<N>], const Frame<N, double> &f, int a, int b,
+                                              double (&Da)[N], double (&Db)[N])
+{
+    double ua[N], ub[N], wa[N], wb[N];
+    column<N, double>(f, a, ua);
+    column<N, double>(f, b, ub);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            const double kv = K[sym_index<N>(k, l)];
+            sa = fma_g(kv, ua[l], sa);
+            sb = fma_g(kv, ub[l], sb);
+        }
+        wa[k] = sa;
+        wb[k] = sb;
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        double da = 0.0, db = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            da = fma_g(f.U[k][c], wa[k], da);
+            db = fma_g(f.U[k][c], wb[k], db);
+        }
+        Da[c] = da;
+        Db[c] = db;
+    }
+}
+
+// Wigner sampling of the harmonic reference (the same draws as the built-in
+// models: Philox block (gid, j, 1) per mode, Box-Muller), frame from the
+// identity, initial element, bin 0.
+template <int N, int M>
+__device__ __forceinline__ void user_sample(const SampleArgs &S, const UserArgs &A, const EnsDev<double> &E,
+                                            double *__restrict__ partials, int32_t n_out, BinLds &lds)
+{
+    int parity = 0;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool live = i < E.n_traj;
+    const uint64_t gid = (uint64_t)(E.traj_offset + (live ? i : 0));
+    const double two_pi = 6.283185307179586476925286766559;
+    const int64_t ld = E.ld;
+    double q[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const U4 x = philox10(U4{(uint32_t)gid, (uint32_t)(gid >> 32), (uint32_t)j, 1u}, S.key0, S.key1);
+        const double u1 = u52(x.x, x.y);
+        const double u2 = u52(x.z, x.w);
+        const double rr = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincos_phase(two_pi * u2, sn, cs);
+        q[j] = S.q0[j] + S.sq[j] * (rr * cs);
+        const double pj = S.sp[j] * (rr * sn);
+        if (live) {
+            E.q[j * ld + i] = q[j];
+            E.p[j * ld + i] = pj;
+        }
+    }
+    double V[kTri<N>];
+    qcl_potential(q, V);
+    Frame<N, double> f;
+    solve_cold<N>(V, A.rot_eps, f);
+    uint32_t flag = 0;
+    if (!(min_gap<N, double>(f) > 2.2250738585072014e-308))
+        flag |= kFlagDegenerate;
+    int a, b;
+    double w;
+    initial_element<N>(f, S, gid, a, b, w);
+    bin_store<N, double>(lds, parity, live, a, b, w, 0.0, f,
+                         partials + ((int64_t)blockIdx.x * n_out + 0) * tile_values(N));
+    if (live) {
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int k = 0; k < N; ++k)
+                E.u[(r * N + k) * ld + i] = f.U[r][k];
+        E.w[i] = w;
+        E.phase[i] = 0.0;
+        E.a[i] = (uint8_t)a;
+        E.b[i] = (uint8_t)b;
+        if (E.flags)
+            E.flags[i] = flag;
+    }
+}
+
+// All steps of one tile of kBlock walkers (the whole workgroup calls it).
+template <int N, int M>
+__device__ __forceinline__ void user_propagate(const UserArgs &A, const PropArgs &P, const EnsDev<double> &E,
+                                               const double (&inv_mass)[M], double *__restrict__ partials,
+                                               BinLds &lds)
+{
+    constexpr int T = kTri<N>;
+    int parity = 0;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool live = i < E.n_traj;
+    const int64_t li = live ? i : E.n_traj - 1;
+    const int64_t ld = E.ld;
+    const uint64_t gid = (uint64_t)(E.traj_offset + li);
+    const uint32_t g_lo = (uint32_t)gid, g_hi = (uint32_t)(gid >> 32);
+    const bool linear_rule = P.scheme == QCL_TRANS_LINEAR;
+
+    double q[M], p[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        q[j] = E.q[j * ld + li];
+        p[j] = E.p[j * ld + li];
+    }
+    double w = E.w[li];
+    double phase = E.phase[li];
+    int a = E.a[li];
+    int b = E.b[li];
+    uint32_t flag = 0;
+    Frame<N, double> f;
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            f.U[r][k] = E.u[(r * N + k) * ld + li];
+    double K[T];
+    {
+        double V[T];
+        qcl_potential(q, V);
+        rayleigh<N, double>(V, f.U, f.E);
+        user_velocity_coupling<N, M>(q, p, inv_mass, K);
+    }
+
+    int64_t step = P.step0;
+    const int64_t end = P.step0 + P.n_steps;
+    U4 rnd{0, 0, 0, 0};
+    if (step & 3)
+        rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
+    while (step < end) {
+        const int64_t next_bin = (step / P.cadence + 1) * P.cadence;
+        const int64_t stop = next_bin < end ? next_bin : end;
+        for (; step < stop; ++step) {
+            if ((step & 3) == 0)
+                rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
+            const double u = u24d(pick_word(rnd, (uint32_t)(step & 3)));
+
+            // 1. Monte Carlo move at (q_n, p_n)
+            double Da[N], Db[N];
+            coupling_rows<N>(K, f, a, b, Da, Db);
+            transition<N, double>(f, Da, Db, u, A.dt, linear_rule, a, b, w, flag);
+
+            // 2. velocity Verlet on the mean force of the current element
+            const double dE0 = energy<N, double>(f, a) - energy<N, double>(f, b);
+            user_kick<N, M>(q, f, a, b, A.hdt, p);
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                q[j] = fma_g(A.dt, p[j] * inv_mass[j], q[j]);
+            {
+                double V[T], U0[N][N];
+                qcl_potential(q, V);
+#pragma unroll
+                for (int r = 0; r < N; ++r)
+#pragma unroll
+                    for (int k = 0; k < N; ++k)
+                        U0[r][k] = f.U[r][k];
+                solve_warm<N, double>(V, U0, A.rot_eps, f);
+            }
+            if (!(min_gap<N, double>(f) > 2.2250738585072014e-308))
+                flag |= kFlagDegenerate;
+            user_kick<N, M>(q, f, a, b, A.hdt, p);
+            user_velocity_coupling<N, M>(q, p, inv_mass, K);
+
+            // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar
+            const double dE1 = energy<N, double>(f, a) - energy<N, double>(f, b);
+            phase += A.dt_hbar * 0.5 * (dE0 + dE1);
+        }
+        // 4. output bin at global step next_bin
+        if (step == next_bin && next_bin / P.cadence < P.n_out) {
+            bin_store<N, double>(lds, parity, live, a, b, w, phase, f,
+                                 partials + ((int64_t)blockIdx.x * P.n_out + next_bin / P.cadence) * tile_values(N));
+        }
+    }
+    if (!(__builtin_isfinite(w) && __builtin_isfinite(phase)))
+        flag |= kFlagNonfinite;
+
+    if (live) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            E.q[j * ld + i] = q[j];
+            E.p[j * ld + i] = p[j];
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int k = 0; k < N; ++k)
+                E.u[(r * N + k) * ld + i] = f.U[r][k];
+        E.w[i] = w;
+        E.phase[i] = phase;
+        E.a[i] = (uint8_t)a;
+        E.b[i] = (uint8_t)b;
+        if (E.flags)
+            E.flags[i] |= flag;
+    }
+}
+
+}  // namespace qcl

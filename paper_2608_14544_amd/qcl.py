@@ -63,6 +63,11 @@ class qcl_bilinear_desc(C.Structure):
                 ("b", C.POINTER(C.c_double))]
 
 
+class qcl_source_desc(C.Structure):
+    _fields_ = [("source", C.c_char_p), ("params", C.POINTER(C.c_double)), ("n_params", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class qcl_init_desc(C.Structure):
     _fields_ = [("kT", C.c_double), ("q0", C.POINTER(C.c_double)),
                 ("state", C.c_int32), ("basis", C.c_int32)]
@@ -87,7 +92,8 @@ class qcl_batch_item(C.Structure):
                 ("partials", C.c_void_p)]
 
 
-EXPORTS = ("qcl_create_model", "qcl_create_model_poly", "qcl_create_model_bilinear", "qcl_destroy_model",
+EXPORTS = ("qcl_create_model", "qcl_create_model_poly", "qcl_create_model_bilinear", "qcl_create_model_source",
+           "qcl_model_is_source", "qcl_destroy_model",
            "qcl_model_states", "qcl_model_modes", "qcl_model_rank", "qcl_model_degree", "qcl_model_pairs",
            "qcl_ensemble_bytes", "qcl_ensemble_bind", "qcl_partials_bytes",
            "qcl_sample_initial", "qcl_propagate", "qcl_batch_workspace_bytes", "qcl_propagate_batch",
@@ -115,6 +121,9 @@ def load_library(path: str = LIB_PATH):
         L.qcl_model_degree.restype = i32
         L.qcl_create_model_bilinear.argtypes = [C.POINTER(qcl_model_desc), C.POINTER(qcl_poly_desc),
                                                 C.POINTER(qcl_bilinear_desc), C.POINTER(vp)]
+        L.qcl_create_model_source.argtypes = [C.POINTER(qcl_model_desc), C.POINTER(qcl_source_desc), C.POINTER(vp)]
+        L.qcl_model_is_source.argtypes = [vp]
+        L.qcl_model_is_source.restype = i32
         L.qcl_model_pairs.argtypes = [vp]
         L.qcl_model_pairs.restype = i32
         L.qcl_destroy_model.argtypes = [vp]
@@ -175,6 +184,9 @@ class Model:
     def __init__(self, lvc):
         L = load_library()
         self.lvc = lvc
+        if getattr(lvc, "hip_source", None) is not None:
+            self._init_source(L, lvc)
+            return
         self._arrays = [np.ascontiguousarray(x, np.float64) for x in (lvc.mass, lvc.omega, lvc.v0, lvc.k)]
         mass, omega, v0, k = self._arrays
         desc = qcl_model_desc(int(v0.shape[0]), int(mass.shape[0]), _dptr(mass), _dptr(omega),
@@ -204,6 +216,30 @@ class Model:
         self.rank = int(L.qcl_model_rank(h))
         self.degree = int(L.qcl_model_degree(h))
         self.n_pairs = int(L.qcl_model_pairs(h))
+
+    def _init_source(self, L, sm):
+        """A model with a supplied potential (``workloads.SourceModel``):
+        its device source is compiled by the library for the current device."""
+        mass = np.ascontiguousarray(sm.mass, np.float64)
+        omega = np.ascontiguousarray(sm.omega, np.float64)
+        prm = np.ascontiguousarray(sm.params, np.float64)
+        self._arrays = [mass, omega, prm]
+        desc = qcl_model_desc(int(sm.n_states), int(mass.shape[0]), _dptr(mass), _dptr(omega), None, None,
+                              float(sm.hbar))
+        self._source = sm.hip_source.encode()
+        src = qcl_source_desc(self._source, _dptr(prm) if prm.size else None, int(prm.size), 0)
+        h = C.c_void_p()
+        _check(L.qcl_create_model_source(C.byref(desc), C.byref(src), C.byref(h)))
+        self.handle = h
+        self.n_states = int(L.qcl_model_states(h))
+        self.n_modes = int(L.qcl_model_modes(h))
+        self.rank = int(L.qcl_model_rank(h))
+        self.degree = 1
+        self.n_pairs = 0
+
+    @property
+    def is_source(self) -> bool:
+        return bool(load_library().qcl_model_is_source(self.handle))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -277,3 +277,58 @@ def test_nonfinite_status_in_header_and_binding():
     assert qcl.QCL_ERR_NONFINITE == 5
     e = qcl.QCLError(5, "3 of 10 walkers excluded")
     assert e.status == 5 and e.out is None
+
+
+def _source_desc(qcl, src, n_params=0):
+    prm = np.ones(max(n_params, 1))
+    keep = [src.encode(), prm]
+    d = qcl.qcl_source_desc(keep[0], prm.ctypes.data_as(C.POINTER(C.c_double)) if n_params else None, n_params, 0)
+    return d, keep
+
+
+def test_create_model_source_validation_on_host():
+    """Sizes, parameters and the source are checked before the compiler or a
+    device is touched; a source that does not compile is reported with the
+    compiler's log (hipRTC runs without a device)."""
+    qcl, L = _lib()
+    wl = W.morse_coupled()
+    good = wl.model.hip_source
+    h = C.c_void_p()
+    for over, src, n_params, expect in [
+        (dict(n_states=5), good, 12, qcl.QCL_ERR_INVALID_ARG),
+        (dict(n_states=1), good, 12, qcl.QCL_ERR_INVALID_ARG),
+        (dict(n_modes=33), good, 12, qcl.QCL_ERR_INVALID_ARG),
+        (dict(mass=[1.0, -1.0]), good, 12, qcl.QCL_ERR_INVALID_ARG),
+        ({}, good, -1, qcl.QCL_ERR_INVALID_ARG),
+        ({}, good, 257, qcl.QCL_ERR_INVALID_ARG),
+        ({}, "__device__ void qcl_potential(const double *q, double *V) { V[0] = ; }", 12, qcl.QCL_ERR_INVALID_ARG),
+    ]:
+        lvc = W.LVCModel("x", mass=over.get("mass", [1.0, 1.0]), omega=[1.0, 1.0], v0=np.zeros((2, 2)),
+                         k=np.zeros((2, 2, 2)))
+        d, keep = _desc(qcl, lvc, **{k: v for k, v in over.items() if k != "mass"})
+        s, keep2 = _source_desc(qcl, src, n_params)
+        st = L.qcl_create_model_source(C.byref(d), C.byref(s), C.byref(h))
+        assert st == expect, (over, n_params, st)
+        assert not h.value
+    assert b"does not compile" in L.qcl_last_error()
+    assert L.qcl_create_model_source(None, None, C.byref(h)) == qcl.QCL_ERR_INVALID_ARG
+    assert L.qcl_model_is_source(None) == 0
+
+
+def test_create_model_source_compiles_on_host():
+    """A valid source compiles here; without a device the model then fails to
+    load (DEVICE), and on a machine with one it is built."""
+    qcl, L = _lib()
+    wl = W.morse_coupled()
+    lvc = W.LVCModel("x", mass=[1.0, 1.0], omega=[1.0, 1.0], v0=np.zeros((2, 2)), k=np.zeros((2, 2, 2)))
+    d, keep = _desc(qcl, lvc)
+    prm = np.ascontiguousarray(wl.model.params)
+    s = qcl.qcl_source_desc(wl.model.hip_source.encode(), prm.ctypes.data_as(C.POINTER(C.c_double)), prm.size, 0)
+    h = C.c_void_p()
+    st = L.qcl_create_model_source(C.byref(d), C.byref(s), C.byref(h))
+    assert st in (qcl.QCL_OK, qcl.QCL_ERR_DEVICE), L.qcl_last_error()
+    if st == qcl.QCL_OK:
+        assert L.qcl_model_is_source(h) == 1
+        L.qcl_destroy_model(h)
+    else:
+        assert b"does not compile" not in L.qcl_last_error()

@@ -82,6 +82,56 @@ class LVCModel:
 
 
 @dataclasses.dataclass
+class SourceModel:
+    """A model whose diabatic potential matrix V(q) is given as code:
+    H = sum_j p_j^2 / (2 m_j) + V(q), V holding every q-dependent term.
+    ``hip_source`` defines the three device functions of
+    qcl_create_model_source (V's upper triangle, the force contraction and
+    the velocity coupling); ``c_source`` is a plain C transcription of the
+    same formulas for the oracle (``qcl_oracle_potential(q, prm, V)`` with V
+    the full N x N matrix, ``qcl_oracle_gradient(j, q, prm, G)`` with
+    G = dV/dq_j).  ``omega`` are the frequencies of the harmonic reference
+    the Wigner initial state is drawn from."""
+
+    name: str
+    n_states_: int
+    mass: np.ndarray    # [M]
+    omega: np.ndarray   # [M]
+    params: np.ndarray  # [P]
+    hip_source: str
+    c_source: str
+    hbar: float = 1.0
+    time_unit_fs: Optional[float] = None
+    poly = None
+    bilinear = None
+
+    def __post_init__(self):
+        self.mass = np.ascontiguousarray(self.mass, dtype=np.float64)
+        self.omega = np.ascontiguousarray(self.omega, dtype=np.float64)
+        self.params = np.ascontiguousarray(self.params, dtype=np.float64)
+
+    @property
+    def degree(self) -> int:
+        return 1
+
+    @property
+    def n_states(self) -> int:
+        return int(self.n_states_)
+
+    @property
+    def n_modes(self) -> int:
+        return int(self.mass.shape[0])
+
+    @property
+    def v0(self) -> np.ndarray:  # not used by either path; the shape carries N
+        return np.zeros((self.n_states, self.n_states))
+
+    @property
+    def k(self) -> np.ndarray:
+        return np.zeros((self.n_modes, self.n_states, self.n_states))
+
+
+@dataclasses.dataclass
 class InitSpec:
     """Initial state: thermal Wigner (q, p) centred on q0, electronic state
     ``state`` in the diabatic (default) or adiabatic basis."""
@@ -335,6 +385,194 @@ def random_bilinear(index: int, n_states: int = 3, n_modes: int = 5, n_pairs: in
     wl.model = LVCModel(name=f"random_bilinear_{key}_{index}", mass=m.mass, omega=m.omega, v0=m.v0, k=m.k,
                         poly=m.poly, bilinear=bil)
     return wl
+
+
+# Two Morse curves along mode 0 (depth D_s, range a, minima x_s, offset of
+# state 1), a harmonic mode 1 shared by both states and shifted linearly on
+# state 1, and a diabatic coupling c (c0 + a Gaussian in mode 0 centred
+# between the minima) (1 + gamma q_1^2): not separable in the modes, and
+# never zero, so the surfaces only come close at an avoided crossing.
+# Parameters: D0, D1, a, x0, x1, offset, k1, kappa, c, beta, xc, gamma, c0.
+_MORSE_HIP = """
+__device__ inline void morse_parts(const double *q, double &e0, double &e1, double &g)
+{
+    e0 = exp(-qcl_param[2] * (q[0] - qcl_param[3]));
+    e1 = exp(-qcl_param[2] * (q[0] - qcl_param[4]));
+    const double d = q[0] - qcl_param[10];
+    g = exp(-qcl_param[9] * d * d);  // the Gaussian; the coupling's shape is c0 + g
+}
+__device__ void qcl_potential(const double *q, double *V)
+{
+    double e0, e1, g;
+    morse_parts(q, e0, e1, g);
+    const double h = 0.5 * qcl_param[6] * q[1] * q[1];
+    V[0] = qcl_param[0] * (1.0 - e0) * (1.0 - e0) + h;
+    V[1] = qcl_param[8] * (qcl_param[12] + g) * (1.0 + qcl_param[11] * q[1] * q[1]);
+    V[2] = qcl_param[1] * (1.0 - e1) * (1.0 - e1) + qcl_param[5] + h + qcl_param[7] * q[1];
+}
+__device__ inline void morse_gradient(const double *q, double (&G)[2][3])
+{
+    double e0, e1, g;
+    morse_parts(q, e0, e1, g);
+    const double a = qcl_param[2];
+    G[0][0] = 2.0 * qcl_param[0] * a * e0 * (1.0 - e0);
+    G[0][1] = -2.0 * qcl_param[9] * (q[0] - qcl_param[10]) * qcl_param[8] * g * (1.0 + qcl_param[11] * q[1] * q[1]);
+    G[0][2] = 2.0 * qcl_param[1] * a * e1 * (1.0 - e1);
+    G[1][0] = qcl_param[6] * q[1];
+    G[1][1] = qcl_param[8] * (qcl_param[12] + g) * 2.0 * qcl_param[11] * q[1];
+    G[1][2] = qcl_param[6] * q[1] + qcl_param[7];
+}
+__device__ void qcl_force(const double *q, const double *w, double *f)
+{
+    double G[2][3];
+    morse_gradient(q, G);
+    for (int j = 0; j < 2; ++j)
+        f[j] = -(w[0] * G[j][0] + w[1] * G[j][1] + w[2] * G[j][2]);
+}
+__device__ void qcl_coupling(const double *q, const double *v, double *K)
+{
+    double G[2][3];
+    morse_gradient(q, G);
+    for (int s = 0; s < 3; ++s)
+        K[s] = v[0] * G[0][s] + v[1] * G[1][s];
+}
+"""
+
+_MORSE_C = """
+void qcl_oracle_potential(const double *q, const double *prm, double *V)
+{
+    double D0 = prm[0], D1 = prm[1], a = prm[2], x0 = prm[3], x1 = prm[4], off = prm[5];
+    double k1 = prm[6], kap = prm[7], c = prm[8], beta = prm[9], xc = prm[10], gam = prm[11], c0 = prm[12];
+    double m0 = 1.0 - exp(-a * (q[0] - x0)), m1 = 1.0 - exp(-a * (q[0] - x1));
+    double bath = 0.5 * k1 * q[1] * q[1];
+    double cpl = c * (c0 + exp(-beta * (q[0] - xc) * (q[0] - xc))) * (1.0 + gam * q[1] * q[1]);
+    V[0] = D0 * m0 * m0 + bath;
+    V[1] = cpl;
+    V[2] = cpl;
+    V[3] = D1 * m1 * m1 + off + bath + kap * q[1];
+}
+
+void qcl_oracle_gradient(int j, const double *q, const double *prm, double *G)
+{
+    double D0 = prm[0], D1 = prm[1], a = prm[2], x0 = prm[3], x1 = prm[4];
+    double k1 = prm[6], kap = prm[7], c = prm[8], beta = prm[9], xc = prm[10], gam = prm[11], c0 = prm[12];
+    double g = c * exp(-beta * (q[0] - xc) * (q[0] - xc));
+    if (j == 0) {
+        double t0 = exp(-a * (q[0] - x0)), t1 = exp(-a * (q[0] - x1));
+        G[0] = 2.0 * D0 * a * t0 * (1.0 - t0);
+        G[3] = 2.0 * D1 * a * t1 * (1.0 - t1);
+        G[1] = G[2] = -2.0 * beta * (q[0] - xc) * g * (1.0 + gam * q[1] * q[1]);
+    } else {
+        G[0] = k1 * q[1];
+        G[3] = k1 * q[1] + kap;
+        G[1] = G[2] = 2.0 * (c * c0 + g) * gam * q[1];
+    }
+}
+"""
+
+
+def morse_coupled(n_traj: int = 4096, n_steps: int = 200, dt: float = 0.05, cadence: int = 10,
+                  seed: int = 11, kT: float = 0.0) -> Workload:
+    """Two coupled Morse states with a harmonic spectator mode (reduced
+    units, m = 1; each Morse well's harmonic frequency a sqrt(2 D / m) = 1,
+    its depth well above the walkers' energy): the walkers start in diabatic
+    state 1 at the state-0 minimum and cross the coupling region between the
+    minima."""
+    params = [5.0, 5.0, 1.0 / math.sqrt(10.0), 0.0, 1.0, 0.2, 1.0, 0.2, 0.15, 1.0, 0.5, 0.3, 0.2]
+    model = SourceModel(name="morse_coupled", n_states_=2, mass=[1.0, 1.0], omega=[1.0, 1.0], params=params,
+                        hip_source=_MORSE_HIP, c_source=_MORSE_C)
+    init = InitSpec(kT=kT, q0=[0.0, 0.0], state=1)
+    return Workload(model, init, RunSpec(n_traj, n_steps, dt, cadence, seed))
+
+
+def lvc_as_source(model: LVCModel, name: Optional[str] = None) -> SourceModel:
+    """The same linear-vibronic Hamiltonian written as a supplied potential:
+    V(q) = V0 + sum_j q_j K_j + I sum_j m_j w_j^2 q_j^2 / 2, with the
+    parameters [V0 slots (T), K_j slots (M x T), m_j w_j^2 (M)]."""
+    n, M = model.n_states, model.n_modes
+    T = n * (n + 1) // 2
+    slots = [(k, l) for k in range(n) for l in range(k, n)]
+    params = [model.v0[k, l] for k, l in slots]
+    for j in range(M):
+        params += [model.k[j, k, l] for k, l in slots]
+    params += list(model.mass * model.omega ** 2)
+    diag = ", ".join("1" if k == l else "0" for k, l in slots)
+    hip = f"""
+#define LVC_T {T}
+__device__ constexpr int lvc_diag[LVC_T] = {{{diag}}};
+__device__ inline double lvc_k(int j, int s) {{ return qcl_param[LVC_T * (1 + j) + s]; }}
+__device__ inline double lvc_mw2(int j) {{ return qcl_param[LVC_T * (1 + QCL_M) + j]; }}
+__device__ void qcl_potential(const double *q, double *V)
+{{
+    double h = 0.0;
+    for (int j = 0; j < QCL_M; ++j)
+        h += 0.5 * lvc_mw2(j) * q[j] * q[j];
+    for (int s = 0; s < LVC_T; ++s) {{
+        double v = qcl_param[s];
+        for (int j = 0; j < QCL_M; ++j)
+            v += q[j] * lvc_k(j, s);
+        V[s] = lvc_diag[s] ? v + h : v;
+    }}
+}}
+__device__ void qcl_force(const double *q, const double *w, double *f)
+{{
+    double wd = 0.0;
+    for (int s = 0; s < LVC_T; ++s)
+        wd += lvc_diag[s] ? w[s] : 0.0;
+    for (int j = 0; j < QCL_M; ++j) {{
+        double g = lvc_mw2(j) * q[j] * wd;
+        for (int s = 0; s < LVC_T; ++s)
+            g += w[s] * lvc_k(j, s);
+        f[j] = -g;
+    }}
+}}
+__device__ void qcl_coupling(const double *q, const double *v, double *K)
+{{
+    double h = 0.0;
+    for (int j = 0; j < QCL_M; ++j)
+        h += v[j] * lvc_mw2(j) * q[j];
+    for (int s = 0; s < LVC_T; ++s) {{
+        double k = 0.0;
+        for (int j = 0; j < QCL_M; ++j)
+            k += v[j] * lvc_k(j, s);
+        K[s] = lvc_diag[s] ? k + h : k;
+    }}
+}}
+"""
+    c = f"""
+#define LVC_N {n}
+#define LVC_M {M}
+#define LVC_T {T}
+static int lvc_slot(int k, int l)
+{{
+    if (k > l) {{ int t = k; k = l; l = t; }}
+    return k * LVC_N - k * (k - 1) / 2 + (l - k);
+}}
+void qcl_oracle_potential(const double *q, const double *prm, double *V)
+{{
+    double h = 0.0;
+    for (int j = 0; j < LVC_M; ++j)
+        h += 0.5 * prm[LVC_T * (1 + LVC_M) + j] * q[j] * q[j];
+    for (int k = 0; k < LVC_N; ++k)
+        for (int l = 0; l < LVC_N; ++l) {{
+            int s = lvc_slot(k, l);
+            double v = prm[s];
+            for (int j = 0; j < LVC_M; ++j)
+                v += q[j] * prm[LVC_T * (1 + j) + s];
+            V[k * LVC_N + l] = (k == l) ? v + h : v;
+        }}
+}}
+void qcl_oracle_gradient(int j, const double *q, const double *prm, double *G)
+{{
+    for (int k = 0; k < LVC_N; ++k)
+        for (int l = 0; l < LVC_N; ++l) {{
+            double g = prm[LVC_T * (1 + j) + lvc_slot(k, l)];
+            G[k * LVC_N + l] = (k == l) ? g + prm[LVC_T * (1 + LVC_M) + j] * q[j] : g;
+        }}
+}}
+"""
+    return SourceModel(name=name or model.name + "_source", n_states_=n, mass=model.mass, omega=model.omega,
+                       params=params, hip_source=hip, c_source=c, hbar=model.hbar, time_unit_fs=model.time_unit_fs)
 
 
 def batched_instances(n_instances: int = 256, key: int = 4, **kw) -> List[Workload]:
