@@ -28,6 +28,11 @@ two.  Two further legs are reported in the same line:
   resample qcl_resample of the headline ensemble (1e7 walkers) against HBM
            bandwidth, and the replica spread of P(t) with and without
            resampling every 1-10 fs (64 x 1e6 walkers).
+  served_full  the served stream with 1e5-1e8 walkers per random job, whose
+           offered load exceeds the device.
+  general  the general-N kernel classes (4,64), (4,32), (3,64) alone.
+  source   models with a supplied potential (coupled Morse states; a
+           linear-vibronic model as source and on the built-in kernels).
 
 Prints one JSON line.
 
@@ -492,6 +497,42 @@ def general_leg(P, torch, n_traj=1 << 20, n_steps=200):
     return rows
 
 
+def source_leg(P, torch, n_traj=1 << 20, n_steps=200):
+    """Models with a supplied potential (binary64): the coupled Morse model,
+    and a 3-state 4-mode linear-vibronic model both as a supplied potential
+    and on the built-in general kernels (the cost of the generic path);
+    walker-steps/s of one qcl_propagate call, and the time to build the
+    model (run-time compilation)."""
+    import workloads as W
+    lvc = W.random_lvc(7, n_states=3, n_modes=4)
+    cases = [("morse_coupled", W.morse_coupled()), ("random_lvc_3_4_source", W.Workload(
+        W.lvc_as_source(lvc.model), lvc.init, lvc.run)), ("random_lvc_3_4_builtin", lvc)]
+    rows = []
+    for name, wl in cases:
+        r = wl.run
+        t0 = time.perf_counter()
+        model = P.Model(wl.model)
+        build_s = time.perf_counter() - t0
+        ens = P.Ensemble(model, n_traj, "fp64", zero=False)
+        part = P.Partials(model, n_traj, n_steps // r.cadence + 1)
+        P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
+        P.qcl_propagate(model, ens, r.dt, r.cadence, r.cadence, r.seed, part)  # warm-up
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        P.qcl_propagate(model, ens, r.dt, n_steps - r.cadence, r.cadence, r.seed, part, 0, s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        rows.append({"model": name, "n_states": wl.model.n_states, "n_modes": wl.model.n_modes, "n_traj": n_traj,
+                     "n_steps": n_steps - r.cadence, "ms": ms, "prec": "fp64",
+                     "value": n_traj * (n_steps - r.cadence) / (ms / 1e3), "model_build_s": build_s})
+        del ens, part, model
+        torch.cuda.empty_cache()
+    return rows
+
+
 def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=None, quantum_work=2e8):
     """The served stream through the continuous-batching server.  Default:
     the sub-saturation variant (walkers log-uniform over 1e5-1e7); ``full``
@@ -504,12 +545,20 @@ def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=
     from paper_2608_14544_amd.tune import autotune
     table = autotune(wls, "fp32", table)  # untimed; classes already tuned are kept
     srv = Server(DeviceBackend(tuning=table), quantum_steps=quantum, quantum_work=quantum_work)
-    res = srv.run(arrivals, specs)
+    done = []
+
+    def progress(r):
+        done.append(r)
+        if len(done) % 20 == 0 or len(done) == n_jobs:
+            print(f"[bench] served ({'full' if full else 'sub-saturation'}): {len(done)}/{n_jobs} jobs done at "
+                  f"{r.finished:.1f} s", file=sys.stderr, flush=True)
+
+    res = srv.run(arrivals, specs, on_result=progress)
     st = latency_stats(res)
-    # the same stream with a fixed 50-step quantum per job, for comparison
-    srv2 = Server(DeviceBackend(tuning=table), quantum_steps=50)
-    st2 = latency_stats(srv2.run(arrivals, specs))
-    st["fixed_50_step_quantum"] = {k: st2[k] for k in ("p50_s", "p99_s", "walker_steps_per_s", "makespan_s")}
+    if not full:  # the same stream with a fixed 50-step quantum per job, for comparison
+        srv2 = Server(DeviceBackend(tuning=table), quantum_steps=50)
+        st2 = latency_stats(srv2.run(arrivals, specs))
+        st["fixed_50_step_quantum"] = {k: st2[k] for k in ("p50_s", "p99_s", "walker_steps_per_s", "makespan_s")}
     kinds = {}
     for rr in res:
         kind = rr.name.split(":", 1)[1] if ":" in rr.name else "job"
@@ -587,8 +636,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--legs", default="headline,spin_boson,batched,served,scaling,convergence,poly,many_states,"
-                    "resample,general",
+    ap.add_argument("--legs", default="headline,spin_boson,batched,served,served_full,scaling,convergence,poly,"
+                    "many_states,resample,general,source",
                     help="comma-separated subset of the default legs")
     ap.add_argument("--resample-replicas", type=int, default=64,
                     help="replicas of the resampling study (0: time the resampling only)")
@@ -596,7 +645,7 @@ def main():
     ap.add_argument("--served-quantum-work", type=float, default=2e8,
                     help="walker-steps per resident job per serving round")
     ap.add_argument("--served-full", action="store_true",
-                    help="served stream with 1e5-1e8 walkers per random job (offered load above capacity)")
+                    help="the served leg uses 1e5-1e8 walkers per random job (as the served_full leg does)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -714,10 +763,20 @@ def main():
                                     quantum_work=args.served_quantum_work)
         print(f"[bench] served: {line['served']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
+    if "served_full" in legs and not args.served_full:
+        line["served_full"] = served_leg(P, torch, args.served_jobs, full=True, table=table,
+                                         quantum_work=args.served_quantum_work)
+        print(f"[bench] served (1e5-1e8 walkers): {line['served_full']}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
     if "general" in legs:
         line["general"] = general_leg(P, torch)
         print("[bench] general: " + "; ".join(f"{x['class']} fp32 {x['fp32']['value']:.3e}, fp64 {x['fp64']['value']:.3e}"
                                               for x in line["general"]), file=sys.stderr, flush=True)
+    if "source" in legs:
+        line["source"] = source_leg(P, torch)
+        print("[bench] supplied potentials: " + "; ".join(
+            f"{x['model']} {x['value']:.3e} (build {x['model_build_s']:.2f} s)" for x in line["source"]),
+            file=sys.stderr, flush=True)
     if "scaling" in legs:
         line["scaling_sweep"] = scaling_leg(P, torch, wl)
         print(f"[bench] scaling sweep: " + ", ".join(f"{x['prec']} {x['n_traj']:.0e}: {x['ms']:.1f} ms"

@@ -269,9 +269,10 @@ class Server:
         return done
 
     def run(self, arrivals: Optional[List[float]] = None, specs: Optional[List[JobSpec]] = None,
-            idle_sleep: float = 2e-4) -> List[JobResult]:
+            idle_sleep: float = 2e-4, on_result: Optional[Callable[[JobResult], None]] = None) -> List[JobResult]:
         """Serves ``specs`` arriving at ``arrivals`` (seconds from now) and
-        returns every result in completion order."""
+        returns every result in completion order; ``on_result`` is called
+        with each result as it is retired."""
         specs = specs or []
         arrivals = list(arrivals or [0.0] * len(specs))
         assert len(arrivals) == len(specs) and arrivals == sorted(arrivals)
@@ -282,7 +283,9 @@ class Server:
             while k < len(specs) and arrivals[k] <= t:
                 self.submit(specs[k], arrival=arrivals[k])
                 k += 1
-            self.step()
+            for r in self.step():
+                if on_result is not None:
+                    on_result(r)
             if not self.active and not self.draining and not self.queue and k < len(specs):
                 time.sleep(max(0.0, min(idle_sleep * 50, arrivals[k] - self.now())))
             elif not self.active and self.draining:
