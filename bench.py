@@ -423,10 +423,18 @@ def batched_leg(P, torch, n_instances=256):
     """One qcl_propagate_batch call over the seeded heterogeneous instances
     (ensembles sampled beforehand, resident in HBM)."""
     import workloads as W
-    from paper_2608_14544_amd.tune import autotune
+    from paper_2608_14544_amd.tune import autotune, launch_class
     wls = W.batched_instances(n_instances)
     t0 = time.perf_counter()
     table = autotune(wls, "fp32")  # untimed: one short run per kernel class and build
+    seen = {}
+    for wl in wls:  # workgroups per CU, per launch class (the instance with the most walkers)
+        m = P.Model(wl.model)
+        k = launch_class(m, "fp32")
+        if k not in seen or wl.run.n_traj > seen[k][0].run.n_traj:
+            seen[k] = (wl, m)
+    for wl, m in seen.values():
+        table.tune_workgroups(wl, "fp32", model=m)
     tune_s = time.perf_counter() - t0
     jobs, tot = [], 0
     stream = torch.cuda.current_stream()
@@ -437,7 +445,8 @@ def batched_leg(P, torch, n_instances=256):
         part = P.Partials(model, r.n_traj, r.n_out)
         P.qcl_sample_initial(model, wl.init, r.seed, ens, part, stream)
         jobs.append(P.BatchJob(model, ens, part, r.dt, r.n_steps, r.cadence, r.seed,
-                               occupancy=table.occupancy(model, "fp32")))
+                               occupancy=table.occupancy(model, "fp32"),
+                               workgroups_per_cu=table.workgroups_per_cu(model, "fp32")))
         tot += r.n_traj * r.n_steps
     ws = P.Workspace()
     torch.cuda.synchronize()
@@ -453,8 +462,16 @@ def batched_leg(P, torch, n_instances=256):
                         "500-4000 steps), fp32, one qcl_propagate_batch call",
             "value": tot / (ms / 1e3), "unit": "trajectory-steps/s", "walker_steps": tot,
             "ms": ms, "wall_ms": wall * 1e3,
-            "autotune": {"classes": len(table.choice), "capped_register_budget": sum(
-                1 for v in table.choice.values() if v != 0), "seconds": tune_s}}, table
+            "autotune": {
+                "seconds": tune_s,
+                "register_budget": {"classes": len(table.choice), "capped": sum(1 for v in table.choice.values() if v),
+                                    "chosen": {"x".join(map(str, k[:3])): v for k, v in table.choice.items()},
+                                    "gain": {"x".join(map(str, k[:3])): t[0] / min(t.values())
+                                             for k, t in table.timings.items()}},
+                "workgroups_per_cu": {"classes": len(table.wpc), "capped": sum(1 for v in table.wpc.values() if v),
+                                      "chosen": {"x".join(map(str, k[:5])): v for k, v in table.wpc.items()},
+                                      "gain": {"x".join(map(str, k[:5])): t[0] / min(t.values())
+                                               for k, t in table.wpc_timings.items()}}}}, table
 
 
 GENERAL_CLASSES = ((4, 64), (4, 32), (3, 64))
@@ -533,7 +550,8 @@ def source_leg(P, torch, n_traj=1 << 20, n_steps=200):
     return rows
 
 
-def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=None, quantum_work=2e8):
+def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=None, quantum_work=2e8,
+               tune_quantum=True):
     """The served stream through the continuous-batching server.  Default:
     the sub-saturation variant (walkers log-uniform over 1e5-1e7); ``full``
     uses 1e5-1e8, whose offered load exceeds one device."""
@@ -542,9 +560,23 @@ def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=
     traj_range = (1e5, 1e8) if full else (1e5, 1e7)
     arrivals, wls = W.served_stream(n_jobs, rate=rate, traj_range=traj_range)
     specs = [JobSpec(wl, prec="fp32", name=f"{i}:{wl.model.name}") for i, wl in enumerate(wls)]
-    from paper_2608_14544_amd.tune import autotune
-    table = autotune(wls, "fp32", table)  # untimed; classes already tuned are kept
-    srv = Server(DeviceBackend(tuning=table), quantum_steps=quantum, quantum_work=quantum_work)
+    from paper_2608_14544_amd.tune import TuningTable, autotune
+    table = autotune(wls, "fp32", table if table is not None else TuningTable())  # untimed; kept if tuned
+    if tune_quantum and "quantum_work" not in table.serving:
+        k = max(1, n_jobs * 3 // 10)  # the first 30 % of the stream, served once per candidate
+
+        def run_prefix(q):
+            s = Server(DeviceBackend(tuning=table), quantum_steps=quantum, quantum_work=q)
+            return latency_stats(s.run(arrivals[:k], specs[:k]))
+        table.tune_quantum(run_prefix)
+        print(f"[bench] serving quantum: {table.quantum_work():.0e} walker-steps per job per round "
+              f"(p99 on the first {k} jobs: " + ", ".join(f"{q:.0e}: {v['p99_s']:.3f} s"
+                                                         for q, v in table.serving_timings.items()) + ")",
+              file=sys.stderr, flush=True)
+    if tune_quantum:
+        quantum_work = table.quantum_work(quantum_work)
+    backend = DeviceBackend(tuning=table)
+    srv = Server(backend, quantum_steps=quantum, quantum_work=quantum_work)
     done = []
 
     def progress(r):
@@ -574,6 +606,10 @@ def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=
                "offered_walker_steps_per_s": offered,
                "rounds": srv.rounds, "quantum": f"{quantum_work:.0e} walker-steps per job per round, "
                                                  f"at most {quantum} steps",
+               "quantum_tuning": {f"{q:.0e}": {kk: v.get(kk) for kk in ("p50_s", "p99_s", "walker_steps_per_s")}
+                                  for q, v in table.serving_timings.items()} if tune_quantum else None,
+               "host_enqueue_s": backend.host_s, "host_enqueue_s_per_round": backend.host_s / max(srv.rounds, 1),
+               "host_enqueue_fraction_of_makespan": backend.host_s / st["makespan_s"] if st.get("makespan_s") else None,
                "memory_budget_GB": srv.budget / 1e9})
     return st
 

@@ -169,7 +169,12 @@ typedef struct {
                              The result is bitwise the same either way; the
                              faster choice depends on the model (see the
                              tuner in the Python package). */
-    int32_t reserved;
+    int32_t workgroups_per_cu; /* qcl_propagate_batch: workgroups each compute
+                             unit receives in the item's persistent launch,
+                             0 = as many as fit, 1..32 = at most that many
+                             (items that differ in it launch separately);
+                             qcl_propagate ignores it.  Results are bitwise
+                             the same for every value. */
 } qcl_prop_desc;
 
 /* Builds a model: validates the description, derives the per-mode

@@ -777,7 +777,7 @@ size_t item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_des
 }
 
 template <int M, typename R, bool POLY>
-hipError_t batch_m_r(int scheme, const void *items, int32_t n_items, int64_t total_tiles,
+hipError_t batch_m_r(int scheme, int wpc, const void *items, int32_t n_items, int64_t total_tiles,
                      unsigned long long *counter, hipStream_t s)
 {
     int cus = 0, per_cu = 0, dev = 0;
@@ -786,7 +786,7 @@ hipError_t batch_m_r(int scheme, const void *items, int32_t n_items, int64_t tot
     const void *fn = scheme == QCL_TRANS_LINEAR ? (const void *)batch_n2_kernel<M, R, QCL_TRANS_LINEAR, POLY>
                                                 : (const void *)batch_n2_kernel<M, R, QCL_TRANS_NORMALIZED, POLY>;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0);
-    const int64_t grid = std::min<int64_t>(total_tiles, (int64_t)std::max(1, cus) * std::max(1, per_cu));
+    const int64_t grid = persistent_grid(total_tiles, cus, per_cu, wpc);
     const BatchItemN2<M, R, POLY> *it = (const BatchItemN2<M, R, POLY> *)items;
     if (scheme == QCL_TRANS_LINEAR)
         hipLaunchKernelGGL((batch_n2_kernel<M, R, QCL_TRANS_LINEAR, POLY>), dim3((unsigned)grid), dim3(kBlock), 0, s,
@@ -809,14 +809,14 @@ size_t item_m(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc
 }
 
 template <int M>
-hipError_t batch_m(bool poly, int prec, int scheme, const void *items, int32_t n_items, int64_t total_tiles,
+hipError_t batch_m(bool poly, int prec, int scheme, int wpc, const void *items, int32_t n_items, int64_t total_tiles,
                    unsigned long long *counter, hipStream_t s)
 {
     if (poly)
-        return prec == QCL_FP64 ? batch_m_r<M, double, true>(scheme, items, n_items, total_tiles, counter, s)
-                                : batch_m_r<M, float, true>(scheme, items, n_items, total_tiles, counter, s);
-    return prec == QCL_FP64 ? batch_m_r<M, double, false>(scheme, items, n_items, total_tiles, counter, s)
-                            : batch_m_r<M, float, false>(scheme, items, n_items, total_tiles, counter, s);
+        return prec == QCL_FP64 ? batch_m_r<M, double, true>(scheme, wpc, items, n_items, total_tiles, counter, s)
+                                : batch_m_r<M, float, true>(scheme, wpc, items, n_items, total_tiles, counter, s);
+    return prec == QCL_FP64 ? batch_m_r<M, double, false>(scheme, wpc, items, n_items, total_tiles, counter, s)
+                            : batch_m_r<M, float, false>(scheme, wpc, items, n_items, total_tiles, counter, s);
 }
 
 }  // namespace
@@ -837,18 +837,18 @@ size_t batch_item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_pr
     }
 }
 
-hipError_t launch_batch_n2(int modes, bool poly, int prec, int scheme, const void *items, int32_t n_items,
+hipError_t launch_batch_n2(int modes, bool poly, int prec, int scheme, int wpc, const void *items, int32_t n_items,
                            int64_t total_tiles, unsigned long long *counter, hipStream_t s)
 {
     switch (modes) {
-    case 1: return batch_m<1>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
-    case 2: return batch_m<2>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
-    case 3: return batch_m<3>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
-    case 4: return batch_m<4>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
-    case 5: return batch_m<5>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
-    case 6: return batch_m<6>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
-    case 7: return batch_m<7>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
-    case 8: return batch_m<8>(poly, prec, scheme, items, n_items, total_tiles, counter, s);
+    case 1: return batch_m<1>(poly, prec, scheme, wpc, items, n_items, total_tiles, counter, s);
+    case 2: return batch_m<2>(poly, prec, scheme, wpc, items, n_items, total_tiles, counter, s);
+    case 3: return batch_m<3>(poly, prec, scheme, wpc, items, n_items, total_tiles, counter, s);
+    case 4: return batch_m<4>(poly, prec, scheme, wpc, items, n_items, total_tiles, counter, s);
+    case 5: return batch_m<5>(poly, prec, scheme, wpc, items, n_items, total_tiles, counter, s);
+    case 6: return batch_m<6>(poly, prec, scheme, wpc, items, n_items, total_tiles, counter, s);
+    case 7: return batch_m<7>(poly, prec, scheme, wpc, items, n_items, total_tiles, counter, s);
+    case 8: return batch_m<8>(poly, prec, scheme, wpc, items, n_items, total_tiles, counter, s);
     default: return hipErrorNotSupported;
     }
 }

@@ -194,6 +194,8 @@ qcl_status check_propagate(qcl_model m, const qcl_ensemble *ens, const qcl_prop_
         return fail(QCL_ERR_INVALID_ARG, "unknown transition scheme %d", pd->scheme);
     if (pd->occupancy != 0 && pd->occupancy != 2 && pd->occupancy != 3)
         return fail(QCL_ERR_INVALID_ARG, "occupancy must be 0, 2 or 3");
+    if (pd->workgroups_per_cu < 0 || pd->workgroups_per_cu > 32)
+        return fail(QCL_ERR_INVALID_ARG, "workgroups_per_cu must be in [0, 32]");
     const int64_t last_bin = (ens->step + pd->n_steps) / pd->cadence;
     if (last_bin >= pd->n_out)
         return fail(QCL_ERR_INVALID_ARG, "bin %lld would be written but n_out is %d", (long long)last_bin,
@@ -225,7 +227,7 @@ qcl_status check_reduce(qcl_model m, const double *partials, int64_t n_traj, int
 // precision and transition rule.
 struct BatchClass {
     bool fast2;
-    int n, modes, prec, scheme, occ;
+    int n, modes, prec, scheme, occ, wpc;
     std::vector<int32_t> order;  // item indices, most expensive tile first
     size_t item_bytes = 0;
     size_t counter_offset = 0;   // one 8-byte tile counter
@@ -305,10 +307,11 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
         const int occ = qcl::occupancy_variant(m, it.ens->prec, it.prop.occupancy);
         for (BatchClass &k : plan.classes)
             if (k.fast2 == m.fast2 && k.n == m.n && k.modes == modes && k.prec == it.ens->prec &&
-                k.scheme == it.prop.scheme && k.occ == occ)
+                k.scheme == it.prop.scheme && k.occ == occ && k.wpc == it.prop.workgroups_per_cu)
                 c = &k;
         if (!c) {
-            plan.classes.push_back(BatchClass{m.fast2, m.n, modes, it.ens->prec, it.prop.scheme, occ});
+            plan.classes.push_back(
+                BatchClass{m.fast2, m.n, modes, it.ens->prec, it.prop.scheme, occ, it.prop.workgroups_per_cu});
             c = &plan.classes.back();
             c->item_bytes = qcl::batch_item(m, *it.ens, it.prop, nullptr, 0, nullptr);
             if (c->item_bytes == 0)
@@ -884,7 +887,7 @@ qcl_status propagate_batch_in(const qcl_batch_item *items, int32_t n_items, void
             return device_fail(e, "batch descriptor upload");
     }
     auto launch_class = [&](const BatchClass &c, hipStream_t on) {
-        return qcl::launch_batch(*items[c.order[0]].model, c.prec, c.scheme, c.occ, ws + c.offset,
+        return qcl::launch_batch(*items[c.order[0]].model, c.prec, c.scheme, c.occ, c.wpc, ws + c.offset,
                                  (int32_t)c.order.size(), c.total_tiles,
                                  (unsigned long long *)(ws + c.counter_offset), on);
     };

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <type_traits>
@@ -77,6 +78,15 @@ constexpr int kSq = 16;
 inline int sq_pad(int n_sq) { return n_sq <= 4 ? 4 : n_sq <= 8 ? 8 : kSq; }
 
 inline int64_t n_tiles(int64_t n_traj) { return (n_traj + kBlock - 1) / kBlock; }
+
+// Workgroups of a persistent batched launch: every compute unit gets the
+// workgroups that fit (per_cu), or at most wpc of them when wpc > 0; never
+// more than there are tiles.
+inline int64_t persistent_grid(int64_t total_tiles, int cus, int per_cu, int wpc)
+{
+    const int per = wpc > 0 ? std::min(wpc, std::max(1, per_cu)) : std::max(1, per_cu);
+    return std::min<int64_t>(total_tiles, (int64_t)std::max(1, cus) * per);
+}
 
 inline int padded_modes(int m)
 {
@@ -195,7 +205,8 @@ struct bilw_ {};  // the same with 16 squares, at most 16 modes (kernels_bilw{K}
                                           const qcl_prop_desc &pd, double *partials, hipStream_t s, TAG);    \
     size_t batch_item_general_n(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,      \
                                 double *partials, int64_t tile_begin, void *out, TAG);                       \
-    hipError_t launch_batch_general_n(int mp, int rb, int prec, int occ, const void *items, int32_t n_items, \
+    hipError_t launch_batch_general_n(int mp, int rb, int prec, int occ, int wpc, const void *items,           \
+                                      int32_t n_items,                                                     \
                                       int64_t total_tiles, unsigned long long *counter, hipStream_t s, TAG);
 QCL_DECLARE_GENERAL(int_<2>)
 QCL_DECLARE_GENERAL(int_<3>)
@@ -269,7 +280,7 @@ inline Ret with_general(const qcl_model_s &m, Ret none, F &&fn)
 
 size_t batch_item_n2(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
                      int64_t tile_begin, void *out);
-hipError_t launch_batch_n2(int modes, bool poly, int prec, int scheme, const void *items, int32_t n_items,
+hipError_t launch_batch_n2(int modes, bool poly, int prec, int scheme, int wpc, const void *items, int32_t n_items,
                            int64_t total_tiles, unsigned long long *counter, hipStream_t s);
 // device-side copy of host words carried in kernel arguments; zeroing of counters
 hipError_t upload_words(const uint64_t *words, size_t n_words, uint64_t *dst, hipStream_t s);
@@ -286,13 +297,13 @@ inline size_t batch_item(const qcl_model_s &m, const qcl_ensemble &ens, const qc
 
 // The register-budget variant a call runs: the one asked for where such
 // kernels exist (binary32, general kernels of a linear model; 3 with at most
-// 32 padded modes, 2 with 64), else 0.
+// 32 padded modes (16 for four states), 2 with 64), else 0.
 inline int occupancy_variant(const qcl_model_s &m, int prec, int requested)
 {
     if (m.fast2 || m.degree != 1 || m.n > 4 || prec != QCL_FP32_ACC64)
         return 0;
     const int mp = padded_modes(m.m);
-    if (requested == 3 && mp <= 32)
+    if (requested == 3 && mp <= (m.n >= 4 ? 16 : 32))
         return 3;
     if (requested == 2 && mp == 64)
         return 2;
@@ -310,14 +321,16 @@ hipError_t launch_user_sample(const qcl_model_s &m, const SampleArgs &sa, const 
 hipError_t launch_user_propagate(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
                                  double *partials, hipStream_t s);
 
-inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, int occ, const void *items,
+// wpc: workgroups per compute unit of the persistent launch (0: as many as
+// fit, else at most that many)
+inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, int occ, int wpc, const void *items,
                                int32_t n_items, int64_t total_tiles, unsigned long long *counter, hipStream_t s)
 {
     if (m.fast2)  // the transition rule is a template parameter of the two-state kernels
-        return launch_batch_n2(m.m, m.degree > 1, prec, scheme, items, n_items, total_tiles, counter, s);
+        return launch_batch_n2(m.m, m.degree > 1, prec, scheme, wpc, items, n_items, total_tiles, counter, s);
     const int mp = padded_modes(m.m), rb = m.rank_pad;
     return with_general(m, hipErrorNotSupported, [&](auto tag) {
-        return launch_batch_general_n(mp, rb, prec, occ, items, n_items, total_tiles, counter, s, tag);
+        return launch_batch_general_n(mp, rb, prec, occ, wpc, items, n_items, total_tiles, counter, s, tag);
     });
 }
 

@@ -84,7 +84,7 @@ class qcl_ensemble(C.Structure):
 class qcl_prop_desc(C.Structure):
     _fields_ = [("dt", C.c_double), ("n_steps", C.c_int32), ("cadence", C.c_int32),
                 ("n_out", C.c_int32), ("scheme", C.c_int32), ("seed", C.c_uint64),
-                ("occupancy", C.c_int32), ("reserved", C.c_int32)]
+                ("occupancy", C.c_int32), ("workgroups_per_cu", C.c_int32)]
 
 
 class qcl_batch_item(C.Structure):
@@ -398,15 +398,17 @@ class BatchJob:
     """Arguments of one qcl_propagate call, as an item of a batch."""
 
     def __init__(self, model: Model, ens: Ensemble, partials: Partials, dt: float, n_steps: int,
-                 cadence: int, seed: int, scheme: int = QCL_TRANS_NORMALIZED, occupancy: int = 0):
+                 cadence: int, seed: int, scheme: int = QCL_TRANS_NORMALIZED, occupancy: int = 0,
+                 workgroups_per_cu: int = 0):
         self.model, self.ens, self.partials = model, ens, partials
         self.dt, self.n_steps, self.cadence = float(dt), int(n_steps), int(cadence)
         self.seed, self.scheme, self.occupancy = int(seed), int(scheme), int(occupancy)
+        self.workgroups_per_cu = int(workgroups_per_cu)
 
     def item(self) -> qcl_batch_item:
         _match(self.model, self.ens, self.partials)
         pd = qcl_prop_desc(self.dt, self.n_steps, self.cadence, self.partials.n_out, self.scheme,
-                           self.seed, self.occupancy, 0)
+                           self.seed, self.occupancy, self.workgroups_per_cu)
         return qcl_batch_item(self.model.handle, C.pointer(self.ens.c), pd, self.partials.ptr)
 
 

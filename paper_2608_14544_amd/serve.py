@@ -96,13 +96,14 @@ class DeviceBackend:
         from . import qcl as Q
         self.Q = Q
         self.torch = torch
-        self.tuning = tuning  # tune.TuningTable: register-budget choice per kernel class
+        self.tuning = tuning  # tune.TuningTable: register budget and workgroups per CU per class
         Q.load_library()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         # descriptors are uploaded by a kernel on the same stream, so one
         # workspace serves every round
         self.ws = Q.Workspace()
         self._models: Dict[tuple, object] = {}
+        self.host_s = 0.0  # host time spent enqueueing rounds
 
     def _model(self, lvc):
         key = (lvc.name, lvc.hbar, lvc.mass.tobytes(), lvc.omega.tobytes(), lvc.v0.tobytes(), lvc.k.tobytes())
@@ -132,13 +133,19 @@ class DeviceBackend:
         return (m, ens, part)
 
     def advance(self, work):
-        """work: list of (handle, spec, n_steps); one batched launch."""
+        """work: list of (handle, spec, n_steps); one batched launch.  The
+        host time spent enqueueing it is added to ``host_s``."""
         Q = self.Q
-        occ = (lambda m, p: self.tuning.occupancy(m, p)) if self.tuning is not None else (lambda m, p: 0)
+        t0 = time.perf_counter()
+        tn = self.tuning
         jobs = [Q.BatchJob(h[0], h[1], h[2], s.workload.run.dt, n, s.workload.run.cadence,
-                           s.workload.run.seed, s.scheme, occupancy=occ(h[0], s.prec)) for h, s, n in work]
+                           s.workload.run.seed, s.scheme,
+                           occupancy=tn.occupancy(h[0], s.prec) if tn is not None else 0,
+                           workgroups_per_cu=tn.workgroups_per_cu(h[0], s.prec) if tn is not None else 0)
+                for h, s, n in work]
         with self.torch.cuda.stream(self.stream):
             Q.qcl_propagate_batch(jobs, self.ws, stream=self.stream)
+        self.host_s += time.perf_counter() - t0
 
     def finish(self, handle, spec: JobSpec):
         """Enqueues the reduction and the copy to host; returns a future."""

@@ -146,6 +146,40 @@ def test_register_budget_variants_bitwise(P, n_states, n_modes, budget):
     assert choice in (0, budget) and t.occupancy(P.Model(wl.model), "fp32") == choice
 
 
+@pytest.mark.parametrize("wpc", [1, 2])
+def test_workgroups_per_cu_bitwise(P, wpc):
+    """A cap on the workgroups per compute unit of the persistent launch
+    changes the launch shape only: every item of a mixed batch (two-state
+    closed form, general N, both precisions) is bitwise its uncapped result,
+    and items that differ in the cap run in separate launches of the same
+    call."""
+    import torch
+    mix = _mix()
+    ref = _batched(P, mix)
+    runs, jobs = [], []
+    for i, (wl, prec, scheme, T) in enumerate(mix):
+        r = wl.run
+        model, ens, part = _setup(P, wl, prec, T)
+        runs.append((model, ens, part, T))
+        jobs.append(P.BatchJob(model, ens, part, r.dt, r.n_steps, r.cadence, r.seed, scheme,
+                               workgroups_per_cu=wpc if i % 2 == 0 else 0))
+    P.qcl_propagate_batch(jobs)
+    torch.cuda.synchronize()
+    for i, (model, ens, part, T) in enumerate(runs):
+        got = (P.qcl_reduce_observables(model, part, T).cpu().numpy(), ens.to_numpy())
+        _assert_same(ref[i], got, f"item {i} wpc {wpc}")
+
+
+def test_tuner_workgroups_per_cu(P):
+    from paper_2608_14544_amd.tune import WPC_CANDIDATES, TuningTable, launch_class
+    wl = W.random_lvc(3, n_states=3, n_modes=20, n_traj=2000, n_steps=60, cadence=20)
+    t = TuningTable()
+    choice = t.tune_workgroups(wl, "fp32", n_traj=1 << 16, n_steps=20)
+    k = launch_class(P.Model(wl.model), "fp32")
+    print("workgroups per CU", t.wpc_timings, flush=True)
+    assert choice in WPC_CANDIDATES and t.wpc[k] == choice and set(t.wpc_timings[k]) == set(WPC_CANDIDATES)
+
+
 def test_batched_workload_full_size():
     """The 256-instance batched workload at full size in the benchmark's
     launch configuration (binary32, tuned register budgets, one batched

@@ -129,15 +129,20 @@ def test_tuning_classes_and_table_roundtrip(tmp_path):
     assert kernel_class(3, 40, 1, "fp32") == (3, 64, 1, "fp32")  # two-wave budget at 64 modes
     assert kernel_class(3, 100, 1, "fp32") is None         # no budget build above 64 modes
     assert kernel_class(4, 20, 1, "fp64") is None          # binary32 only
-    assert kernel_class(4, 20, 2, "fp32") == (4, 32, 4, "fp32")
+    assert kernel_class(4, 20, 2, "fp32") is None          # no budget build for four states at 32 modes
+    assert kernel_class(4, 12, 2, "fp32") == (4, 16, 4, "fp32")
+    assert kernel_class(3, 20, 2, "fp32") == (3, 32, 3, "fp32")
     t = TuningTable()
-    t.choice[(4, 32, 4, "fp32")] = 3
+    t.choice[(4, 16, 4, "fp32")] = 3
     t.choice[(3, 16, 1, "fp32")] = 0
     t.choice[(2, 64, 1, "fp32")] = 2
+    t.wpc[(4, 64, 1, 0, 0, "fp32")] = 2
+    t.wpc[(2, 3, 0, 0, 0, "fp32")] = 0
+    t.serving["quantum_work"] = 8e8
     path = str(tmp_path / "tuning.json")
     t.save(path)
     u = TuningTable(path)
-    assert u.choice == t.choice
+    assert u.choice == t.choice and u.wpc == t.wpc and u.quantum_work() == 8e8
 
 
 def test_failing_jobs_are_answered_not_fatal():
