@@ -88,7 +88,7 @@ def _crossing_model(coupling=5e-5):
 
 def test_general_fp32_near_degenerate(P):
     """The binary32 path refines the closest pair in binary64 below the gap
-    threshold; ensemble averages stay within 1e-3 (or 3 SE) of the oracle."""
+    threshold; ensemble averages stay within 1e-3 * max(1, rms) of the oracle."""
     wl = _crossing_model()
     out_g, st_g, _, _ = gpu_run(P, wl, prec="fp32")
     out_o, st_o, _, _ = oracle_run(wl)
