@@ -86,15 +86,52 @@ __device__ __forceinline__ void canon2(const Geo2<R> &g, R &c0, R &c1)
     c1 = g.x1 * n;
 }
 
-template <int M, typename R>
+// Mode classes of a linear model, fixed per kernel build.  With MT >= 0 the
+// first MT modes only tune the gap (K_01 = 0) and the others only couple the
+// two states (K_00 = K_11 = 0, so no bath force either); MT < 0 treats every
+// mode as both.  Linear-vibronic models are commonly of this form (tuning
+// modes of the totally symmetric irrep, coupling modes of the irrep of the
+// coupling).  The terms a build leaves out are products with exact zeros,
+// so it computes the same values as the general build (up to the sign of an
+// exact zero).
+template <int MT>
+__device__ constexpr bool tunes(int j) { return MT < 0 || j < MT; }
+template <int MT>
+__device__ constexpr bool couples(int j) { return MT < 0 || j >= MT; }
+
+template <int M, typename R, int MT>
 __device__ __forceinline__ void coupling_coords(const N2Const<M, R> &C, const R (&q)[M], R &dl, R &cc)
 {
     dl = C.dlt0;
     cc = C.c0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        dl = fma2(C.dlt[j], q[j], dl);
-        cc = fma2(C.cpl[j], q[j], cc);
+        if (tunes<MT>(j))
+            dl = fma2(C.dlt[j], q[j], dl);
+        if (couples<MT>(j))
+            cc = fma2(C.cpl[j], q[j], cc);
+    }
+}
+
+// dt (dl_v, c_v) = (sum_j p_j vdl_j, sum_j p_j vcp_j) over the modes of each class
+template <int M, typename R, int MT>
+__device__ __forceinline__ void velocity_coords(const N2Const<M, R> &C, const R (&p)[M], R &dlv, R &cv)
+{
+    constexpr int jc = MT < 0 ? 0 : MT;  // first coupling mode
+    dlv = R(0);
+    cv = R(0);
+    if constexpr (MT != 0) {
+        dlv = p[0] * C.vdl[0];
+#pragma unroll
+        for (int j = 1; j < M; ++j)
+            if (tunes<MT>(j))
+                dlv = fma2(p[j], C.vdl[j], dlv);
+    }
+    if constexpr (jc < M) {
+        cv = p[jc] * C.vcp[jc];
+#pragma unroll
+        for (int j = jc + 1; j < M; ++j)
+            cv = fma2(p[j], C.vcp[j], cv);
     }
 }
 
@@ -167,7 +204,9 @@ __device__ __forceinline__ Geo2<float> resolve64_poly(const double *__restrict__
 // Geometry at q.  binary32: a gap 2r below the model threshold is re-solved
 // in binary64 (a rare, divergent branch); an exact degeneracy can only
 // occur there, so it is checked there.  binary64: checked at every point.
-template <int M, typename R, bool POLY>
+// (r is compared with half the threshold: doubling is exact, so the
+// decision is the one on 2r.)
+template <int M, typename R, bool POLY, int MT = -1>
 __device__ __forceinline__ void geo_at(const N2Const<M, R> &C, const N2Extra<M, R, POLY> &Q, const R (&q)[M],
                                        Geo2<R> &g, uint32_t &flag)
 {
@@ -175,10 +214,10 @@ __device__ __forceinline__ void geo_at(const N2Const<M, R> &C, const N2Extra<M, 
     if constexpr (POLY)
         poly_coords<M, R>(C, Q, q, dl, cc);
     else
-        coupling_coords<M, R>(C, q, dl, cc);
+        coupling_coords<M, R, MT>(C, q, dl, cc);
     geo2<R>(dl, cc, g);
     if constexpr (sizeof(R) == 4) {
-        if (!(R(2) * g.r >= C.gap_thr)) {
+        if (!(g.r >= C.gap_half)) {
             if constexpr (POLY)
                 g = resolve64_poly<M>(Q.c64, q);
             else
@@ -188,7 +227,7 @@ __device__ __forceinline__ void geo_at(const N2Const<M, R> &C, const N2Extra<M, 
                 flag |= kFlagDegenerate;
         }
     } else {
-        if (!(R(2) * g.r > R(2.2250738585072014e-308)))
+        if (!(g.r > R(0x1p-1023)))  // 2r below the smallest normal double
             flag |= kFlagDegenerate;
     }
 }
@@ -362,8 +401,11 @@ __global__ __launch_bounds__(kBlock) void sample_n2_kernel(N2Const<M, double> C,
 // One walker between steps, in registers.  G_j = dl dlt_j + cc cpl_j (or,
 // with higher powers, dl phi^d'_j + cc phi^c'_j) is the element-independent
 // part of the Hellmann-Feynman force at the current point, so that
-// dE_{0,1}/dq_j = kbar_j -+ G_j/r; hr = (dt/2)/r and kx = s0 s1/(2 r^2) are
-// kept with it for the two kicks and the next coupling.
+// dE_{0,1}/dq_j = kbar_j -+ G_j/r; hr = (dt/4)/r and kx = s0 s1/(2 r^2) are
+// kept with it for the two kicks and the next coupling.  The element (a, b)
+// is held as the signs sa = 2a - 1, sb = 2b - 1 (a move negates one, and
+// a + b - 1 and a - b are (sa + sb)/2 and (sa - sb)/2, the halves folded
+// into hr and the phase factor exactly).
 template <int M, typename R, bool POLY>
 struct WalkerN2 {
     static constexpr int MP = POLY ? M : 1;
@@ -373,15 +415,15 @@ struct WalkerN2 {
     R SD[MP], SC[MP], SB[MP];  // polynomial slopes at the current point (POLY)
     R hr, kx, hsig, s1;
     double w, phase, r_old;
-    int a, b;
+    float sa, sb;
     uint32_t flag;
 };
 
 // geometry, force terms and the per-point factors at the walker's q
-template <int M, typename R, bool POLY>
+template <int M, typename R, bool POLY, int MT>
 __device__ __forceinline__ void point_n2(const N2Const<M, R> &C, const N2Extra<M, R, POLY> &Q, WalkerN2<M, R, POLY> &k)
 {
-    geo_at<M, R, POLY>(C, Q, k.q, k.g, k.flag);
+    geo_at<M, R, POLY, MT>(C, Q, k.q, k.g, k.flag);
     if constexpr (POLY) {
         poly_slopes<M, R>(Q, k.q, k.SD, k.SC, k.SB);
 #pragma unroll
@@ -389,17 +431,23 @@ __device__ __forceinline__ void point_n2(const N2Const<M, R> &C, const N2Extra<M
             k.G[j] = fma2(k.g.dl, k.SD[j], k.g.cc * k.SC[j]);
     } else {
 #pragma unroll
-        for (int j = 0; j < M; ++j)
-            k.G[j] = fma2(k.g.dl, C.dlt[j], k.g.cc * C.cpl[j]);
+        for (int j = 0; j < M; ++j) {
+            if constexpr (MT < 0)
+                k.G[j] = fma2(k.g.dl, C.dlt[j], k.g.cc * C.cpl[j]);
+            else if (tunes<MT>(j))
+                k.G[j] = k.g.dl * C.dlt[j];
+            else
+                k.G[j] = k.g.cc * C.cpl[j];
+        }
     }
-    k.hr = C.hdt * k.g.rinv;
+    k.hr = C.hdt2 * k.g.rinv;
     k.kx = k.hsig * (k.g.rinv * k.g.rinv);
 }
 
 // p += (dt/2) * mean force of element (a,b), h = (a + b - 1) (dt/2)/r:
 // (dt/2)(F_a + F_b)/2 = -hk q - hb - h G  (hb_j = (dt/2) phi^b'_j with
-// higher powers)
-template <int M, typename R, bool POLY>
+// higher powers; hb_j = 0 for coupling modes)
+template <int M, typename R, bool POLY, int MT>
 __device__ __forceinline__ void kick_n2(const N2Const<M, R> &C, WalkerN2<M, R, POLY> &k, R h)
 {
 #pragma unroll
@@ -408,13 +456,13 @@ __device__ __forceinline__ void kick_n2(const N2Const<M, R> &C, WalkerN2<M, R, P
         if constexpr (POLY)
             t = fma2(-C.hdt, k.SB[j], k.p[j]);
         else
-            t = k.p[j] - C.hb[j];
+            t = tunes<MT>(j) ? k.p[j] - C.hb[j] : k.p[j];
         k.p[j] = fma2(-h, k.G[j], fma2(-C.hk[j], k.q[j], t));
     }
 }
 
 // One step n -> n+1 of one walker; word is its Philox output for step n.
-template <int M, typename R, int SCHEME, bool POLY>
+template <int M, typename R, int SCHEME, bool POLY, int MT>
 __device__ __forceinline__ void step_n2(const N2Const<M, R> &C, const N2Extra<M, R, POLY> &Q, WalkerN2<M, R, POLY> &k,
                                         uint32_t word)
 {
@@ -436,57 +484,60 @@ __device__ __forceinline__ void step_n2(const N2Const<M, R> &C, const N2Extra<M,
             cv = fma2(vj, k.SC[j], cv);
         }
     } else {
-        dlv = k.p[0] * C.vdl[0];
-        cv = k.p[0] * C.vcp[0];
-#pragma unroll
-        for (int j = 1; j < M; ++j) {
-            dlv = fma2(k.p[j], C.vdl[j], dlv);
-            cv = fma2(k.p[j], C.vcp[j], cv);
-        }
+        velocity_coords<M, R, MT>(C, k.p, dlv, cv);
     }
-    const R x = fma2(k.g.dl, cv, -(k.g.cc * dlv)) * k.kx;
+    R xs;  // dl c_v - cc dl_v
+    if constexpr (!POLY && MT == 0)
+        xs = k.g.dl * cv;  // no tuning mode: dl_v = 0
+    else if constexpr (!POLY && MT == M)
+        xs = -(k.g.cc * dlv);  // no coupling mode: c_v = 0
+    else
+        xs = fma2(k.g.dl, cv, -(k.g.cc * dlv));
+    const R x = xs * k.kx;
     const R ax = __builtin_fabs(x);
     const R S = ax + ax;
-    const bool xpos = x > R(0);
-    int pick;     // -1 stay, 0 -> (1-a, b), 1 -> (a, 1-b)
-    double mul;   // weight factor (normalized rule) or divisor (linear rule, staying)
+    int pick;  // -1 stay, 0 -> (1-a, b), 1 -> (a, 1-b)
+    R mul;     // weight factor (normalized rule) or divisor (linear rule, staying)
     if (SCHEME == QCL_TRANS_LINEAR && S < R(1)) {
         pick = (u < ax) ? 0 : ((u < S) ? 1 : -1);
-        mul = (double)(R(1) - S);
+        mul = R(1) - S;
     } else {
         if (SCHEME == QCL_TRANS_LINEAR)
             k.flag |= kFlagFallback;
         const R one_s = R(1) + S;
         const R t = u * one_s;
         pick = (t < R(1)) ? -1 : ((t < R(1) + ax) ? 0 : 1);
-        mul = (double)one_s;
+        mul = one_s;
     }
     // sign of the chosen candidate's factor: f0 = (a ? -x : x), f1 = (b ? -x : x)
-    const bool fpos = (pick == 0) ? (xpos != (k.a != 0)) : (xpos != (k.b != 0));
+    const float sc = (pick == 0) ? k.sa : k.sb;
+    const bool fpos = (x > R(0)) != (sc > 0.0f);
     if (SCHEME == QCL_TRANS_LINEAR && S < R(1)) {
-        if (pick < 0) k.w = k.w / mul;
+        if (pick < 0) k.w = k.w / (double)mul;
         else k.w = fpos ? k.w : -k.w;
     } else {
-        k.w = k.w * mul;
-        k.w = (pick < 0 || fpos) ? k.w : -k.w;
+        // the factor's sign goes into the multiplier: w (-m) = -(w m) exactly
+        k.w = k.w * (double)((pick < 0 || fpos) ? mul : -mul);
     }
-    k.a = (pick == 0) ? 1 - k.a : k.a;
-    k.b = (pick == 1) ? 1 - k.b : k.b;
+    k.sa = (pick == 0) ? -k.sa : k.sa;
+    k.sb = (pick == 1) ? -k.sb : k.sb;
 
-    // 2. velocity Verlet on the mean force of the current element
-    const R lam = R(k.a + k.b - 1);
+    // 2. velocity Verlet on the mean force of the current element:
+    // (a + b - 1) (dt/2)/r = (sa + sb) hr
+    const R lam2 = R(k.sa + k.sb);
     const R xo0 = k.g.x0, xo1 = k.g.x1;
-    kick_n2<M, R, POLY>(C, k, lam * k.hr);
+    kick_n2<M, R, POLY, MT>(C, k, lam2 * k.hr);
 #pragma unroll
     for (int j = 0; j < M; ++j)
         k.q[j] = fma2(C.dtm[j], k.p[j], k.q[j]);
-    point_n2<M, R, POLY>(C, Q, k);
+    point_n2<M, R, POLY, MT>(C, Q, k);
     k.s1 = (fma2(xo0, k.g.x0, xo1 * k.g.x1) < R(0)) ? -k.s1 : k.s1;  // frame continuity
-    kick_n2<M, R, POLY>(C, k, lam * k.hr);
+    kick_n2<M, R, POLY, MT>(C, k, lam2 * k.hr);
 
-    // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar = 2 (a - b) r / hbar
+    // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar = 2 (a - b) r / hbar,
+    // (a - b) dt/hbar = (sa - sb) dt/(2 hbar)
     const double r_new = (double)k.g.r;
-    k.phase = fma2((double)(k.a - k.b), C.dt_hbar * (k.r_old + r_new), k.phase);
+    k.phase = fma2((double)(k.sa - k.sb), C.dt_hbar2 * (k.r_old + r_new), k.phase);
     k.r_old = r_new;
 }
 
@@ -497,7 +548,7 @@ __device__ __forceinline__ void step_n2(const N2Const<M, R> &C, const N2Extra<M,
 // block run one at a time with the word selected at run time.  Every copy
 // performs the same operations (no contraction), so the bits do not depend
 // on the copy.  Bins fall between stretches.
-template <int M, typename R, int SCHEME, bool POLY>
+template <int M, typename R, int SCHEME, bool POLY, int MT>
 __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C_in, const N2Extra<M, R, POLY> &Q,
                                                   const PropArgs &P, const EnsDev<R> &E,
                                                   double *__restrict__ partials, int64_t tile, BinLds &lds,
@@ -524,11 +575,11 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C_in, con
     const R p00 = E.u[0 * ld + li], p01 = E.u[1 * ld + li], p10 = E.u[2 * ld + li], p11 = E.u[3 * ld + li];
     k.w = E.w[li];
     k.phase = E.phase[li];
-    k.a = E.a[li];
-    k.b = E.b[li];
+    k.sa = E.a[li] ? 1.0f : -1.0f;
+    k.sb = E.b[li] ? 1.0f : -1.0f;
     k.flag = 0;
     k.hsig = R(0.5);
-    point_n2<M, R, POLY>(C, Q, k);
+    point_n2<M, R, POLY, MT>(C, Q, k);
     // column signs of the stored frame relative to the canonical one; the
     // product s0 s1 is invariant along the walker, s1 is tracked
     const R s0_in = fma2(p00, -k.g.x1, p10 * k.g.x0) < R(0) ? R(-1) : R(1);
@@ -549,25 +600,25 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C_in, con
         const int64_t stop = next_bin < end ? next_bin : end;
         int n = (int)(stop - step);
         for (; n > 0 && (step & 3); --n, ++step)
-            step_n2<M, R, SCHEME, POLY>(C, Q, k, pick_word(rnd, (uint32_t)(step & 3)));
+            step_n2<M, R, SCHEME, POLY, MT>(C, Q, k, pick_word(rnd, (uint32_t)(step & 3)));
         for (; n >= 4; n -= 4, step += 4) {
             rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
-            step_n2<M, R, SCHEME, POLY>(C, Q, k, rnd.x);
-            step_n2<M, R, SCHEME, POLY>(C, Q, k, rnd.y);
-            step_n2<M, R, SCHEME, POLY>(C, Q, k, rnd.z);
-            step_n2<M, R, SCHEME, POLY>(C, Q, k, rnd.w);
+            step_n2<M, R, SCHEME, POLY, MT>(C, Q, k, rnd.x);
+            step_n2<M, R, SCHEME, POLY, MT>(C, Q, k, rnd.y);
+            step_n2<M, R, SCHEME, POLY, MT>(C, Q, k, rnd.z);
+            step_n2<M, R, SCHEME, POLY, MT>(C, Q, k, rnd.w);
         }
         for (; n > 0; --n, ++step) {
             if ((step & 3) == 0)
                 rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
-            step_n2<M, R, SCHEME, POLY>(C, Q, k, pick_word(rnd, (uint32_t)(step & 3)));
+            step_n2<M, R, SCHEME, POLY, MT>(C, Q, k, pick_word(rnd, (uint32_t)(step & 3)));
         }
         // 4. output bin at global step next_bin
         if (step == next_bin) {
             if (obin < P.n_out) {
                 R c0, c1;
                 canon2<R>(k.g, c0, c1);
-                bin_n2<R>(lds, parity, live, k.a, k.b, k.w, k.phase, c0, c1, sig,
+                bin_n2<R>(lds, parity, live, k.sa > 0.0f, k.sb > 0.0f, k.w, k.phase, c0, c1, sig,
                           partials + (tile * P.n_out + obin) * tile_values(2));
             }
             ++obin;
@@ -592,8 +643,8 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C_in, con
         E.u[3 * ld + i] = k.s1 * c1;
         E.w[i] = k.w;
         E.phase[i] = k.phase;
-        E.a[i] = (uint8_t)k.a;
-        E.b[i] = (uint8_t)k.b;
+        E.a[i] = k.sa > 0.0f ? 1 : 0;
+        E.b[i] = k.sb > 0.0f ? 1 : 0;
         if (E.flags)
             E.flags[i] |= k.flag;
     }
@@ -605,13 +656,13 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C_in, con
 template <int M, typename R, bool POLY>
 constexpr int kN2Occupancy = (sizeof(R) == 4 && !POLY && M <= 4) ? 5 : 1;
 
-template <int M, typename R, int SCHEME, bool POLY>
+template <int M, typename R, int SCHEME, bool POLY, int MT = -1>
 __global__ __launch_bounds__(kBlock, (kN2Occupancy<M, R, POLY>)) void propagate_n2_kernel(N2Const<M, R> C, N2Extra<M, R, POLY> Q, PropArgs P,
                                                               EnsDev<R> E, double *__restrict__ partials)
 {
     __shared__ BinLds lds;
     int parity = 0;
-    propagate_n2_tile<M, R, SCHEME, POLY>(C, Q, P, E, partials, (int64_t)blockIdx.x, lds, parity);
+    propagate_n2_tile<M, R, SCHEME, POLY, MT>(C, Q, P, E, partials, (int64_t)blockIdx.x, lds, parity);
 }
 
 // Persistent launch over (instance, tile) work items of many two-state
@@ -643,7 +694,8 @@ __global__ __launch_bounds__(kBlock, (kN2Occupancy<M, R, POLY>)) void batch_n2_k
             if (items[mid].tile_begin <= item) lo = mid; else hi = mid - 1;
         }
         const BatchItemN2<M, R, POLY> &it = items[lo];
-        propagate_n2_tile<M, R, SCHEME, POLY>(it.C, it.Q, it.P, it.E, it.partials, item - it.tile_begin, lds, parity);
+        propagate_n2_tile<M, R, SCHEME, POLY, -1>(it.C, it.Q, it.P, it.E, it.partials, item - it.tile_begin, lds,
+                                                  parity);
         __syncthreads();
     }
 }
@@ -666,8 +718,10 @@ N2Const<M, R> make_const(const qcl_model_s &m, double dt)
     C.dlt0 = (R)m.dlt0;
     C.c0 = (R)m.c0;
     C.hdt = (R)hdt;
-    C.gap_thr = (R)(1e-4 * m.energy_scale);
+    C.hdt2 = (R)(0.5 * hdt);
+    C.gap_half = (R)(0.5 * (1e-4 * m.energy_scale));
     C.dt_hbar = dt / m.hbar;
+    C.dt_hbar2 = 0.5 * C.dt_hbar;
     C.c64 = m.d_model + m.c64_offset;
     return C;
 }
@@ -720,6 +774,39 @@ hipError_t sample_m(const qcl_model_s &m, const SampleArgs &sa, const qcl_ensemb
     return hipGetLastError();
 }
 
+// Mode-class builds exist for linear models with up to this many modes and
+// the normalized transition rule; other models take the general build.
+constexpr int kSplitMaxModes = 4;
+
+// The mode classes of a linear two-state model: the smallest MT such that
+// the modes before it have K_01 = 0 and the others K_00 = K_11 = 0, or -1
+// when the modes are not ordered that way.
+int mode_split(const qcl_model_s &m)
+{
+    for (int mt = 0; mt <= m.m; ++mt) {
+        bool ok = true;
+        for (int j = 0; j < m.m && ok; ++j)
+            ok = j < mt ? m.cpl[j] == 0.0 : (m.dlt[j] == 0.0 && m.kbar[j] == 0.0);
+        if (ok)
+            return mt;
+    }
+    return -1;
+}
+
+template <int M, typename R, int MT>
+void launch_split(int mt, dim3 grid, const N2Const<M, R> &C, const PropArgs &P, const EnsDev<R> &E, double *partials,
+                  hipStream_t s)
+{
+    if constexpr (MT <= M) {
+        if (mt == MT) {
+            hipLaunchKernelGGL((propagate_n2_kernel<M, R, QCL_TRANS_NORMALIZED, false, MT>), grid, dim3(kBlock), 0, s,
+                               C, N2Linear{}, P, E, partials);
+            return;
+        }
+        launch_split<M, R, MT + 1>(mt, grid, C, P, E, partials, s);
+    }
+}
+
 template <int M, typename R>
 void propagate_mr(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
                   hipStream_t s)
@@ -728,6 +815,13 @@ void propagate_mr(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_
     const PropArgs P{ens.step, pd.n_steps, pd.cadence, pd.n_out, pd.scheme, (uint32_t)pd.seed,
                      (uint32_t)(pd.seed >> 32)};
     const N2Const<M, R> C = make_const<M, R>(m, pd.dt);
+    if constexpr (M <= kSplitMaxModes) {
+        const int mt = m.degree > 1 || pd.scheme == QCL_TRANS_LINEAR ? -1 : mode_split(m);
+        if (mt >= 0) {
+            launch_split<M, R, 0>(mt, grid, C, P, ens_dev<R>(ens), partials, s);
+            return;
+        }
+    }
     if (m.degree > 1) {
         const N2Poly<M, R> Q = make_poly<M, R>(m);
         if (pd.scheme == QCL_TRANS_LINEAR)

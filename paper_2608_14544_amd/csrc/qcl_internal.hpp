@@ -33,8 +33,11 @@ struct N2Const {
     R dlt0;     // (V0_00 - V0_11)/2
     R c0;       // V0_01
     R hdt;      // dt/2
-    R gap_thr;  // binary32 path: gaps 2r below this are re-solved in binary64
+    R hdt2;     // dt/4 (the kick factor (a + b - 1) (dt/2)/r is (sa + sb) (dt/4)/r with sa = 2a - 1)
+    R gap_half; // binary32 path: points with r below this (a gap 2r below 1e-4 of the
+                // model's energy scale) are re-solved in binary64
     double dt_hbar;
+    double dt_hbar2;  // dt/(2 hbar), the phase factor for sa - sb = 2 (a - b)
     // binary64 copies [dlt0, c0, dlt_0..M-1, cpl_0..M-1] in device memory,
     // read only by the binary32 path's near-degenerate re-solve
     const double *c64;
