@@ -128,15 +128,24 @@ def run_curve(workload, n_traj: int, traj_offset: int, prec: str = "fp32", n_ste
               model: Optional["Q.Model"] = None, state: Optional[int] = None) -> Curve:
     """Sample, propagate and reduce ``n_traj`` walkers with global ids from
     ``traj_offset`` on the device; returns the population curve and the
-    device time of the run (sampling included)."""
+    time of the run (sampling, propagation and reduction; the buffers are
+    allocated before the clock starts)."""
     import torch
     r = workload.run
     S = r.n_steps if n_steps is None else int(n_steps)
+    n_out = S // r.cadence + 1
     model = model or Q.Model(workload.model)
+    ens = Q.Ensemble(model, int(n_traj), prec, int(traj_offset))
+    part = Q.Partials(model, int(n_traj), n_out)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out, ens = Q.run(workload, prec, n_traj=n_traj, n_steps=S, traj_offset=traj_offset, model=model)
+    Q.qcl_sample_initial(model, workload.init, r.seed, ens, part)
+    Q.qcl_propagate(model, ens, r.dt, S, r.cadence, r.seed, part, Q.QCL_TRANS_NORMALIZED)
+    out = Q.qcl_reduce_observables(model, part, int(n_traj))
+    torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
+    out = out.cpu().numpy()
+    del part
     fl = ens.tensors()["flags"][:n_traj]
     flags = {name: int(((fl & bit) != 0).sum().item()) for name, bit in
              (("nonfinite", Q.FLAG_NONFINITE), ("degenerate", Q.FLAG_DEGENERATE), ("resolved64", Q.FLAG_RESOLVED64))}

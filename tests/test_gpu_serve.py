@@ -86,3 +86,34 @@ def test_served_mixed_model_families_equal_alone(P):
     by_name = {r.name: r for r in results}
     for s in specs:
         assert np.array_equal(by_name[s.name].out, _alone(P, s.workload, s.prec)), s.name
+
+
+def test_served_fp64_jobs_match_oracle(P):
+    """Binary64 jobs of every batched model family through the server, admitted
+    at different times and advanced in quanta beside each other, against the
+    FP64 oracle run of the same job: every mean of every bin within
+    1e-9 * max(1, rms of its summed terms).  The served path returns only the
+    reduced observables, so no flip allowance is taken: at these sizes a
+    binary64 walker whose decision differs from the oracle's is not expected
+    (its uniform number would have to fall within ~1e-13 of a threshold)."""
+    from paper_2608_14544_amd.serve import DeviceBackend, JobSpec, Server
+    from parity import check_ensemble64, oracle_run
+    wls = [
+        W.spin_boson_1mode(n_traj=700, n_steps=80, cadence=8),
+        W.pyrazine_ci(n_traj=1000, n_steps=60, cadence=6),
+        W.random_lvc(5, n_states=3, n_modes=6, n_traj=600, n_steps=50, cadence=10),
+        W.random_lvc(9, n_states=4, n_modes=10, n_traj=500, n_steps=40, cadence=8),
+        W.pyrazine_qvc(n_traj=800, n_steps=40, cadence=8),
+        W.random_bilinear(42, n_states=3, n_modes=6, n_pairs=4, degree=3, n_traj=600, n_steps=40, cadence=10),
+    ]
+    specs = [JobSpec(wl, prec="fp64", name=f"job{i}") for i, wl in enumerate(wls)]
+    be = DeviceBackend()
+    fps = [be.footprint(s) for s in specs]
+    srv = Server(be, memory_budget=max(fps) * 3, max_slots=3, quantum_steps=16)
+    results = srv.run([0.003 * i for i in range(len(specs))], specs)
+    assert len(results) == len(specs) and not any(r.error for r in results)
+    assert srv.rounds > 3
+    by_name = {r.name: r for r in results}
+    for s in specs:
+        out_o = oracle_run(s.workload)[0]
+        check_ensemble64(by_name[s.name].out, out_o, s.workload.run.n_traj, label="served " + s.workload.model.name)
