@@ -92,6 +92,42 @@ def test_batch_bitwise_equals_solo(P):
         _assert_same(s, b, f"item {i}")
 
 
+def _classed_model(n_modes, mt, seed):
+    """A two-state linear model whose first ``mt`` modes only tune the gap
+    (K_01 = 0) and whose other modes only couple the states
+    (K_00 = K_11 = 0), with a constant coupling in V0."""
+    rng = np.random.default_rng(seed)
+    k = np.zeros((n_modes, 2, 2))
+    for j in range(n_modes):
+        if j < mt:
+            k[j] = np.diag(rng.uniform(-0.6, 0.6, 2))
+        else:
+            c = rng.uniform(-0.4, 0.4)
+            k[j] = [[0.0, c], [c, 0.0]]
+    model = W.LVCModel(name=f"classes_{mt}_of_{n_modes}", mass=rng.uniform(0.5, 2.0, n_modes),
+                       omega=rng.uniform(0.5, 1.5, n_modes), v0=[[-0.3, 0.05], [0.05, 0.3]], k=k)
+    init = W.InitSpec(kT=0.3, q0=np.zeros(n_modes), state=1)
+    return W.Workload(model, init, W.RunSpec(700, 90, 0.05, 9, seed))
+
+
+@pytest.mark.parametrize("n_modes,mt", [(1, 0), (1, 1), (3, 0), (3, 1), (3, 2), (3, 3), (4, 2), (4, 4)])
+def test_mode_class_builds_equal_general(P, n_modes, mt):
+    """Solo calls of these models (normalized rule, up to four modes) run the
+    two-state build specialised to the mode classes, batched calls the
+    general build: walkers and bins agree bit for bit in both precisions
+    (the class build only leaves out products with exact zeros), and the
+    binary64 run agrees with the oracle."""
+    wl = _classed_model(n_modes, mt, 100 + 10 * n_modes + mt)
+    for prec in ("fp32", "fp64"):
+        s = _solo(P, wl, prec, 0, 700)
+        b = _batched(P, [(wl, prec, 0, 700)])[0]
+        _assert_same(s, b, f"{wl.model.name} {prec}")
+    out_o, st_o, _, _ = oracle_run(wl)
+    out_g, st_g = s
+    flip = compare_walkers(st_g, st_o, rtol=1e-10, label=wl.model.name)
+    check_ensemble64(out_g, out_o, 700, flip, st_g, st_o, label=wl.model.name)
+
+
 def test_batch_sliced_equals_solo(P):
     """K-step slices of a batch (continuous-batching quanta) change nothing."""
     mix = _mix()[:6]
