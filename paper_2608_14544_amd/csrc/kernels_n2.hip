@@ -276,13 +276,16 @@ __device__ __forceinline__ void bin_n2(BinLds &L, int &parity, bool live, int a,
     const double ua1 = a ? d1 : d0;   // C_1a
     const double ub0 = b ? d0 : -d1;  // C_0b
     const double ub1 = b ? d1 : d0;   // C_1b
-    const double sg = (a == b) ? 1.0 : (double)sig;
-    const double cf[4] = {sg * (ua0 * ub0), sg * (ua0 * ub1), sg * (ua1 * ub0), sg * (ua1 * ub1)};
+    // the sign s0 s1 (off-diagonal elements) scales the weight: an exact
+    // sign change, the same bits as scaling each product
+    const bool flip = (a != b) && sig < R(0);
+    const double res = flip ? -re : re, ims = flip ? -im : im;
+    const double cf[4] = {ua0 * ub0, ua0 * ub1, ua1 * ub0, ua1 * ub1};
 #pragma unroll
     for (int p = 0; p < 2; ++p) {  // diabatic cells 2p and 2p + 1
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const double r = re * cf[2 * p + h], m = im * cf[2 * p + h];
+            const double r = res * cf[2 * p + h], m = ims * cf[2 * p + h];
             B.put(4 * h + 0, r);
             B.put(4 * h + 1, m);
             B.put(4 * h + 2, r * r);
@@ -506,7 +509,8 @@ __device__ __forceinline__ void step_n2(const N2Const<M, R> &C, const N2Extra<M,
             k.flag |= kFlagFallback;
         const R one_s = R(1) + S;
         const R t = u * one_s;
-        pick = (t < R(1)) ? -1 : ((t < R(1) + ax) ? 0 : 1);
+        const bool stay = t < R(1), first = t < R(1) + ax;
+        pick = stay ? -1 : (first ? 0 : 1);
         mul = one_s;
     }
     // sign of the chosen candidate's factor: f0 = (a ? -x : x), f1 = (b ? -x : x)

@@ -35,7 +35,7 @@ __device__ double kTaylorSinCos[18] = {
     0.5, -1.0 / 24.0, 1.0 / 720.0, -1.0 / 40320.0, 1.0 / 3628800.0, -1.0 / 479001600.0,
     1.0 / 87178291200.0, -1.0 / 20922789888000.0, 1.0 / 6402373705728000.0};
 
-__device__ __forceinline__ double reduce_half_pi(double x, long long &quadrant)
+__device__ __forceinline__ double reduce_half_pi(double x, int &quadrant)
 {
     constexpr double two_over_pi = 0.6366197723675814;
     constexpr double half_pi_hi = 0x1.921fb54442d18p+0;   // pi/2 rounded to binary64
@@ -43,12 +43,15 @@ __device__ __forceinline__ double reduce_half_pi(double x, long long &quadrant)
     const double k = rint(x * two_over_pi);
     double r = fma(-k, half_pi_hi, x);
     r = fma(-k, half_pi_lo, r);
-    quadrant = (long long)k & 3;
+    // k mod 4 from the low word of k + 1.5 * 2^52 (exact for |k| < 2^51,
+    // whose integer bits then fill the low mantissa bits)
+    const double kb = k + 0x1.8p52;
+    quadrant = (int)((uint32_t)__double_as_longlong(kb) & 3u);
     return r;
 }
 
 template <typename T>
-__device__ __forceinline__ void apply_quadrant(long long q, T sr, T cr, T &s, T &c)
+__device__ __forceinline__ void apply_quadrant(int q, T sr, T cr, T &s, T &c)
 {
     const T s0 = (q & 1) ? cr : sr;
     const T c0 = (q & 1) ? sr : cr;
@@ -59,7 +62,7 @@ __device__ __forceinline__ void apply_quadrant(long long q, T sr, T cr, T &s, T 
 __device__ __forceinline__ void sincos_phase(double x, double &s, double &c)
 {
     const double *__restrict__ t = kTaylorSinCos;
-    long long q;
+    int q;
     const double r = reduce_half_pi(x, q);
     const double r2 = r * r;
     double ps = t[7];
@@ -77,7 +80,7 @@ __device__ __forceinline__ void sincos_phase(double x, double &s, double &c)
 
 __device__ __forceinline__ void sincos_phase32(double x, float &s, float &c)
 {
-    long long q;
+    int q;
     const float r = (float)reduce_half_pi(x, q);
     const float r2 = r * r;
     float ps = -1.0f / 39916800.0f;       // -1/11!
