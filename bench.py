@@ -109,15 +109,19 @@ def coupling_slots(lvc) -> float:
 GOLDEN = os.path.join(ROOT, "tests", "golden", "pyrazine_ci_1e7_oracle.json")
 
 
-def oracle_accuracy(out, wl, n_traj, prec):
-    """Every bin of a full-size headline result against the oracle's run of
-    the same 1e7 walkers stored in tests/golden (written from the oracle
-    alone); None when the workload differs from the stored one."""
+def spin_boson_golden(kT):
+    return os.path.join(ROOT, "tests", "golden", f"spin_boson_ohmic_m3_kT{kT}_1e6_oracle.json")
+
+
+def oracle_accuracy(out, wl, n_traj, prec, golden=GOLDEN):
+    """Every bin of a full-size result against the oracle's run of the same
+    walkers stored in tests/golden (written from the oracle alone); None
+    when the workload differs from the stored one."""
     import numpy as np
     r = wl.run
-    if not os.path.exists(GOLDEN) or n_traj != r.n_traj:
+    if not os.path.exists(golden) or n_traj != r.n_traj:
         return None
-    with open(GOLDEN) as f:
+    with open(golden) as f:
         g = json.load(f)
     if (g["n_traj"], g["n_steps"], g["cadence"], g["seed"]) != (r.n_traj, r.n_steps, r.cadence, r.seed):
         return None
@@ -127,15 +131,16 @@ def oracle_accuracy(out, wl, n_traj, prec):
     err = np.abs(out[..., :2] - ref[..., :2])
     tol = 1e-9 if prec == "fp64" else 1e-3
     d_pop = np.abs(out[:, 0, 1, 1, 0] - ref[:, 0, 1, 1, 0])
-    dt_fs = r.dt * (wl.model.time_unit_fs or 1.0)
+    fs = wl.model.time_unit_fs
     se = ref[:, 0, 1, 1, 2]
     unresolved = np.nonzero(~(se < 0.01))[0]
     n_res = int(unresolved[0]) if len(unresolved) else len(se)
+    until = (n_res - 1) * r.cadence * r.dt * (fs or 1.0) if n_res else None
     return {
         "max_abs_upper_population_diff": float(d_pop.max()),
         "max_abs_upper_population_diff_resolved_bins": float(d_pop[:n_res].max()) if n_res else None,
         "resolved_bins": n_res,
-        "resolved_until_fs": (n_res - 1) * r.cadence * dt_fs if n_res else None,
+        ("resolved_until_fs" if fs else "resolved_until"): until,
         "bins_within_1e-3": int(np.count_nonzero(d_pop <= 1e-3)),
         "bins": int(d_pop.size),
         "max_err_over_rms_scaled_bound": float((err / (tol * np.maximum(1.0, rms))).max()),
@@ -267,7 +272,8 @@ def _oracle_other_legs():
 def spin_boson_leg(P, torch):
     """The 3-mode Ohmic spin-boson runs (1e6 walkers, 2000 steps) at kT 0.2
     and 1.0, FP32_ACC64 beside FP64, with the largest population difference
-    between the two over the bins the FP64 run resolves (SE < 0.01)."""
+    between the two over the bins the FP64 run resolves (SE < 0.01), and
+    every bin of each against the oracle's run of the same walkers."""
     import numpy as np
     import workloads as W
     out = []
@@ -284,10 +290,14 @@ def spin_boson_leg(P, torch):
         bad = np.nonzero(~(se < 0.01))[0]
         n_res = int(bad[0]) if len(bad) else len(se)
         dpop = max(float(np.max(np.abs(r32[:n_res, 0, i, i, 0] - r64[:n_res, 0, i, i, 0]))) for i in range(2))
+        gold = spin_boson_golden(kT)
         out.append({"kT": kT, "n_traj": r.n_traj, "n_steps": r.n_steps,
                     "fp32": {"value": r.n_traj * r.n_steps / (res["fp32"][0] / 1e3), "ms": res["fp32"][0]},
                     "fp64": {"value": r.n_traj * r.n_steps / (res["fp64"][0] / 1e3), "ms": res["fp64"][0]},
-                    "fp32_vs_fp64_max_abs_population_diff": dpop, "resolved_bins": n_res, "bins": len(se)})
+                    "fp32_vs_fp64_max_abs_population_diff": dpop, "resolved_bins": n_res, "bins": len(se),
+                    "fp32_vs_oracle": oracle_accuracy(r32, wl, r.n_traj, "fp32", gold),
+                    "fp64_vs_oracle": oracle_accuracy(r64, wl, r.n_traj, "fp64", gold),
+                    "oracle": f"FP64 CPU oracle run of the same 1e6 walkers ({os.path.relpath(gold, ROOT)})"})
         torch.cuda.empty_cache()
     return out
 

@@ -1,10 +1,11 @@
-"""The headline workload at full size against the oracle's full run.
+"""The full-size workloads against the oracle's full runs.
 
 ``pyrazine_ci`` (2-state 3-mode conical-intersection model, 1e7 walkers,
-1000 steps of 0.5 fs, bins every 10 steps) is run on the device in both
-precisions, one launch each as the benchmark does, and every bin of the
-reduced result is compared with the oracle's run of the same 1e7 walkers
-(``tests/golden/pyrazine_ci_1e7_oracle.json``, written by
+1000 steps of 0.5 fs, bins every 10 steps) and the 3-mode Ohmic spin-boson
+model at kT 0.2 and 1.0 (1e6 walkers, 2000 steps of 0.02) are run on the
+device in both precisions, one launch each as the benchmark does, and
+every bin of the reduced result is compared with the oracle's run of the
+same walkers (``tests/golden/*_oracle.json``, written by
 ``tests/golden/make_golden.py`` from the oracle only).
 
 Binary64: every mean within 1e-9 x max(1, rms of its terms), widened by the
@@ -29,7 +30,12 @@ import workloads as W
 from parity import check_ensemble32, check_ensemble64, flip_mask, oracle_state, rms_terms
 
 pytestmark = pytest.mark.gpu
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pyrazine_ci_1e7_oracle.json")
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+CASES = {
+    "pyrazine_ci": (W.pyrazine_ci, "pyrazine_ci_1e7_oracle.json"),
+    "spin_boson_kT0.2": (lambda: W.spin_boson_ohmic(kT=0.2), "spin_boson_ohmic_m3_kT0.2_1e6_oracle.json"),
+    "spin_boson_kT1.0": (lambda: W.spin_boson_ohmic(kT=1.0), "spin_boson_ohmic_m3_kT1.0_1e6_oracle.json"),
+}
 
 
 @pytest.fixture(scope="module")
@@ -41,11 +47,14 @@ def P():
     return pkg
 
 
-@pytest.fixture(scope="module")
-def golden():
-    with open(GOLDEN) as f:
+@pytest.fixture(scope="module", params=list(CASES))
+def golden(request):
+    make, fname = CASES[request.param]
+    with open(os.path.join(GOLDEN_DIR, fname)) as f:
         d = json.load(f)
-    wl = W.pyrazine_ci()
+    wl = make()
+    d["workload"] = wl
+    d["label"] = request.param
     r = wl.run
     assert (d["n_traj"], d["n_steps"], d["cadence"], d["seed"]) == (r.n_traj, r.n_steps, r.cadence, r.seed)
     assert d["dt"] == r.dt
@@ -55,9 +64,8 @@ def golden():
     return d
 
 
-def _run(P, prec):
+def _run(P, prec, wl):
     import torch
-    wl = W.pyrazine_ci()
     r = wl.run
     model = P.Model(wl.model)
     ens = P.Ensemble(model, r.n_traj, prec, zero=False)
@@ -86,7 +94,7 @@ def _group_digests(w, ab, group):
 
 
 def test_headline_fp64_every_bin_against_oracle(P, golden):
-    wl, out, w, ab, t = _run(P, "fp64")
+    wl, out, w, ab, t = _run(P, "fp64", golden["workload"])
     r = wl.run
     G = golden["group"]
     gw, gab = _group_digests(w, ab, G)
@@ -110,7 +118,7 @@ def test_headline_fp64_every_bin_against_oracle(P, golden):
         allow += float((np.abs(g["w"][flip]).sum() + np.abs(o["w"][flip]).sum()) / r.n_traj)
     print(f"walkers whose decisions differ from the oracle's: {n_flip} of {r.n_traj}", flush=True)
     assert n_flip <= 1e-4 * r.n_traj
-    check_ensemble64(out, golden["out"], r.n_traj, tol=1e-9, label="pyrazine_ci 1e7 fp64", extra_allow=allow)
+    check_ensemble64(out, golden["out"], r.n_traj, tol=1e-9, label=golden["label"] + " fp64", extra_allow=allow)
     # standard errors too, at the same bound relative to the terms' rms
     rms = rms_terms(golden["out"], r.n_traj)
     d_se = np.abs(out[..., 2:] - golden["out"][..., 2:])
@@ -118,12 +126,12 @@ def test_headline_fp64_every_bin_against_oracle(P, golden):
 
 
 def test_headline_fp32_every_bin_against_oracle(P, golden):
-    wl, out, w, ab, t = _run(P, "fp32")
+    wl, out, w, ab, t = _run(P, "fp32", golden["workload"])
     r = wl.run
     flags = t["flags"][:r.n_traj].cpu().numpy().view(np.uint32)
     print(f"flags: resolved in binary64 {int(np.count_nonzero(flags & 4))}, "
           f"non-finite {int(np.count_nonzero(flags & 1))} (oracle {golden['nonfinite']})", flush=True)
-    check_ensemble32(out, golden["out"], r.n_traj, tol=1e-3, label="pyrazine_ci 1e7 fp32")
+    check_ensemble32(out, golden["out"], r.n_traj, tol=1e-3, label=golden["label"] + " fp32")
     P_up = out[:, 0, 1, 1, 0]
     P_or = golden["out"][:, 0, 1, 1, 0]
     within = np.abs(P_up - P_or) <= 1e-3
