@@ -656,9 +656,13 @@ __device__ __forceinline__ void propagate_n2_tile(const N2Const<M, R> &C_in, con
 
 // Resident workgroups per CU the propagation kernels are built for: five
 // for the binary32 linear models up to 4 modes (the step loop and the bins
-// fit 96 registers, five waves per SIMD), no constraint otherwise.
+// fit 96 registers, five waves per SIMD), four for the models with higher
+// powers up to 3 modes and, in binary32, 4 modes (128 registers), no
+// constraint otherwise.
 template <int M, typename R, bool POLY>
-constexpr int kN2Occupancy = (sizeof(R) == 4 && !POLY && M <= 4) ? 5 : 1;
+constexpr int kN2Occupancy = (sizeof(R) == 4 && !POLY && M <= 4)            ? 5
+                             : (POLY && (M <= 3 || (sizeof(R) == 4 && M <= 4))) ? 4
+                                                                                 : 1;
 
 template <int M, typename R, int SCHEME, bool POLY, int MT = -1>
 __global__ __launch_bounds__(kBlock, (kN2Occupancy<M, R, POLY>)) void propagate_n2_kernel(N2Const<M, R> C, N2Extra<M, R, POLY> Q, PropArgs P,
