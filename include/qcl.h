@@ -274,8 +274,9 @@ int32_t qcl_model_pairs(qcl_model model);
  * desc supplies N (2..4), M (1..QCL_MAX_MODES_SOURCE), the masses, hbar and
  * the frequencies omega of the harmonic reference that the Wigner initial
  * state is drawn from (qcl_sample_initial); v0 and k are not read.  Such a
- * model propagates binary64 ensembles only (UNSUPPORTED for binary32) and
- * is not accepted in batches.  Errors: INVALID_ARG (as qcl_create_model
+ * model propagates binary64 ensembles only (UNSUPPORTED for binary32); in
+ * qcl_propagate_batch the items of one such model form a class of their
+ * own (its compiled program holds a persistent batched kernel).  Errors: INVALID_ARG (as qcl_create_model
  * for the sizes and the masses and frequencies; NULL source; n_params
  * outside [0, QCL_MAX_PARAMS] or a non-finite parameter; a source that does
  * not compile, with the compiler's log in qcl_last_error), DEVICE (no
@@ -377,8 +378,9 @@ qcl_status qcl_batch_workspace_bytes(const qcl_batch_item *items, int32_t n_item
  * one qcl_propagate would give for it alone.
  *
  * Items that need the same kernel (two-state closed form with the same
- * mode count; or the same state count N and padded mode count; same
- * precision and transition rule) form one class.  Each class runs as ONE
+ * mode count; or the same state count N and padded mode count; or the same
+ * model with a supplied potential; same precision and transition rule)
+ * form one class.  Each class runs as ONE
  * persistent launch (about one workgroup per free slot of the device);
  * its workgroups take (item, tile of QCL_TILE walkers) pairs from a device
  * counter, heaviest tiles first, so uneven instances balance across the

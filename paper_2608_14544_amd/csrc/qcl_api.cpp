@@ -228,6 +228,7 @@ qcl_status check_reduce(qcl_model m, const double *partials, int64_t n_traj, int
 struct BatchClass {
     bool fast2;
     int n, modes, prec, scheme, occ, wpc;
+    const qcl_model_s *src;      // the model, for a supplied potential (its own program); else null
     std::vector<int32_t> order;  // item indices, most expensive tile first
     size_t item_bytes = 0;
     size_t counter_offset = 0;   // one 8-byte tile counter
@@ -295,9 +296,8 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
         if (it.ens->n_traj == 0 || it.prop.n_steps == 0)
             continue;
         const qcl_model_s &m = *it.model;
-        if (m.source)
-            return fail(QCL_ERR_UNSUPPORTED, "item %d: a model with a supplied potential runs only in qcl_propagate", i);
-        // general kernels are specialised on padded modes and rank bucket
+        // general kernels are specialised on padded modes and rank bucket;
+        // a model with a supplied potential is a class of its own (its program)
         const int poly = m.degree > 1 ? 1 : 0;
         const int modes = m.fast2 ? m.m + 16 * poly
                                   : qcl::padded_modes(m.m) * 64 + m.rank_pad + 32 * poly + 16 * (m.n_pairs > 0) +
@@ -305,13 +305,14 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
                                         4 * (m.n_pairs > 0 && qcl::sq_pad(m.n_sq) == qcl::kSq);
         BatchClass *c = nullptr;
         const int occ = qcl::occupancy_variant(m, it.ens->prec, it.prop.occupancy);
+        const qcl_model_s *src = m.source ? &m : nullptr;
         for (BatchClass &k : plan.classes)
             if (k.fast2 == m.fast2 && k.n == m.n && k.modes == modes && k.prec == it.ens->prec &&
-                k.scheme == it.prop.scheme && k.occ == occ && k.wpc == it.prop.workgroups_per_cu)
+                k.scheme == it.prop.scheme && k.occ == occ && k.wpc == it.prop.workgroups_per_cu && k.src == src)
                 c = &k;
         if (!c) {
             plan.classes.push_back(
-                BatchClass{m.fast2, m.n, modes, it.ens->prec, it.prop.scheme, occ, it.prop.workgroups_per_cu});
+                BatchClass{m.fast2, m.n, modes, it.ens->prec, it.prop.scheme, occ, it.prop.workgroups_per_cu, src});
             c = &plan.classes.back();
             c->item_bytes = qcl::batch_item(m, *it.ens, it.prop, nullptr, 0, nullptr);
             if (c->item_bytes == 0)

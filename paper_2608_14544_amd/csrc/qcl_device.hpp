@@ -65,6 +65,19 @@ struct UserArgs {
     double rot_eps;  // Jacobi: rotate while |a_pq| > rot_eps * ||A||_F
 };
 
+// One (instance, tile) work item of a batched call for a model with a
+// supplied potential: the same layout on the host, which writes it, and in
+// the run-time compiled kernel, which reads it
+struct UserBatchItem {
+    UserArgs A;
+    PropArgs P;
+    EnsDev<double> E;
+    double *partials;
+    int64_t tile_begin;
+};
+static_assert(sizeof(PropArgs) == 40 && sizeof(EnsDev<double>) == 88 && sizeof(UserBatchItem) == 176,
+              "the batch descriptor must have one layout on the host and in the compiled program");
+
 // One bin of one tile's partials: the 8 N^2 sums [2][N][N][Re, Im, Re^2,
 // Im^2], then the number of walkers excluded from the bin (non-finite weight
 // or phase), stored as a double so that the tile reduction adds it exactly.

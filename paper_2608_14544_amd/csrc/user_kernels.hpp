@@ -141,13 +141,12 @@ __device__ __forceinline__ void user_sample(const SampleArgs &S, const UserArgs 
 
 // All steps of one tile of kBlock walkers (the whole workgroup calls it).
 template <int N, int M>
-__device__ __forceinline__ void user_propagate(const UserArgs &A, const PropArgs &P, const EnsDev<double> &E,
-                                               const double (&inv_mass)[M], double *__restrict__ partials,
-                                               BinLds &lds)
+__device__ __forceinline__ void user_propagate_tile(const UserArgs &A, const PropArgs &P, const EnsDev<double> &E,
+                                                    const double (&inv_mass)[M], double *__restrict__ partials,
+                                                    int64_t tile, BinLds &lds, int &parity)
 {
     constexpr int T = kTri<N>;
-    int parity = 0;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = tile * kBlock + threadIdx.x;
     const bool live = i < E.n_traj;
     const int64_t li = live ? i : E.n_traj - 1;
     const int64_t ld = E.ld;
@@ -226,7 +225,7 @@ __device__ __forceinline__ void user_propagate(const UserArgs &A, const PropArgs
         // 4. output bin at global step next_bin
         if (step == next_bin && next_bin / P.cadence < P.n_out) {
             bin_store<N, double>(lds, parity, live, a, b, w, phase, f,
-                                 partials + ((int64_t)blockIdx.x * P.n_out + next_bin / P.cadence) * tile_values(N));
+                                 partials + (tile * P.n_out + next_bin / P.cadence) * tile_values(N));
         }
     }
     if (!(__builtin_isfinite(w) && __builtin_isfinite(phase)))
@@ -249,6 +248,45 @@ __device__ __forceinline__ void user_propagate(const UserArgs &A, const PropArgs
         E.b[i] = (uint8_t)b;
         if (E.flags)
             E.flags[i] |= flag;
+    }
+}
+
+template <int N, int M>
+__device__ __forceinline__ void user_propagate(const UserArgs &A, const PropArgs &P, const EnsDev<double> &E,
+                                               const double (&inv_mass)[M], double *__restrict__ partials,
+                                               BinLds &lds)
+{
+    int parity = 0;
+    user_propagate_tile<N, M>(A, P, E, inv_mass, partials, (int64_t)blockIdx.x, lds, parity);
+}
+
+// Persistent launch over the (instance, tile) items of many ensembles of
+// this model: items are taken from a device counter (descriptors sorted by
+// decreasing work per tile), as in the built-in batched kernels.
+template <int N, int M>
+__device__ __forceinline__ void user_batch(const UserBatchItem *__restrict__ items, int32_t n_items,
+                                           int64_t total_tiles, unsigned long long *counter,
+                                           const double (&inv_mass)[M], BinLds &lds, long long &item_sh)
+{
+    int parity = 0;
+    for (;;) {
+        if (threadIdx.x == 0)
+            item_sh = (long long)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const long long raw = item_sh;
+        const long long item = (long long)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(raw >> 32)) << 32) |
+                                           (uint32_t)__builtin_amdgcn_readfirstlane((int)raw));
+        __syncthreads();
+        if (item >= total_tiles)
+            break;
+        int lo = 0, hi = n_items - 1;  // last descriptor with tile_begin <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].tile_begin <= item) lo = mid; else hi = mid - 1;
+        }
+        const UserBatchItem &it = items[lo];
+        user_propagate_tile<N, M>(it.A, it.P, it.E, inv_mass, it.partials, item - it.tile_begin, lds, parity);
+        __syncthreads();
     }
 }
 

@@ -33,6 +33,7 @@ namespace {
 
 constexpr const char *kSampleName = "qcl_user_sample_kernel";
 constexpr const char *kPropagateName = "qcl_user_propagate_kernel";
+constexpr const char *kBatchName = "qcl_user_batch_kernel";
 
 // the same rotation threshold as the built-in binary64 kernels
 constexpr double kRotEps64 = 64.0 * 1.1102230246251565e-16;
@@ -90,6 +91,13 @@ std::string program_text(const qcl_model_s &m, const char *source, const double 
          "{\n"
          "    __shared__ qcl::BinLds lds;\n"
          "    qcl::user_propagate<QCL_N, QCL_M>(A, P, E, qcl_inv_mass, partials, lds);\n"
+         "}\n"
+         "extern \"C\" __global__ __launch_bounds__(QCL_TILE) void qcl_user_batch_kernel(\n"
+         "    const qcl::UserBatchItem *items, int32_t n_items, int64_t total_tiles, unsigned long long *counter)\n"
+         "{\n"
+         "    __shared__ qcl::BinLds lds;\n"
+         "    __shared__ long long item_sh;\n"
+         "    qcl::user_batch<QCL_N, QCL_M>(items, n_items, total_tiles, counter, qcl_inv_mass, lds, item_sh);\n"
          "}\n";
     return s;
 }
@@ -153,10 +161,12 @@ qcl_status user_load(qcl_model_s &m)
     hipError_t e = hipModuleLoadData(&mod, m.user_code.data());
     if (e != hipSuccess)
         return set_error(QCL_ERR_DEVICE, "hipModuleLoadData: %s", hipGetErrorString(e));
-    hipFunction_t fs = nullptr, fp = nullptr;
+    hipFunction_t fs = nullptr, fp = nullptr, fb = nullptr;
     e = hipModuleGetFunction(&fs, mod, kSampleName);
     if (e == hipSuccess)
         e = hipModuleGetFunction(&fp, mod, kPropagateName);
+    if (e == hipSuccess)
+        e = hipModuleGetFunction(&fb, mod, kBatchName);
     if (e != hipSuccess) {
         (void)hipModuleUnload(mod);
         return set_error(QCL_ERR_DEVICE, "hipModuleGetFunction: %s", hipGetErrorString(e));
@@ -164,6 +174,7 @@ qcl_status user_load(qcl_model_s &m)
     m.user_module = mod;
     m.user_sample = (void *)fs;
     m.user_propagate = (void *)fp;
+    m.user_batch = (void *)fb;
     return QCL_OK;
 }
 
@@ -171,7 +182,7 @@ void user_release(qcl_model_s &m)
 {
     if (m.user_module)
         (void)hipModuleUnload((hipModule_t)m.user_module);
-    m.user_module = m.user_sample = m.user_propagate = nullptr;
+    m.user_module = m.user_sample = m.user_propagate = m.user_batch = nullptr;
 }
 
 hipError_t launch_user_sample(const qcl_model_s &m, const SampleArgs &sa_in, const qcl_ensemble &ens,
@@ -196,6 +207,36 @@ hipError_t launch_user_propagate(const qcl_model_s &m, const qcl_ensemble &ens, 
     void *args[] = {&A, &P, &E, &partials};
     return hipModuleLaunchKernel((hipFunction_t)m.user_propagate, (unsigned)n_tiles(ens.n_traj), 1, 1, kBlock, 1, 1,
                                  0, s, args, nullptr);
+}
+
+size_t batch_item_user(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
+                       int64_t tile_begin, void *out)
+{
+    if (out) {
+        UserBatchItem it{};
+        it.A = user_args(m, pd.dt);
+        it.P = PropArgs{ens.step, pd.n_steps, pd.cadence, pd.n_out, pd.scheme, (uint32_t)pd.seed,
+                        (uint32_t)(pd.seed >> 32), m.m};
+        it.E = ens64(ens);
+        it.partials = partials;
+        it.tile_begin = tile_begin;
+        std::memcpy(out, &it, sizeof(it));
+    }
+    return sizeof(UserBatchItem);
+}
+
+hipError_t launch_user_batch(const qcl_model_s &m, int wpc, const void *items, int32_t n_items, int64_t total_tiles,
+                             unsigned long long *counter, hipStream_t s)
+{
+    int cus = 0, per_cu = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (hipFunction_t)m.user_batch, kBlock, 0);
+    const int64_t grid = persistent_grid(total_tiles, cus, per_cu, wpc);
+    const UserBatchItem *it = (const UserBatchItem *)items;
+    void *args[] = {&it, &n_items, &total_tiles, &counter};
+    return hipModuleLaunchKernel((hipFunction_t)m.user_batch, (unsigned)grid, 1, 1, kBlock, 1, 1, 0, s, args,
+                                 nullptr);
 }
 
 }  // namespace qcl

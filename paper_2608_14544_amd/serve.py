@@ -105,8 +105,24 @@ class DeviceBackend:
         self._models: Dict[tuple, object] = {}
         self.host_s = 0.0  # host time spent enqueueing rounds
 
+    @staticmethod
+    def _model_key(lvc):
+        """Everything that defines a model's device tables (or, for a
+        supplied potential, its compiled program)."""
+        key = [lvc.name, lvc.hbar, np.asarray(lvc.mass).tobytes(), np.asarray(lvc.omega).tobytes(),
+               np.asarray(lvc.v0).tobytes(), np.asarray(lvc.k).tobytes()]
+        poly = getattr(lvc, "poly", None)
+        key.append(None if poly is None else np.asarray(poly).tobytes())
+        bil = getattr(lvc, "bilinear", None)
+        key.append(None if bil is None else tuple((i, j, np.asarray(B).tobytes()) for i, j, B in bil))
+        src = getattr(lvc, "hip_source", None)
+        key.append(src)
+        params = getattr(lvc, "params", None)
+        key.append(None if params is None else np.asarray(params, dtype=np.float64).tobytes())
+        return tuple(key)
+
     def _model(self, lvc):
-        key = (lvc.name, lvc.hbar, lvc.mass.tobytes(), lvc.omega.tobytes(), lvc.v0.tobytes(), lvc.k.tobytes())
+        key = self._model_key(lvc)
         m = self._models.get(key)
         if m is None:
             m = self.Q.Model(lvc)

@@ -83,7 +83,10 @@ def kernel_class(n_states: int, n_modes: int, rank: int, prec: str) -> Optional[
 def launch_class(model: "Q.Model", prec: str) -> tuple:
     """The kernel a batch item of ``model`` runs: the closed-form two-state
     kernels per mode count, the general kernels per padded modes and rank
-    bucket, each per model form and precision."""
+    bucket, each per model form and precision; a model with a supplied
+    potential runs the kernel of its own program."""
+    if getattr(model, "is_source", False):
+        return ("source", int(model.handle.value), prec)
     n, m = int(model.n_states), int(model.n_modes)
     closed = n == 2 and m <= 8 and not getattr(model, "n_pairs", 0)
     modes = m if closed else padded_modes(m)

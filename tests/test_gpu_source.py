@@ -81,8 +81,7 @@ def test_source_split_run_bitwise(P):
     assert np.array_equal(out1, out2)
 
 
-def test_source_rejects_fp32_and_batches(P):
-    import ctypes as C
+def test_source_rejects_fp32(P):
     wl = CASES["morse"]()
     model = P.Model(wl.model)
     with pytest.raises(P.QCLError) as e:
@@ -90,17 +89,82 @@ def test_source_rejects_fp32_and_batches(P):
         part = P.Partials(model, 256, 2)
         P.qcl_sample_initial(model, wl.init, 1, ens, part)
     assert e.value.status == P.QCL_ERR_UNSUPPORTED
-    ens = P.Ensemble(model, 256, "fp64")
-    part = P.Partials(model, 256, 3)
-    P.qcl_sample_initial(model, wl.init, 1, ens, part)
-    L = P.load_library()
-    item = P.qcl.qcl_batch_item(model.handle, C.pointer(ens.c),
-                                P.qcl.qcl_prop_desc(0.05, 10, 10, 3, 0, 1, 0, 0), part.ptr)
-    items = (P.qcl.qcl_batch_item * 1)(item)
-    nbytes = C.c_size_t()
-    st = L.qcl_batch_workspace_bytes(items, 1, C.byref(nbytes))
-    assert st == P.QCL_ERR_UNSUPPORTED
-    assert b"supplied potential" in L.qcl_last_error()
+
+
+def _setup(P, wl, T, model=None):
+    r = wl.run
+    model = model or P.Model(wl.model)
+    ens = P.Ensemble(model, T, "fp64")
+    part = P.Partials(model, T, r.n_steps // r.cadence + 1)
+    P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
+    return model, ens, part
+
+
+def _solo(P, wl, T, scheme=0, model=None):
+    model, ens, part = _setup(P, wl, T, model)
+    r = wl.run
+    P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part, scheme)
+    return P.qcl_reduce_observables(model, part, T).cpu().numpy(), ens.to_numpy()
+
+
+def _batched(P, mix, slices=(None,)):
+    import torch
+    runs = [(_setup(P, wl, T, model), wl, scheme, T) for wl, T, scheme, model in mix]
+    ws = P.Workspace()
+    done = [0] * len(runs)
+    for frac in slices:
+        jobs = []
+        for i, ((model, ens, part), wl, scheme, T) in enumerate(runs):
+            r = wl.run
+            n = r.n_steps - done[i] if frac is None else min(r.n_steps - done[i], int(r.n_steps * frac))
+            done[i] += n
+            jobs.append(P.BatchJob(model, ens, part, r.dt, n, r.cadence, r.seed, scheme))
+        P.qcl_propagate_batch(jobs, ws)
+    outs = [(P.qcl_reduce_observables(model, part, T).cpu().numpy(), ens.to_numpy())
+            for (model, ens, part), wl, scheme, T in runs]
+    torch.cuda.synchronize()
+    return outs
+
+
+@pytest.mark.parametrize("slices", [(None,), (0.3, 0.3, None)], ids=["whole", "sliced"])
+def test_source_batch_bitwise_equals_solo(P, slices):
+    """Items of two supplied-potential models (one class each, the persistent
+    kernel compiled into each model's program) beside a built-in item, whole
+    and in K-step slices: every item bitwise its solo run."""
+    morse = W.morse_coupled(n_traj=3000, n_steps=160, cadence=10)
+    m_morse = P.Model(morse.model)
+    src, _ = _lvc_source(7, 3, 4, n_traj=2000, n_steps=150, cadence=15)
+    m_src = P.Model(src.model)
+    builtin = W.random_lvc(8, n_states=3, n_modes=4, n_traj=900, n_steps=100, cadence=10)
+    mix = [(morse, 3000, 0, m_morse), (W.morse_coupled(n_traj=777, n_steps=97, cadence=7), 777, 0, m_morse),
+           (src, 2000, 0, m_src), (src, 513, 1, m_src), (builtin, 900, 0, None)]
+    solo = [_solo(P, wl, T, scheme, model) for wl, T, scheme, model in mix]
+    batch = _batched(P, mix, slices)
+    for k, (s, b) in enumerate(zip(solo, batch)):
+        for key in s[1]:
+            assert np.array_equal(s[1][key], b[1][key]), (k, key)
+        assert np.array_equal(s[0], b[0]), k
+
+
+def test_source_served_equal_alone(P):
+    """Supplied-potential jobs through the server beside built-in jobs, each
+    result bitwise the job run alone."""
+    from paper_2608_14544_amd.serve import DeviceBackend, JobSpec, Server
+    wls = [W.morse_coupled(n_traj=3000, n_steps=160, cadence=10),
+           W.pyrazine_ci(n_traj=2000, n_steps=60, cadence=6),
+           _lvc_source(7, 3, 4, n_traj=1500, n_steps=90, cadence=15)[0],
+           W.morse_coupled(n_traj=1000, n_steps=80, cadence=8)]
+    specs = [JobSpec(wl, prec="fp64", name=f"job{i}") for i, wl in enumerate(wls)]
+    be = DeviceBackend()
+    fps = [be.footprint(s) for s in specs]
+    srv = Server(be, memory_budget=max(fps) * 3, max_slots=3, quantum_steps=16)
+    results = srv.run([0.002 * i for i in range(len(specs))], specs)
+    assert len(results) == len(specs) and not any(r.error for r in results), [r.error for r in results]
+    by_name = {r.name: r for r in results}
+    for s in specs:
+        r = s.workload.run
+        out = _solo(P, s.workload, r.n_traj)[0]
+        assert np.array_equal(by_name[s.name].out, out), s.name
 
 
 def test_source_compile_error_is_reported(P):
