@@ -525,11 +525,11 @@ def general_leg(P, torch, n_traj=1 << 20, n_steps=200):
 
 
 def source_leg(P, torch, n_traj=1 << 20, n_steps=200):
-    """Models with a supplied potential (binary64): the coupled Morse model,
-    and a 3-state 4-mode linear-vibronic model both as a supplied potential
-    and on the built-in general kernels (the cost of the generic path);
-    walker-steps/s of one qcl_propagate call, and the time to build the
-    model (run-time compilation)."""
+    """Models with a supplied potential: the coupled Morse model, and a
+    3-state 4-mode linear-vibronic model both as a supplied potential and on
+    the built-in general kernels (the cost of the generic path); in binary64
+    and binary32, walker-steps/s of one qcl_propagate call, and the time to
+    build the model (run-time compilation)."""
     import workloads as W
     lvc = W.random_lvc(7, n_states=3, n_modes=4)
     cases = [("morse_coupled", W.morse_coupled()), ("random_lvc_3_4_source", W.Workload(
@@ -540,23 +540,27 @@ def source_leg(P, torch, n_traj=1 << 20, n_steps=200):
         t0 = time.perf_counter()
         model = P.Model(wl.model)
         build_s = time.perf_counter() - t0
-        ens = P.Ensemble(model, n_traj, "fp64", zero=False)
-        part = P.Partials(model, n_traj, n_steps // r.cadence + 1)
-        P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
-        P.qcl_propagate(model, ens, r.dt, r.cadence, r.cadence, r.seed, part)  # warm-up
-        torch.cuda.synchronize()
-        s = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        P.qcl_propagate(model, ens, r.dt, n_steps - r.cadence, r.cadence, r.seed, part, 0, s)
-        e1.record(s)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        rows.append({"model": name, "n_states": wl.model.n_states, "n_modes": wl.model.n_modes, "n_traj": n_traj,
-                     "n_steps": n_steps - r.cadence, "ms": ms, "prec": "fp64",
-                     "value": n_traj * (n_steps - r.cadence) / (ms / 1e3), "model_build_s": build_s})
-        del ens, part, model
-        torch.cuda.empty_cache()
+        row = {"model": name, "n_states": wl.model.n_states, "n_modes": wl.model.n_modes, "n_traj": n_traj,
+               "n_steps": n_steps - r.cadence, "model_build_s": build_s}
+        for prec in ("fp64", "fp32"):
+            ens = P.Ensemble(model, n_traj, prec, zero=False)
+            part = P.Partials(model, n_traj, n_steps // r.cadence + 1)
+            P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
+            P.qcl_propagate(model, ens, r.dt, r.cadence, r.cadence, r.seed, part)  # warm-up
+            torch.cuda.synchronize()
+            s = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            P.qcl_propagate(model, ens, r.dt, n_steps - r.cadence, r.cadence, r.seed, part, 0, s)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            row[prec] = {"ms": ms, "value": n_traj * (n_steps - r.cadence) / (ms / 1e3)}
+            del ens, part
+            torch.cuda.empty_cache()
+        row["value"] = row["fp64"]["value"]  # binary64 rate (earlier lines' key)
+        rows.append(row)
+        del model
     return rows
 
 
@@ -821,7 +825,8 @@ def main():
     if "source" in legs:
         line["source"] = source_leg(P, torch)
         print("[bench] supplied potentials: " + "; ".join(
-            f"{x['model']} {x['value']:.3e} (build {x['model_build_s']:.2f} s)" for x in line["source"]),
+            f"{x['model']} fp64 {x['fp64']['value']:.3e} fp32 {x['fp32']['value']:.3e} (build {x['model_build_s']:.2f} s)"
+            for x in line["source"]),
             file=sys.stderr, flush=True)
     if "scaling" in legs:
         line["scaling_sweep"] = scaling_leg(P, torch, wl)

@@ -273,10 +273,15 @@ int32_t qcl_model_pairs(qcl_model model);
  * over calls reproduces the uninterrupted one bit for bit.
  * desc supplies N (2..4), M (1..QCL_MAX_MODES_SOURCE), the masses, hbar and
  * the frequencies omega of the harmonic reference that the Wigner initial
- * state is drawn from (qcl_sample_initial); v0 and k are not read.  Such a
- * model propagates binary64 ensembles only (UNSUPPORTED for binary32); in
- * qcl_propagate_batch the items of one such model form a class of their
- * own (its compiled program holds a persistent batched kernel).  Errors: INVALID_ARG (as qcl_create_model
+ * state is drawn from (qcl_sample_initial); v0 and k are not read.  A
+ * source that also defines the three functions for float arguments
+ * (overloads or templates) and defines QCL_SOURCE_FP32 gets binary32
+ * kernels too (binary32 state and step; binary64 weight, phase and sums;
+ * where the smallest gap falls below 1e-4 of the largest hbar*omega, the
+ * closest pair re-solved from the binary64 potential); otherwise binary32
+ * ensembles are UNSUPPORTED.  In qcl_propagate_batch the items of one such
+ * model form a class of their own (its compiled program holds persistent
+ * batched kernels).  Errors: INVALID_ARG (as qcl_create_model
  * for the sizes and the masses and frequencies; NULL source; n_params
  * outside [0, QCL_MAX_PARAMS] or a non-finite parameter; a source that does
  * not compile, with the compiler's log in qcl_last_error), DEVICE (no

@@ -445,6 +445,90 @@ __device__ __forceinline__ void bin_store(BinLds &L, int &parity, bool live, int
 // Weights of the slots of a symmetric matrix A in the mean of element
 // (a, b): sum_{k<=l} A_kl P_kl = [(U^T A U)_aa + (U^T A U)_bb] / 2, with
 // P_kk = (U_ka^2 + U_kb^2) / 2 and P_kl = U_ka U_la + U_kb U_lb (k < l).
+// The binary32 solve leaves each eigenvector accurate to O(eps32 ||V||/gap)
+// per gap; only the mixing inside the closest pair (k, k+1) degrades as
+// their gap closes.  That pair's 2x2 block of V is rebuilt in binary64 in
+// the binary32 columns (vslot(s) gives slot s of V in binary64), diagonalised
+// by one binary64 Jacobi rotation, and the two columns are rotated, ordered
+// by their binary64 energies and sign-aligned with the previous frame U0.
+template <int N, typename VSlot>
+__device__ __forceinline__ void refine_pair64_with(VSlot vslot, const float (&U0)[N][N], Frame<N, float> &f)
+{
+    // the pair with the smallest gap
+    int k = 0;
+    float g = f.E[1] - f.E[0];
+#pragma unroll
+    for (int c = 1; c + 1 < N; ++c) {
+        const float gc = f.E[c + 1] - f.E[c];
+        k = gc < g ? c : k;
+        g = gc < g ? gc : g;
+    }
+    // the 2x2 block of V in the pair's binary32 columns u, v (their entries
+    // are exact in binary64), slot by slot
+    float u[N], v[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        u[r] = pick<N, float>(f.U[r], k);
+        v[r] = pick<N, float>(f.U[r], k + 1);
+    }
+    double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int l = i; l < N; ++l) {
+            const double vs = vslot(tri_index<N>(i, l));
+            const double ui = u[i], ul = u[l], vi = v[i], vl = v[l];
+            if (i == l) {
+                a = fma_g(vs, ui * ui, a);
+                b = fma_g(vs, vi * vi, b);
+                c = fma_g(vs, ui * vi, c);
+            } else {
+                a = fma_g(vs, 2.0 * (ui * ul), a);
+                b = fma_g(vs, 2.0 * (vi * vl), b);
+                c = fma_g(vs, fma_g(ui, vl, ul * vi), c);
+            }
+        }
+    double cs = 1.0, sn = 0.0;
+    if (c != 0.0) {
+        const double theta = (b - a) * rcp_g(2.0 * c);
+        double t = rcp_g(abs_g(theta) + sqrt_ge1<double>(fma_g(theta, theta, 1.0)));
+        t = theta < 0.0 ? -t : t;
+        cs = rsq_g(fma_g(t, t, 1.0));
+        sn = t * cs;
+        a -= t * c;
+        b += t * c;
+    }
+    // rotated columns, lower energy first, signs continuous with U0
+    const bool swap = b < a;
+    float nu[N], nv[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        const double x = fma_g(cs, (double)u[r], -sn * (double)v[r]);
+        const double y = fma_g(sn, (double)u[r], cs * (double)v[r]);
+        nu[r] = (float)(swap ? y : x);
+        nv[r] = (float)(swap ? x : y);
+    }
+    // sign alignment against the previous frame's columns k, k+1
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        d0 = fma_g((double)pick<N, float>(U0[r], k), (double)nu[r], d0);
+        d1 = fma_g((double)pick<N, float>(U0[r], k + 1), (double)nv[r], d1);
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        nu[r] = d0 < 0.0 ? -nu[r] : nu[r];
+        nv[r] = d1 < 0.0 ? -nv[r] : nv[r];
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int col = 0; col < N; ++col) {
+            const float x = f.U[r][col];
+            f.U[r][col] = (col == k) ? nu[r] : (col == k + 1) ? nv[r] : x;
+        }
+}
+
 template <int N, typename R>
 __device__ __forceinline__ void pair_weights(const Frame<N, R> &f, int a, int b, R (&P)[kTri<N>])
 {

@@ -173,8 +173,10 @@ qcl_status check_ensemble(const qcl_model_s &m, const qcl_ensemble *e)
             !aligned256(e->phase) || !aligned256(e->a) || !aligned256(e->b) || !aligned256(e->flags))
             return fail(QCL_ERR_INVALID_ARG, "ensemble arrays must be 256-byte aligned");
     }
-    if (m.source && e->prec != QCL_FP64)
-        return fail(QCL_ERR_UNSUPPORTED, "a model with a supplied potential runs binary64 ensembles only");
+    if (m.source && e->prec != QCL_FP64 && !m.user_propagate32)
+        return fail(QCL_ERR_UNSUPPORTED,
+                    "this supplied potential runs binary64 ensembles only (its source defines no binary32 "
+                    "functions and no QCL_SOURCE_FP32)");
     return QCL_OK;
 }
 

@@ -63,19 +63,22 @@ struct UserArgs {
     double dt, hdt;
     double dt_hbar;
     double rot_eps;  // Jacobi: rotate while |a_pq| > rot_eps * ||A||_F
+    double gap_thr;  // binary32 step: gaps below this are re-solved in binary64
 };
 
 // One (instance, tile) work item of a batched call for a model with a
 // supplied potential: the same layout on the host, which writes it, and in
 // the run-time compiled kernel, which reads it
+template <typename R>
 struct UserBatchItem {
     UserArgs A;
     PropArgs P;
-    EnsDev<double> E;
+    EnsDev<R> E;
     double *partials;
     int64_t tile_begin;
 };
-static_assert(sizeof(PropArgs) == 40 && sizeof(EnsDev<double>) == 88 && sizeof(UserBatchItem) == 176,
+static_assert(sizeof(PropArgs) == 40 && sizeof(EnsDev<double>) == 88 && sizeof(UserBatchItem<double>) == 184 &&
+                  sizeof(UserBatchItem<float>) == 184,
               "the batch descriptor must have one layout on the host and in the compiled program");
 
 // One bin of one tile's partials: the 8 N^2 sums [2][N][N][Re, Im, Re^2,

@@ -164,6 +164,9 @@ struct qcl_model_s {
     void *user_sample = nullptr;
     void *user_propagate = nullptr;
     void *user_batch = nullptr;
+    void *user_sample32 = nullptr;  // binary32 kernels, when the source provides binary32 functions
+    void *user_propagate32 = nullptr;
+    void *user_batch32 = nullptr;
     double *d_model = nullptr;  // device: V0 [N*N], K [M*N*N], then two-state binary64
                                 // constants [dlt0, c0, dlt[M], cpl[M]]
     size_t c64_offset = 0;      // element offset of the two-state constants
@@ -329,8 +332,8 @@ hipError_t launch_user_sample(const qcl_model_s &m, const SampleArgs &sa, const 
                               int32_t n_out, hipStream_t s);
 hipError_t launch_user_propagate(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
                                  double *partials, hipStream_t s);
-hipError_t launch_user_batch(const qcl_model_s &m, int wpc, const void *items, int32_t n_items, int64_t total_tiles,
-                             unsigned long long *counter, hipStream_t s);
+hipError_t launch_user_batch(const qcl_model_s &m, int prec, int wpc, const void *items, int32_t n_items,
+                             int64_t total_tiles, unsigned long long *counter, hipStream_t s);
 
 // wpc: workgroups per compute unit of the persistent launch (0: as many as
 // fit, else at most that many)
@@ -338,7 +341,7 @@ inline hipError_t launch_batch(const qcl_model_s &m, int prec, int scheme, int o
                                int32_t n_items, int64_t total_tiles, unsigned long long *counter, hipStream_t s)
 {
     if (m.source)  // each supplied potential is its own compiled program
-        return launch_user_batch(m, wpc, items, n_items, total_tiles, counter, s);
+        return launch_user_batch(m, prec, wpc, items, n_items, total_tiles, counter, s);
     if (m.fast2)  // the transition rule is a template parameter of the two-state kernels
         return launch_batch_n2(m.m, m.degree > 1, prec, scheme, wpc, items, n_items, total_tiles, counter, s);
     const int mp = padded_modes(m.m), rb = m.rank_pad;

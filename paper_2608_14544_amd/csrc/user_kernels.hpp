@@ -11,7 +11,12 @@
 //       K_s = sum_j v_j dV_s/dq_j (v: one value per mode)
 //
 // and may read QCL_N, QCL_M and the caller's parameters qcl_param[], which
-// the compilation defines before it.  Everything is binary64.  The step is
+// the compilation defines before it.  The functions are binary64; a source
+// that also defines them for float arguments (overloads or templates) and
+// defines QCL_SOURCE_FP32 gets the binary32 kernels too (binary32 state and
+// step, binary64 weight, phase and sums, and a binary64 re-solve of the
+// closest pair of states, from the binary64 potential, where the smallest
+// gap falls below the model's threshold).  The step is
 // the one of the built-in models (Monte Carlo move from rows a and b of
 // D = U^T K(v) U at (q_n, p_n), velocity Verlet on the mean force of the
 // new element, eigen-solve at q_{n+1} warm-started from the previous
@@ -26,12 +31,11 @@
 namespace qcl {
 
 // p_j += dt/2 f_j with the mean force of element (a, b) in frame f at q
-template <int N, int M>
-__device__ __forceinline__ void user_kick(const double (&q)[M], const Frame<N, double> &f, int a, int b, double hdt,
-                                          double (&p)[M])
+template <int N, int M, typename R>
+__device__ __forceinline__ void user_kick(const R (&q)[M], const Frame<N, R> &f, int a, int b, R hdt, R (&p)[M])
 {
-    double P[kTri<N>], F[M];
-    pair_weights<N, double>(f, a, b, P);
+    R P[kTri<N>], F[M];
+    pair_weights<N, R>(f, a, b, P);
     qcl_force(q, P, F);
 #pragma unroll
     for (int j = 0; j < M; ++j)
@@ -39,31 +43,31 @@ __device__ __forceinline__ void user_kick(const double (&q)[M], const Frame<N, d
 }
 
 // K(v) = sum_j v_j dV/dq_j at q, v = p/m
-template <int N, int M>
-__device__ __forceinline__ void user_velocity_coupling(const double (&q)[M], const double (&p)[M],
-                                                       const double (&inv_mass)[M], double (&K)[kTri<N>])
+template <int N, int M, typename R>
+__device__ __forceinline__ void user_velocity_coupling(const R (&q)[M], const R (&p)[M], const double (&inv_mass)[M],
+                                                       R (&K)[kTri<N>])
 {
-    double v[M];
+    R v[M];
 #pragma unroll
     for (int j = 0; j < M; ++j)
-        v[j] = p[j] * inv_mass[j];
+        v[j] = p[j] * (R)inv_mass[j];
     qcl_coupling(q, v, K);
 }
 
 // rows a and b of D = U^T K U
-template <int N>
-__device__ __forceinline__ void coupling_rows(const double (&K)[kTri<N>], const Frame<N, double> &f, int a, int b,
-                                              double (&Da)[N], double (&Db)[N])
+template <int N, typename R>
+__device__ __forceinline__ void coupling_rows(const R (&K)[kTri<N>], const Frame<N, R> &f, int a, int b, R (&Da)[N],
+                                              R (&Db)[N])
 {
-    double ua[N], ub[N], wa[N], wb[N];
-    column<N, double>(f, a, ua);
-    column<N, double>(f, b, ub);
+    R ua[N], ub[N], wa[N], wb[N];
+    column<N, R>(f, a, ua);
+    column<N, R>(f, b, ub);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        double sa = 0.0, sb = 0.0;
+        R sa = R(0), sb = R(0);
 #pragma unroll
         for (int l = 0; l < N; ++l) {
-            const double kv = K[sym_index<N>(k, l)];
+            const R kv = K[sym_index<N>(k, l)];
             sa = fma_g(kv, ua[l], sa);
             sb = fma_g(kv, ub[l], sb);
         }
@@ -72,7 +76,7 @@ __device__ __forceinline__ void coupling_rows(const double (&K)[kTri<N>], const 
     }
 #pragma unroll
     for (int c = 0; c < N; ++c) {
-        double da = 0.0, db = 0.0;
+        R da = R(0), db = R(0);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             da = fma_g(f.U[k][c], wa[k], da);
@@ -85,9 +89,10 @@ __device__ __forceinline__ void coupling_rows(const double (&K)[kTri<N>], const 
 
 // Wigner sampling of the harmonic reference (the same draws as the built-in
 // models: Philox block (gid, j, 1) per mode, Box-Muller), frame from the
-// identity, initial element, bin 0.
-template <int N, int M>
-__device__ __forceinline__ void user_sample(const SampleArgs &S, const UserArgs &A, const EnsDev<double> &E,
+// identity, initial element, bin 0; all in binary64, stored in the
+// ensemble's precision R.
+template <int N, int M, typename R>
+__device__ __forceinline__ void user_sample(const SampleArgs &S, const UserArgs &A, const EnsDev<R> &E,
                                             double *__restrict__ partials, int32_t n_out, BinLds &lds)
 {
     int parity = 0;
@@ -108,8 +113,8 @@ __device__ __forceinline__ void user_sample(const SampleArgs &S, const UserArgs 
         q[j] = S.q0[j] + S.sq[j] * (rr * cs);
         const double pj = S.sp[j] * (rr * sn);
         if (live) {
-            E.q[j * ld + i] = q[j];
-            E.p[j * ld + i] = pj;
+            E.q[j * ld + i] = (R)q[j];
+            E.p[j * ld + i] = (R)pj;
         }
     }
     double V[kTri<N>];
@@ -129,7 +134,7 @@ __device__ __forceinline__ void user_sample(const SampleArgs &S, const UserArgs 
         for (int r = 0; r < N; ++r)
 #pragma unroll
             for (int k = 0; k < N; ++k)
-                E.u[(r * N + k) * ld + i] = f.U[r][k];
+                E.u[(r * N + k) * ld + i] = (R)f.U[r][k];
         E.w[i] = w;
         E.phase[i] = 0.0;
         E.a[i] = (uint8_t)a;
@@ -140,8 +145,8 @@ __device__ __forceinline__ void user_sample(const SampleArgs &S, const UserArgs 
 }
 
 // All steps of one tile of kBlock walkers (the whole workgroup calls it).
-template <int N, int M>
-__device__ __forceinline__ void user_propagate_tile(const UserArgs &A, const PropArgs &P, const EnsDev<double> &E,
+template <int N, int M, typename R>
+__device__ __forceinline__ void user_propagate_tile(const UserArgs &A, const PropArgs &P, const EnsDev<R> &E,
                                                     const double (&inv_mass)[M], double *__restrict__ partials,
                                                     int64_t tile, BinLds &lds, int &parity)
 {
@@ -153,8 +158,9 @@ __device__ __forceinline__ void user_propagate_tile(const UserArgs &A, const Pro
     const uint64_t gid = (uint64_t)(E.traj_offset + li);
     const uint32_t g_lo = (uint32_t)gid, g_hi = (uint32_t)(gid >> 32);
     const bool linear_rule = P.scheme == QCL_TRANS_LINEAR;
+    const R dt = (R)A.dt, hdt = (R)A.hdt, eps = (R)A.rot_eps;
 
-    double q[M], p[M];
+    R q[M], p[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         q[j] = E.q[j * ld + li];
@@ -165,18 +171,18 @@ __device__ __forceinline__ void user_propagate_tile(const UserArgs &A, const Pro
     int a = E.a[li];
     int b = E.b[li];
     uint32_t flag = 0;
-    Frame<N, double> f;
+    Frame<N, R> f;
 #pragma unroll
     for (int r = 0; r < N; ++r)
 #pragma unroll
         for (int k = 0; k < N; ++k)
             f.U[r][k] = E.u[(r * N + k) * ld + li];
-    double K[T];
+    R K[T];
     {
-        double V[T];
+        R V[T];
         qcl_potential(q, V);
-        rayleigh<N, double>(V, f.U, f.E);
-        user_velocity_coupling<N, M>(q, p, inv_mass, K);
+        rayleigh<N, R>(V, f.U, f.E);
+        user_velocity_coupling<N, M, R>(q, p, inv_mass, K);
     }
 
     int64_t step = P.step0;
@@ -190,42 +196,56 @@ __device__ __forceinline__ void user_propagate_tile(const UserArgs &A, const Pro
         for (; step < stop; ++step) {
             if ((step & 3) == 0)
                 rnd = philox10(U4{g_lo, g_hi, (uint32_t)(step >> 2), 0u}, P.key0, P.key1);
-            const double u = u24d(pick_word(rnd, (uint32_t)(step & 3)));
+            const uint32_t word = pick_word(rnd, (uint32_t)(step & 3));
+            R u;
+            if constexpr (sizeof(R) == 4) u = u24f(word); else u = u24d(word);
 
             // 1. Monte Carlo move at (q_n, p_n)
-            double Da[N], Db[N];
-            coupling_rows<N>(K, f, a, b, Da, Db);
-            transition<N, double>(f, Da, Db, u, A.dt, linear_rule, a, b, w, flag);
+            R Da[N], Db[N];
+            coupling_rows<N, R>(K, f, a, b, Da, Db);
+            transition<N, R>(f, Da, Db, u, dt, linear_rule, a, b, w, flag);
 
             // 2. velocity Verlet on the mean force of the current element
-            const double dE0 = energy<N, double>(f, a) - energy<N, double>(f, b);
-            user_kick<N, M>(q, f, a, b, A.hdt, p);
+            const R dE0 = energy<N, R>(f, a) - energy<N, R>(f, b);
+            user_kick<N, M, R>(q, f, a, b, hdt, p);
 #pragma unroll
             for (int j = 0; j < M; ++j)
-                q[j] = fma_g(A.dt, p[j] * inv_mass[j], q[j]);
+                q[j] = fma_g(dt, p[j] * (R)inv_mass[j], q[j]);
             {
-                double V[T], U0[N][N];
+                R V[T], U0[N][N];
                 qcl_potential(q, V);
 #pragma unroll
                 for (int r = 0; r < N; ++r)
 #pragma unroll
                     for (int k = 0; k < N; ++k)
                         U0[r][k] = f.U[r][k];
-                solve_warm<N, double>(V, U0, A.rot_eps, f);
+                solve_warm<N, R>(V, U0, eps, f);
+                if constexpr (sizeof(R) == 4) {
+                    if (!(min_gap<N, R>(f) >= (R)A.gap_thr)) {  // near-degenerate: binary64
+                        double q64[M], V64[T];
+#pragma unroll
+                        for (int j = 0; j < M; ++j)
+                            q64[j] = (double)q[j];
+                        qcl_potential(q64, V64);
+                        refine_pair64_with<N>([&](int sl) { return V64[sl]; }, U0, f);
+                        rayleigh<N, R>(V, f.U, f.E);
+                        flag |= kFlagResolved;
+                    }
+                }
             }
-            if (!(min_gap<N, double>(f) > 2.2250738585072014e-308))
+            if (!(min_gap<N, R>(f) > R(2.2250738585072014e-308)))
                 flag |= kFlagDegenerate;
-            user_kick<N, M>(q, f, a, b, A.hdt, p);
-            user_velocity_coupling<N, M>(q, p, inv_mass, K);
+            user_kick<N, M, R>(q, f, a, b, hdt, p);
+            user_velocity_coupling<N, M, R>(q, p, inv_mass, K);
 
             // 3. phase: trapezoid of w_ab = (E_a - E_b)/hbar
-            const double dE1 = energy<N, double>(f, a) - energy<N, double>(f, b);
-            phase += A.dt_hbar * 0.5 * (dE0 + dE1);
+            const R dE1 = energy<N, R>(f, a) - energy<N, R>(f, b);
+            phase += A.dt_hbar * 0.5 * ((double)dE0 + (double)dE1);
         }
         // 4. output bin at global step next_bin
         if (step == next_bin && next_bin / P.cadence < P.n_out) {
-            bin_store<N, double>(lds, parity, live, a, b, w, phase, f,
-                                 partials + (tile * P.n_out + next_bin / P.cadence) * tile_values(N));
+            bin_store<N, R>(lds, parity, live, a, b, w, phase, f,
+                            partials + (tile * P.n_out + next_bin / P.cadence) * tile_values(N));
         }
     }
     if (!(__builtin_isfinite(w) && __builtin_isfinite(phase)))
@@ -251,20 +271,20 @@ __device__ __forceinline__ void user_propagate_tile(const UserArgs &A, const Pro
     }
 }
 
-template <int N, int M>
-__device__ __forceinline__ void user_propagate(const UserArgs &A, const PropArgs &P, const EnsDev<double> &E,
+template <int N, int M, typename R>
+__device__ __forceinline__ void user_propagate(const UserArgs &A, const PropArgs &P, const EnsDev<R> &E,
                                                const double (&inv_mass)[M], double *__restrict__ partials,
                                                BinLds &lds)
 {
     int parity = 0;
-    user_propagate_tile<N, M>(A, P, E, inv_mass, partials, (int64_t)blockIdx.x, lds, parity);
+    user_propagate_tile<N, M, R>(A, P, E, inv_mass, partials, (int64_t)blockIdx.x, lds, parity);
 }
 
 // Persistent launch over the (instance, tile) items of many ensembles of
 // this model: items are taken from a device counter (descriptors sorted by
 // decreasing work per tile), as in the built-in batched kernels.
-template <int N, int M>
-__device__ __forceinline__ void user_batch(const UserBatchItem *__restrict__ items, int32_t n_items,
+template <int N, int M, typename R>
+__device__ __forceinline__ void user_batch(const UserBatchItem<R> *__restrict__ items, int32_t n_items,
                                            int64_t total_tiles, unsigned long long *counter,
                                            const double (&inv_mass)[M], BinLds &lds, long long &item_sh)
 {
@@ -284,8 +304,8 @@ __device__ __forceinline__ void user_batch(const UserBatchItem *__restrict__ ite
             const int mid = (lo + hi + 1) >> 1;
             if (items[mid].tile_begin <= item) lo = mid; else hi = mid - 1;
         }
-        const UserBatchItem &it = items[lo];
-        user_propagate_tile<N, M>(it.A, it.P, it.E, inv_mass, it.partials, item - it.tile_begin, lds, parity);
+        const UserBatchItem<R> &it = items[lo];
+        user_propagate_tile<N, M, R>(it.A, it.P, it.E, inv_mass, it.partials, item - it.tile_begin, lds, parity);
         __syncthreads();
     }
 }

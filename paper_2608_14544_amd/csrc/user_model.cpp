@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cinttypes>
 #include <cmath>
 #include <cstdio>
@@ -34,6 +35,9 @@ namespace {
 constexpr const char *kSampleName = "qcl_user_sample_kernel";
 constexpr const char *kPropagateName = "qcl_user_propagate_kernel";
 constexpr const char *kBatchName = "qcl_user_batch_kernel";
+constexpr const char *kSample32Name = "qcl_user_sample32_kernel";
+constexpr const char *kPropagate32Name = "qcl_user_propagate32_kernel";
+constexpr const char *kBatch32Name = "qcl_user_batch32_kernel";
 
 // the same rotation threshold as the built-in binary64 kernels
 constexpr double kRotEps64 = 64.0 * 1.1102230246251565e-16;
@@ -80,38 +84,59 @@ std::string program_text(const qcl_model_s &m, const char *source, const double 
     for (int j = 0; j < m.m; ++j)
         s += (j ? ", " : "") + hex_literal(1.0 / m.mass[j]);
     s += "};\n";
-    s += "extern \"C\" __global__ __launch_bounds__(QCL_TILE) void qcl_user_sample_kernel(\n"
-         "    qcl::SampleArgs S, qcl::UserArgs A, qcl::EnsDev<double> E, double *partials, int32_t n_out)\n"
-         "{\n"
-         "    __shared__ qcl::BinLds lds;\n"
-         "    qcl::user_sample<QCL_N, QCL_M>(S, A, E, partials, n_out, lds);\n"
-         "}\n"
-         "extern \"C\" __global__ __launch_bounds__(QCL_TILE) void qcl_user_propagate_kernel(\n"
-         "    qcl::UserArgs A, qcl::PropArgs P, qcl::EnsDev<double> E, double *partials)\n"
-         "{\n"
-         "    __shared__ qcl::BinLds lds;\n"
-         "    qcl::user_propagate<QCL_N, QCL_M>(A, P, E, qcl_inv_mass, partials, lds);\n"
-         "}\n"
-         "extern \"C\" __global__ __launch_bounds__(QCL_TILE) void qcl_user_batch_kernel(\n"
-         "    const qcl::UserBatchItem *items, int32_t n_items, int64_t total_tiles, unsigned long long *counter)\n"
-         "{\n"
-         "    __shared__ qcl::BinLds lds;\n"
-         "    __shared__ long long item_sh;\n"
-         "    qcl::user_batch<QCL_N, QCL_M>(items, n_items, total_tiles, counter, qcl_inv_mass, lds, item_sh);\n"
-         "}\n";
+    // the three kernels per precision; the binary32 ones exist when the
+    // source provides binary32 functions and says so (QCL_SOURCE_FP32)
+    auto kernels = [&](const char *suffix, const char *R) {
+        char b[2048];
+        std::snprintf(
+            b, sizeof(b),
+            "extern \"C\" __global__ __launch_bounds__(QCL_TILE) void qcl_user_sample%s_kernel(\n"
+            "    qcl::SampleArgs S, qcl::UserArgs A, qcl::EnsDev<%s> E, double *partials, int32_t n_out)\n"
+            "{\n"
+            "    __shared__ qcl::BinLds lds;\n"
+            "    qcl::user_sample<QCL_N, QCL_M, %s>(S, A, E, partials, n_out, lds);\n"
+            "}\n"
+            "extern \"C\" __global__ __launch_bounds__(QCL_TILE) void qcl_user_propagate%s_kernel(\n"
+            "    qcl::UserArgs A, qcl::PropArgs P, qcl::EnsDev<%s> E, double *partials)\n"
+            "{\n"
+            "    __shared__ qcl::BinLds lds;\n"
+            "    qcl::user_propagate<QCL_N, QCL_M, %s>(A, P, E, qcl_inv_mass, partials, lds);\n"
+            "}\n"
+            "extern \"C\" __global__ __launch_bounds__(QCL_TILE) void qcl_user_batch%s_kernel(\n"
+            "    const qcl::UserBatchItem<%s> *items, int32_t n_items, int64_t total_tiles,\n"
+            "    unsigned long long *counter)\n"
+            "{\n"
+            "    __shared__ qcl::BinLds lds;\n"
+            "    __shared__ long long item_sh;\n"
+            "    qcl::user_batch<QCL_N, QCL_M, %s>(items, n_items, total_tiles, counter, qcl_inv_mass, lds,\n"
+            "                                     item_sh);\n"
+            "}\n",
+            suffix, R, R, suffix, R, R, suffix, R, R);
+        s += b;
+    };
+    kernels("", "double");
+    s += "#ifdef QCL_SOURCE_FP32\n";
+    kernels("32", "float");
+    s += "#endif\n";
     return s;
 }
 
-UserArgs user_args(const qcl_model_s &m, double dt)
+// Jacobi thresholds as in the built-in kernels; the binary32 re-solve
+// threshold is 1e-4 of the harmonic reference's largest quantum hbar w
+UserArgs user_args(const qcl_model_s &m, double dt, bool fp32)
 {
-    return UserArgs{dt, 0.5 * dt, dt / m.hbar, kRotEps64};
+    double scale = 0.0;
+    for (int j = 0; j < m.m; ++j)
+        scale = std::max(scale, m.hbar * m.omega[j]);
+    return UserArgs{dt, 0.5 * dt, dt / m.hbar, fp32 ? 64.0 * 5.9604644775390625e-08 : kRotEps64, 1e-4 * scale};
 }
 
-EnsDev<double> ens64(const qcl_ensemble &e)
+template <typename R>
+EnsDev<R> ens_user(const qcl_ensemble &e)
 {
-    return EnsDev<double>{(double *)e.q, (double *)e.p, (double *)e.u, e.w, e.phase, e.a, e.b, e.flags,
-                          e.ld, e.n_traj, e.traj_offset};
+    return EnsDev<R>{(R *)e.q, (R *)e.p, (R *)e.u, e.w, e.phase, e.a, e.b, e.flags, e.ld, e.n_traj, e.traj_offset};
 }
+
 
 }  // namespace
 
@@ -175,6 +200,16 @@ qcl_status user_load(qcl_model_s &m)
     m.user_sample = (void *)fs;
     m.user_propagate = (void *)fp;
     m.user_batch = (void *)fb;
+    // binary32 kernels: present only when the source provides them
+    hipFunction_t fs32 = nullptr, fp32 = nullptr, fb32 = nullptr;
+    if (hipModuleGetFunction(&fs32, mod, kSample32Name) == hipSuccess &&
+        hipModuleGetFunction(&fp32, mod, kPropagate32Name) == hipSuccess &&
+        hipModuleGetFunction(&fb32, mod, kBatch32Name) == hipSuccess) {
+        m.user_sample32 = (void *)fs32;
+        m.user_propagate32 = (void *)fp32;
+        m.user_batch32 = (void *)fb32;
+    }
+    (void)hipGetLastError();  // a kernel the source did not ask for is no error
     return QCL_OK;
 }
 
@@ -183,6 +218,7 @@ void user_release(qcl_model_s &m)
     if (m.user_module)
         (void)hipModuleUnload((hipModule_t)m.user_module);
     m.user_module = m.user_sample = m.user_propagate = m.user_batch = nullptr;
+    m.user_sample32 = m.user_propagate32 = m.user_batch32 = nullptr;
 }
 
 hipError_t launch_user_sample(const qcl_model_s &m, const SampleArgs &sa_in, const qcl_ensemble &ens,
@@ -190,53 +226,75 @@ hipError_t launch_user_sample(const qcl_model_s &m, const SampleArgs &sa_in, con
 {
     SampleArgs sa = sa_in;
     sa.m = m.m;
-    UserArgs A = user_args(m, 1.0);
-    EnsDev<double> E = ens64(ens);
+    UserArgs A = user_args(m, 1.0, false);  // sampling is binary64 in both precisions
+    const unsigned grid = (unsigned)n_tiles(ens.n_traj);
+    if (ens.prec == QCL_FP32_ACC64) {
+        EnsDev<float> E = ens_user<float>(ens);
+        void *args[] = {&sa, &A, &E, &partials, &n_out};
+        return hipModuleLaunchKernel((hipFunction_t)m.user_sample32, grid, 1, 1, kBlock, 1, 1, 0, s, args, nullptr);
+    }
+    EnsDev<double> E = ens_user<double>(ens);
     void *args[] = {&sa, &A, &E, &partials, &n_out};
-    return hipModuleLaunchKernel((hipFunction_t)m.user_sample, (unsigned)n_tiles(ens.n_traj), 1, 1, kBlock, 1, 1,
-                                 0, s, args, nullptr);
+    return hipModuleLaunchKernel((hipFunction_t)m.user_sample, grid, 1, 1, kBlock, 1, 1, 0, s, args, nullptr);
 }
 
 hipError_t launch_user_propagate(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd,
                                  double *partials, hipStream_t s)
 {
-    UserArgs A = user_args(m, pd.dt);
+    const bool fp32 = ens.prec == QCL_FP32_ACC64;
+    UserArgs A = user_args(m, pd.dt, fp32);
     PropArgs P{ens.step, pd.n_steps, pd.cadence, pd.n_out, pd.scheme, (uint32_t)pd.seed, (uint32_t)(pd.seed >> 32),
                m.m};
-    EnsDev<double> E = ens64(ens);
+    const unsigned grid = (unsigned)n_tiles(ens.n_traj);
+    if (fp32) {
+        EnsDev<float> E = ens_user<float>(ens);
+        void *args[] = {&A, &P, &E, &partials};
+        return hipModuleLaunchKernel((hipFunction_t)m.user_propagate32, grid, 1, 1, kBlock, 1, 1, 0, s, args,
+                                     nullptr);
+    }
+    EnsDev<double> E = ens_user<double>(ens);
     void *args[] = {&A, &P, &E, &partials};
-    return hipModuleLaunchKernel((hipFunction_t)m.user_propagate, (unsigned)n_tiles(ens.n_traj), 1, 1, kBlock, 1, 1,
-                                 0, s, args, nullptr);
+    return hipModuleLaunchKernel((hipFunction_t)m.user_propagate, grid, 1, 1, kBlock, 1, 1, 0, s, args, nullptr);
+}
+
+template <typename R>
+void write_user_item(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
+                     int64_t tile_begin, void *out)
+{
+    UserBatchItem<R> it{};
+    it.A = user_args(m, pd.dt, sizeof(R) == 4);
+    it.P = PropArgs{ens.step, pd.n_steps, pd.cadence, pd.n_out, pd.scheme, (uint32_t)pd.seed,
+                    (uint32_t)(pd.seed >> 32), m.m};
+    it.E = ens_user<R>(ens);
+    it.partials = partials;
+    it.tile_begin = tile_begin;
+    std::memcpy(out, &it, sizeof(it));
 }
 
 size_t batch_item_user(const qcl_model_s &m, const qcl_ensemble &ens, const qcl_prop_desc &pd, double *partials,
                        int64_t tile_begin, void *out)
 {
     if (out) {
-        UserBatchItem it{};
-        it.A = user_args(m, pd.dt);
-        it.P = PropArgs{ens.step, pd.n_steps, pd.cadence, pd.n_out, pd.scheme, (uint32_t)pd.seed,
-                        (uint32_t)(pd.seed >> 32), m.m};
-        it.E = ens64(ens);
-        it.partials = partials;
-        it.tile_begin = tile_begin;
-        std::memcpy(out, &it, sizeof(it));
+        if (ens.prec == QCL_FP32_ACC64)
+            write_user_item<float>(m, ens, pd, partials, tile_begin, out);
+        else
+            write_user_item<double>(m, ens, pd, partials, tile_begin, out);
     }
-    return sizeof(UserBatchItem);
+    return sizeof(UserBatchItem<double>);
 }
 
-hipError_t launch_user_batch(const qcl_model_s &m, int wpc, const void *items, int32_t n_items, int64_t total_tiles,
-                             unsigned long long *counter, hipStream_t s)
+hipError_t launch_user_batch(const qcl_model_s &m, int prec, int wpc, const void *items, int32_t n_items,
+                             int64_t total_tiles, unsigned long long *counter, hipStream_t s)
 {
+    const hipFunction_t fn = (hipFunction_t)(prec == QCL_FP32_ACC64 ? m.user_batch32 : m.user_batch);
     int cus = 0, per_cu = 0, dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (hipFunction_t)m.user_batch, kBlock, 0);
+    (void)hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0);
     const int64_t grid = persistent_grid(total_tiles, cus, per_cu, wpc);
-    const UserBatchItem *it = (const UserBatchItem *)items;
+    const void *it = items;
     void *args[] = {&it, &n_items, &total_tiles, &counter};
-    return hipModuleLaunchKernel((hipFunction_t)m.user_batch, (unsigned)grid, 1, 1, kBlock, 1, 1, 0, s, args,
-                                 nullptr);
+    return hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, kBlock, 1, 1, 0, s, args, nullptr);
 }
 
 }  // namespace qcl

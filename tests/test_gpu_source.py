@@ -81,27 +81,74 @@ def test_source_split_run_bitwise(P):
     assert np.array_equal(out1, out2)
 
 
-def test_source_rejects_fp32(P):
-    wl = CASES["morse"]()
-    model = P.Model(wl.model)
+_DOUBLE_ONLY = """
+__device__ void qcl_potential(const double *q, double *V)
+{
+    V[0] = 0.5 * q[0] * q[0] + qcl_param[0] * q[0];
+    V[1] = qcl_param[1];
+    V[2] = 0.5 * q[0] * q[0] - qcl_param[0] * q[0];
+}
+__device__ void qcl_force(const double *q, const double *w, double *f)
+{
+    f[0] = -(w[0] * (q[0] + qcl_param[0]) + w[2] * (q[0] - qcl_param[0]));
+}
+__device__ void qcl_coupling(const double *q, const double *v, double *K)
+{
+    K[0] = v[0] * (q[0] + qcl_param[0]);
+    K[1] = 0.0;
+    K[2] = v[0] * (q[0] - qcl_param[0]);
+}
+"""
+
+
+def test_source_without_fp32_functions_rejects_fp32(P):
+    """A source with binary64 functions only runs binary64 ensembles: a
+    binary32 ensemble is UNSUPPORTED, before any launch."""
+    sm = W.SourceModel(name="double_only", n_states_=2, mass=[1.0], omega=[1.0], params=[0.4, 0.2],
+                       hip_source=_DOUBLE_ONLY, c_source="")
+    model = P.Model(sm)
+    init = W.InitSpec(kT=0.0, q0=[0.0], state=0)
     with pytest.raises(P.QCLError) as e:
         ens = P.Ensemble(model, 256, "fp32")
         part = P.Partials(model, 256, 2)
-        P.qcl_sample_initial(model, wl.init, 1, ens, part)
+        P.qcl_sample_initial(model, init, 1, ens, part)
     assert e.value.status == P.QCL_ERR_UNSUPPORTED
+    assert "binary64 ensembles only" in str(e.value)
 
 
-def _setup(P, wl, T, model=None):
+@pytest.mark.parametrize("name", ["morse", "morse_ragged", "lvc_n3_m4", "lvc_n4_m6"])
+def test_source_fp32_against_oracle(P, name):
+    """Binary32 steps of a supplied potential (binary64 weight, phase and
+    sums, binary64 re-solve of near-degenerate pairs) against the FP64 oracle:
+    every mean within 1e-3 x max(1, rms), widened by the walkers whose
+    decisions differ."""
+    from parity import check_ensemble32
+    wl = CASES[name]()
+    out_g, st_g, _, flags = gpu_run(P, wl, prec="fp32")
+    out_o, st_o, _, _ = oracle_run(wl)
+    check_ensemble32(out_g, out_o, wl.run.n_traj, tol=1e-3, label=name + " fp32", g=st_g, o=st_o)
+
+
+def test_source_fp32_split_run_bitwise(P):
+    wl = CASES["morse"]()
+    out1, st1, _, _ = gpu_run(P, wl, prec="fp32")
+    out2, st2, _, _ = gpu_run(P, wl, prec="fp32", split=[37, 3, 120])
+    for k in st1:
+        assert np.array_equal(st1[k], st2[k]), k
+    assert np.array_equal(out1, out2)
+
+
+def _setup(P, wl, T, model=None, prec="fp64"):
     r = wl.run
     model = model or P.Model(wl.model)
-    ens = P.Ensemble(model, T, "fp64")
+    ens = P.Ensemble(model, T, prec)
     part = P.Partials(model, T, r.n_steps // r.cadence + 1)
     P.qcl_sample_initial(model, wl.init, r.seed, ens, part)
     return model, ens, part
 
 
-def _solo(P, wl, T, scheme=0, model=None):
-    model, ens, part = _setup(P, wl, T, model)
+def _solo(P, wl, T, scheme=0, model=None, prec="fp64"):
+    model, ens, part = _setup(P, wl, T, model, prec)
     r = wl.run
     P.qcl_propagate(model, ens, r.dt, r.n_steps, r.cadence, r.seed, part, scheme)
     return P.qcl_reduce_observables(model, part, T).cpu().numpy(), ens.to_numpy()
@@ -109,7 +156,7 @@ def _solo(P, wl, T, scheme=0, model=None):
 
 def _batched(P, mix, slices=(None,)):
     import torch
-    runs = [(_setup(P, wl, T, model), wl, scheme, T) for wl, T, scheme, model in mix]
+    runs = [(_setup(P, wl, T, model, prec), wl, scheme, T) for wl, T, scheme, model, prec in mix]
     ws = P.Workspace()
     done = [0] * len(runs)
     for frac in slices:
@@ -128,17 +175,21 @@ def _batched(P, mix, slices=(None,)):
 
 @pytest.mark.parametrize("slices", [(None,), (0.3, 0.3, None)], ids=["whole", "sliced"])
 def test_source_batch_bitwise_equals_solo(P, slices):
-    """Items of two supplied-potential models (one class each, the persistent
-    kernel compiled into each model's program) beside a built-in item, whole
-    and in K-step slices: every item bitwise its solo run."""
+    """Items of two supplied-potential models in both precisions (one class
+    per model and precision, the persistent kernels compiled into each
+    model's program) beside a built-in item, whole and in K-step slices:
+    every item bitwise its solo run."""
     morse = W.morse_coupled(n_traj=3000, n_steps=160, cadence=10)
     m_morse = P.Model(morse.model)
     src, _ = _lvc_source(7, 3, 4, n_traj=2000, n_steps=150, cadence=15)
     m_src = P.Model(src.model)
     builtin = W.random_lvc(8, n_states=3, n_modes=4, n_traj=900, n_steps=100, cadence=10)
-    mix = [(morse, 3000, 0, m_morse), (W.morse_coupled(n_traj=777, n_steps=97, cadence=7), 777, 0, m_morse),
-           (src, 2000, 0, m_src), (src, 513, 1, m_src), (builtin, 900, 0, None)]
-    solo = [_solo(P, wl, T, scheme, model) for wl, T, scheme, model in mix]
+    mix = [(morse, 3000, 0, m_morse, "fp64"),
+           (W.morse_coupled(n_traj=777, n_steps=97, cadence=7), 777, 0, m_morse, "fp64"),
+           (morse, 2048, 0, m_morse, "fp32"),
+           (src, 2000, 0, m_src, "fp64"), (src, 513, 1, m_src, "fp64"), (src, 1000, 0, m_src, "fp32"),
+           (builtin, 900, 0, None, "fp64")]
+    solo = [_solo(P, wl, T, scheme, model, prec) for wl, T, scheme, model, prec in mix]
     batch = _batched(P, mix, slices)
     for k, (s, b) in enumerate(zip(solo, batch)):
         for key in s[1]:

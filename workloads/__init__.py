@@ -394,44 +394,54 @@ def random_bilinear(index: int, n_states: int = 3, n_modes: int = 5, n_pairs: in
 # never zero, so the surfaces only come close at an avoided crossing.
 # Parameters: D0, D1, a, x0, x1, offset, k1, kappa, c, beta, xc, gamma, c0.
 _MORSE_HIP = """
-__device__ inline void morse_parts(const double *q, double &e0, double &e1, double &g)
+// binary64 and binary32 (templates): the binary32 kernels are built too
+#define QCL_SOURCE_FP32 1
+template <typename T>
+__device__ inline T morse_prm(int i) { return (T)qcl_param[i]; }
+template <typename T>
+__device__ inline void morse_parts(const T *q, T &e0, T &e1, T &g)
 {
-    e0 = exp(-qcl_param[2] * (q[0] - qcl_param[3]));
-    e1 = exp(-qcl_param[2] * (q[0] - qcl_param[4]));
-    const double d = q[0] - qcl_param[10];
-    g = exp(-qcl_param[9] * d * d);  // the Gaussian; the coupling's shape is c0 + g
+    e0 = exp(-morse_prm<T>(2) * (q[0] - morse_prm<T>(3)));
+    e1 = exp(-morse_prm<T>(2) * (q[0] - morse_prm<T>(4)));
+    const T d = q[0] - morse_prm<T>(10);
+    g = exp(-morse_prm<T>(9) * d * d);  // the Gaussian; the coupling's shape is c0 + g
 }
-__device__ void qcl_potential(const double *q, double *V)
+template <typename T>
+__device__ void qcl_potential(const T *q, T *V)
 {
-    double e0, e1, g;
+    T e0, e1, g;
     morse_parts(q, e0, e1, g);
-    const double h = 0.5 * qcl_param[6] * q[1] * q[1];
-    V[0] = qcl_param[0] * (1.0 - e0) * (1.0 - e0) + h;
-    V[1] = qcl_param[8] * (qcl_param[12] + g) * (1.0 + qcl_param[11] * q[1] * q[1]);
-    V[2] = qcl_param[1] * (1.0 - e1) * (1.0 - e1) + qcl_param[5] + h + qcl_param[7] * q[1];
+    const T h = T(0.5) * morse_prm<T>(6) * q[1] * q[1];
+    V[0] = morse_prm<T>(0) * (T(1) - e0) * (T(1) - e0) + h;
+    V[1] = morse_prm<T>(8) * (morse_prm<T>(12) + g) * (T(1) + morse_prm<T>(11) * q[1] * q[1]);
+    V[2] = morse_prm<T>(1) * (T(1) - e1) * (T(1) - e1) + morse_prm<T>(5) + h + morse_prm<T>(7) * q[1];
 }
-__device__ inline void morse_gradient(const double *q, double (&G)[2][3])
+template <typename T>
+__device__ inline void morse_gradient(const T *q, T (&G)[2][3])
 {
-    double e0, e1, g;
+    T e0, e1, g;
     morse_parts(q, e0, e1, g);
-    const double a = qcl_param[2];
-    G[0][0] = 2.0 * qcl_param[0] * a * e0 * (1.0 - e0);
-    G[0][1] = -2.0 * qcl_param[9] * (q[0] - qcl_param[10]) * qcl_param[8] * g * (1.0 + qcl_param[11] * q[1] * q[1]);
-    G[0][2] = 2.0 * qcl_param[1] * a * e1 * (1.0 - e1);
-    G[1][0] = qcl_param[6] * q[1];
-    G[1][1] = qcl_param[8] * (qcl_param[12] + g) * 2.0 * qcl_param[11] * q[1];
-    G[1][2] = qcl_param[6] * q[1] + qcl_param[7];
+    const T a = morse_prm<T>(2);
+    G[0][0] = T(2) * morse_prm<T>(0) * a * e0 * (T(1) - e0);
+    G[0][1] = T(-2) * morse_prm<T>(9) * (q[0] - morse_prm<T>(10)) * morse_prm<T>(8) * g *
+              (T(1) + morse_prm<T>(11) * q[1] * q[1]);
+    G[0][2] = T(2) * morse_prm<T>(1) * a * e1 * (T(1) - e1);
+    G[1][0] = morse_prm<T>(6) * q[1];
+    G[1][1] = morse_prm<T>(8) * (morse_prm<T>(12) + g) * T(2) * morse_prm<T>(11) * q[1];
+    G[1][2] = morse_prm<T>(6) * q[1] + morse_prm<T>(7);
 }
-__device__ void qcl_force(const double *q, const double *w, double *f)
+template <typename T>
+__device__ void qcl_force(const T *q, const T *w, T *f)
 {
-    double G[2][3];
+    T G[2][3];
     morse_gradient(q, G);
     for (int j = 0; j < 2; ++j)
         f[j] = -(w[0] * G[j][0] + w[1] * G[j][1] + w[2] * G[j][2]);
 }
-__device__ void qcl_coupling(const double *q, const double *v, double *K)
+template <typename T>
+__device__ void qcl_coupling(const T *q, const T *v, T *K)
 {
-    double G[2][3];
+    T G[2][3];
     morse_gradient(q, G);
     for (int s = 0; s < 3; ++s)
         K[s] = v[0] * G[0][s] + v[1] * G[1][s];
@@ -498,43 +508,50 @@ def lvc_as_source(model: LVCModel, name: Optional[str] = None) -> SourceModel:
     params += list(model.mass * model.omega ** 2)
     diag = ", ".join("1" if k == l else "0" for k, l in slots)
     hip = f"""
+// binary64 and binary32 (templates): the binary32 kernels are built too
+#define QCL_SOURCE_FP32 1
 #define LVC_T {T}
 __device__ constexpr int lvc_diag[LVC_T] = {{{diag}}};
-__device__ inline double lvc_k(int j, int s) {{ return qcl_param[LVC_T * (1 + j) + s]; }}
-__device__ inline double lvc_mw2(int j) {{ return qcl_param[LVC_T * (1 + QCL_M) + j]; }}
-__device__ void qcl_potential(const double *q, double *V)
+template <typename T>
+__device__ inline T lvc_k(int j, int s) {{ return (T)qcl_param[LVC_T * (1 + j) + s]; }}
+template <typename T>
+__device__ inline T lvc_mw2(int j) {{ return (T)qcl_param[LVC_T * (1 + QCL_M) + j]; }}
+template <typename T>
+__device__ void qcl_potential(const T *q, T *V)
 {{
-    double h = 0.0;
+    T h = T(0);
     for (int j = 0; j < QCL_M; ++j)
-        h += 0.5 * lvc_mw2(j) * q[j] * q[j];
+        h += T(0.5) * lvc_mw2<T>(j) * q[j] * q[j];
     for (int s = 0; s < LVC_T; ++s) {{
-        double v = qcl_param[s];
+        T v = (T)qcl_param[s];
         for (int j = 0; j < QCL_M; ++j)
-            v += q[j] * lvc_k(j, s);
+            v += q[j] * lvc_k<T>(j, s);
         V[s] = lvc_diag[s] ? v + h : v;
     }}
 }}
-__device__ void qcl_force(const double *q, const double *w, double *f)
+template <typename T>
+__device__ void qcl_force(const T *q, const T *w, T *f)
 {{
-    double wd = 0.0;
+    T wd = T(0);
     for (int s = 0; s < LVC_T; ++s)
-        wd += lvc_diag[s] ? w[s] : 0.0;
+        wd += lvc_diag[s] ? w[s] : T(0);
     for (int j = 0; j < QCL_M; ++j) {{
-        double g = lvc_mw2(j) * q[j] * wd;
+        T g = lvc_mw2<T>(j) * q[j] * wd;
         for (int s = 0; s < LVC_T; ++s)
-            g += w[s] * lvc_k(j, s);
+            g += w[s] * lvc_k<T>(j, s);
         f[j] = -g;
     }}
 }}
-__device__ void qcl_coupling(const double *q, const double *v, double *K)
+template <typename T>
+__device__ void qcl_coupling(const T *q, const T *v, T *K)
 {{
-    double h = 0.0;
+    T h = T(0);
     for (int j = 0; j < QCL_M; ++j)
-        h += v[j] * lvc_mw2(j) * q[j];
+        h += v[j] * lvc_mw2<T>(j) * q[j];
     for (int s = 0; s < LVC_T; ++s) {{
-        double k = 0.0;
+        T k = T(0);
         for (int j = 0; j < QCL_M; ++j)
-            k += v[j] * lvc_k(j, s);
+            k += v[j] * lvc_k<T>(j, s);
         K[s] = lvc_diag[s] ? k + h : k;
     }}
 }}
