@@ -312,7 +312,7 @@ inline size_t batch_item(const qcl_model_s &m, const qcl_ensemble &ens, const qc
 // 32 padded modes (16 for four states), 2 with 64), else 0.
 inline int occupancy_variant(const qcl_model_s &m, int prec, int requested)
 {
-    if (m.fast2 || m.degree != 1 || m.n > 4 || prec != QCL_FP32_ACC64)
+    if (m.source || m.fast2 || m.degree != 1 || m.n > 4 || prec != QCL_FP32_ACC64)
         return 0;
     const int mp = padded_modes(m.m);
     if (requested == 3 && mp <= (m.n >= 4 ? 16 : 32))

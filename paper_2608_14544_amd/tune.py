@@ -106,7 +106,8 @@ class TuningTable:
             self.load(path)
 
     def key(self, model: "Q.Model", prec: str) -> Optional[Key]:
-        if getattr(model, "degree", 1) > 1:  # one build only for models with higher powers
+        # one build only for models with higher powers and supplied potentials
+        if getattr(model, "degree", 1) > 1 or getattr(model, "is_source", False):
             return None
         return kernel_class(model.n_states, model.n_modes, model.rank, prec)
 
