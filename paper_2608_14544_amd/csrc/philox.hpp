@@ -3,7 +3,9 @@
 // of the 4x32 S-box with multipliers 0xD2511F53 / 0xCD9E8D57 and Weyl key
 // increments 0x9E3779B9 / 0xBB67AE85.  The key is the 64-bit seed, which
 // is wave-uniform, so the key schedule runs on the scalar unit; each
-// 32x32->64 product is one v_mad_u64_u32.
+// 32x32->64 product is one v_mad_u64_u32, and each three-way exclusive or
+// one v_bitop3_b32 (truth table 0x96, a ^ b ^ c), which the compiler does
+// not form from two exclusive ors by itself.
 #pragma once
 
 #ifndef __HIPCC_RTC__
@@ -25,9 +27,9 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
         U4 n;
-        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        n.x = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96);
         n.y = (uint32_t)p1;
-        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        n.z = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96);
         n.w = (uint32_t)p0;
         c = n;
         k0 += 0x9E3779B9u;
