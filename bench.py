@@ -565,10 +565,14 @@ def source_leg(P, torch, n_traj=1 << 20, n_steps=200):
 
 
 def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=None, quantum_work=2e8,
-               tune_quantum=True):
+               tune_quantum=True, min_steps=1):
     """The served stream through the continuous-batching server.  Default:
     the sub-saturation variant (walkers log-uniform over 1e5-1e7); ``full``
-    uses 1e5-1e8, whose offered load exceeds one device."""
+    uses 1e5-1e8, whose offered load exceeds one device.  The serving
+    quantum and its step floor are tuned on the first 30 % of this stream
+    (each stream its own) unless ``tune_quantum`` is false, in which case
+    every job advances ``quantum_work`` walker-steps and at least
+    ``min_steps`` steps per round."""
     import workloads as W
     from paper_2608_14544_amd.serve import DeviceBackend, JobSpec, Server, latency_stats
     traj_range = (1e5, 1e8) if full else (1e5, 1e7)
@@ -576,21 +580,21 @@ def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=
     specs = [JobSpec(wl, prec="fp32", name=f"{i}:{wl.model.name}") for i, wl in enumerate(wls)]
     from paper_2608_14544_amd.tune import TuningTable, autotune
     table = autotune(wls, "fp32", table if table is not None else TuningTable())  # untimed; kept if tuned
-    if tune_quantum and "quantum_work" not in table.serving:
+    if tune_quantum:
         k = max(1, n_jobs * 3 // 10)  # the first 30 % of the stream, served once per candidate
 
-        def run_prefix(q):
-            s = Server(DeviceBackend(tuning=table), quantum_steps=quantum, quantum_work=q)
+        def run_prefix(q, ms):
+            s = Server(DeviceBackend(tuning=table), quantum_steps=quantum, quantum_work=q, min_steps=ms)
             return latency_stats(s.run(arrivals[:k], specs[:k]))
         table.tune_quantum(run_prefix)
-        print(f"[bench] serving quantum: {table.quantum_work():.0e} walker-steps per job per round "
-              f"(p99 on the first {k} jobs: " + ", ".join(f"{q:.0e}: {v['p99_s']:.3f} s"
-                                                         for q, v in table.serving_timings.items()) + ")",
+        print(f"[bench] serving quantum: {table.quantum_work():.0e} walker-steps per job per round, at least "
+              f"{table.min_steps()} steps (p99 on the first {k} jobs: " +
+              ", ".join(f"{q:.0e}/{ms}: {v['p99_s']:.3f} s" for (q, ms), v in table.serving_timings.items()) + ")",
               file=sys.stderr, flush=True)
-    if tune_quantum:
         quantum_work = table.quantum_work(quantum_work)
+        min_steps = table.min_steps(min_steps)
     backend = DeviceBackend(tuning=table)
-    srv = Server(backend, quantum_steps=quantum, quantum_work=quantum_work)
+    srv = Server(backend, quantum_steps=quantum, quantum_work=quantum_work, min_steps=min_steps)
     done = []
 
     def progress(r):
@@ -619,9 +623,10 @@ def served_leg(P, torch, n_jobs=200, rate=20.0, quantum=2000, full=False, table=
                "variant": "full" if full else "sub-saturation",
                "offered_walker_steps_per_s": offered,
                "rounds": srv.rounds, "quantum": f"{quantum_work:.0e} walker-steps per job per round, "
-                                                 f"at most {quantum} steps",
-               "quantum_tuning": {f"{q:.0e}": {kk: v.get(kk) for kk in ("p50_s", "p99_s", "walker_steps_per_s")}
-                                  for q, v in table.serving_timings.items()} if tune_quantum else None,
+                                                 f"at least {min_steps} and at most {quantum} steps",
+               "quantum_tuning": {f"{q:.0e} walker-steps, at least {ms} steps":
+                                  {kk: v.get(kk) for kk in ("p50_s", "p99_s", "walker_steps_per_s")}
+                                  for (q, ms), v in table.serving_timings.items()} if tune_quantum else None,
                "host_enqueue_s": backend.host_s, "host_enqueue_s_per_round": backend.host_s / max(srv.rounds, 1),
                "host_enqueue_fraction_of_makespan": backend.host_s / st["makespan_s"] if st.get("makespan_s") else None,
                "memory_budget_GB": srv.budget / 1e9})
@@ -694,6 +699,10 @@ def main():
     ap.add_argument("--served-jobs", type=int, default=200)
     ap.add_argument("--served-quantum-work", type=float, default=2e8,
                     help="walker-steps per resident job per serving round")
+    ap.add_argument("--served-min-steps", type=int, default=1,
+                    help="with --served-no-tune: steps every resident job advances at least per serving round")
+    ap.add_argument("--served-no-tune", action="store_true",
+                    help="serve at --served-quantum-work instead of tuning the quantum on a prefix")
     ap.add_argument("--served-full", action="store_true",
                     help="the served leg uses 1e5-1e8 walkers per random job (as the served_full leg does)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -810,12 +819,14 @@ def main():
         torch.cuda.empty_cache()
     if "served" in legs:
         line["served"] = served_leg(P, torch, args.served_jobs, full=args.served_full, table=table,
-                                    quantum_work=args.served_quantum_work)
+                                    quantum_work=args.served_quantum_work, tune_quantum=not args.served_no_tune,
+                                    min_steps=args.served_min_steps)
         print(f"[bench] served: {line['served']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     if "served_full" in legs and not args.served_full:
         line["served_full"] = served_leg(P, torch, args.served_jobs, full=True, table=table,
-                                         quantum_work=args.served_quantum_work)
+                                         quantum_work=args.served_quantum_work,
+                                         tune_quantum=not args.served_no_tune, min_steps=args.served_min_steps)
         print(f"[bench] served (1e5-1e8 walkers): {line['served_full']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     if "general" in legs:

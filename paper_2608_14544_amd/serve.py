@@ -17,9 +17,17 @@ models and sizes can share a launch).  Between quanta it
 
 A quantum is either a fixed step count per job (``quantum_steps``) or a
 fixed amount of work per job (``quantum_work`` walker-steps, i.e.
-quantum_work / n_traj steps, at least one and at most ``quantum_steps``):
-the second shares the device roughly equally between resident jobs, so a
-small job is not held back by rounds sized for large ones.
+quantum_work / n_traj steps, at least ``min_steps`` and at most
+``quantum_steps``): the second shares the device roughly equally between
+resident jobs, so a small job is not held back by rounds sized for large
+ones.  The floor is there because every round loads and stores each
+resident walker's whole state once (the kernels keep it in registers for
+the length of a call): that round trip costs as much as a few to about 17
+steps of the step arithmetic (per mode, 16 bytes in and out at HBM speed
+against about 10 instructions per step; the electronic part adds more
+arithmetic than state for N > 2), so a job of many walkers advanced one
+or two steps per round would spend most of its device time moving its
+state.
 
 Because a batched launch and any split of the steps into calls leave each
 ensemble's arithmetic unchanged, a job's result is bitwise the one it gets
@@ -214,7 +222,7 @@ class Server:
     def __init__(self, backend=None, memory_budget: Optional[int] = None, max_slots: int = 64,
                  quantum_steps: int = 50, max_backfill_wait: float = 2.0,
                  clock: Callable[[], float] = time.perf_counter, max_in_flight: int = 2,
-                 quantum_work: Optional[float] = None):
+                 quantum_work: Optional[float] = None, min_steps: int = 1):
         self.backend = backend if backend is not None else DeviceBackend()
         if memory_budget is None:
             import torch
@@ -224,6 +232,7 @@ class Server:
         self.max_slots = int(max_slots)
         self.quantum = int(quantum_steps)
         self.quantum_work = None if quantum_work is None else float(quantum_work)
+        self.min_steps = max(1, int(min_steps))
         self.max_backfill_wait = float(max_backfill_wait)
         self.clock = clock
         self.t0 = clock()
@@ -319,7 +328,7 @@ class Server:
     def _steps_per_round(self, spec: JobSpec) -> int:
         if self.quantum_work is None:
             return self.quantum
-        return max(1, min(self.quantum, int(self.quantum_work // max(spec.n_traj, 1))))
+        return max(1, min(self.quantum, max(self.min_steps, int(self.quantum_work // max(spec.n_traj, 1)))))
 
     def _collect(self) -> List[JobResult]:
         done, keep = [], []

@@ -24,10 +24,12 @@ class (the kernel a batch item runs) with one batched call of a synthetic
 ensemble.
 
 3. The serving quantum: walker-steps each resident job advances per
-scheduling round (serve.Server quantum_work).  Short rounds answer small
-jobs sooner, long rounds spend less on per-round launches; timed on a
-prefix of the served stream, the candidate with the lowest p99 latency
-kept.
+scheduling round (serve.Server quantum_work), with a floor in steps
+(serve.Server min_steps).  Short rounds answer small jobs sooner, long
+rounds spend less on per-round launches and on moving each job's state in
+and out of registers (a job of 1e8 walkers at 2e8 walker-steps per round
+would advance two steps per round); timed on a prefix of the served
+stream, the candidate with the lowest p99 latency kept.
 
 None of the three changes a result bit.  ``TuningTable`` keeps the choices
 and their timings and can save and load them as JSON.
@@ -44,7 +46,7 @@ from . import qcl as Q
 Key = Tuple[int, int, int, str]
 VARIANTS = (0, 2, 3)
 WPC_CANDIDATES = (0, 1, 2)
-QUANTUM_CANDIDATES = (5e7, 2e8, 8e8)
+QUANTUM_CANDIDATES = ((5e7, 1), (2e8, 1), (8e8, 1), (2e8, 16), (8e8, 16))  # (quantum_work, min_steps)
 
 
 def budget_variant(mp: int, n_states: int = 3) -> int:
@@ -101,7 +103,7 @@ class TuningTable:
         self.wpc: Dict[tuple, int] = {}
         self.wpc_timings: Dict[tuple, Dict[int, float]] = {}
         self.serving: Dict[str, float] = {}
-        self.serving_timings: Dict[float, dict] = {}
+        self.serving_timings: Dict[tuple, dict] = {}
         if path and os.path.exists(path):
             self.load(path)
 
@@ -120,6 +122,9 @@ class TuningTable:
 
     def quantum_work(self, default: float = 2e8) -> float:
         return float(self.serving.get("quantum_work", default))
+
+    def min_steps(self, default: int = 1) -> int:
+        return int(self.serving.get("min_steps", default))
 
     def save(self, path: str):
         rows = [{"n": k[0], "mp": k[1], "rb": k[2], "prec": k[3], "occupancy": v,
@@ -184,12 +189,17 @@ class TuningTable:
         del ens, part
         return best
 
-    def tune_quantum(self, run_stream, candidates=QUANTUM_CANDIDATES) -> float:
-        """``run_stream(quantum_work)`` serves a stream and returns its
-        latency statistics; keeps the candidate with the lowest p99."""
-        stats = {float(q): run_stream(float(q)) for q in candidates}
-        best = min(stats, key=lambda q: (stats[q].get("p99_s") or float("inf")))
-        self.serving["quantum_work"] = best
+    def tune_quantum(self, run_stream, candidates=QUANTUM_CANDIDATES) -> tuple:
+        """``run_stream(quantum_work, min_steps)`` serves a stream and
+        returns its latency statistics; keeps the candidate pair with the
+        lowest p99."""
+        stats = {(float(q), int(m)): run_stream(float(q), int(m)) for q, m in candidates}
+        def p99(c):
+            v = stats[c].get("p99_s")
+            return float("inf") if v is None else v
+        best = min(stats, key=p99)
+        self.serving["quantum_work"] = best[0]
+        self.serving["min_steps"] = float(best[1])
         self.serving_timings = stats
         return best
 

@@ -139,10 +139,24 @@ def test_tuning_classes_and_table_roundtrip(tmp_path):
     t.wpc[(4, 64, 1, 0, 0, "fp32")] = 2
     t.wpc[(2, 3, 0, 0, 0, "fp32")] = 0
     t.serving["quantum_work"] = 8e8
+    t.serving["min_steps"] = 16.0
     path = str(tmp_path / "tuning.json")
     t.save(path)
     u = TuningTable(path)
-    assert u.choice == t.choice and u.wpc == t.wpc and u.quantum_work() == 8e8
+    assert u.choice == t.choice and u.wpc == t.wpc and u.quantum_work() == 8e8 and u.min_steps() == 16
+
+
+def test_quantum_tuning_keeps_the_lowest_p99_pair():
+    from paper_2608_14544_amd.tune import QUANTUM_CANDIDATES, TuningTable
+    t = TuningTable()
+    seen = []
+
+    def run(q, ms):
+        seen.append((q, ms))
+        return {"p99_s": abs(q - 2e8) / 1e8 + (0.0 if ms == 16 else 0.5)}
+    assert t.tune_quantum(run) == (2e8, 16)
+    assert seen == [(float(q), int(m)) for q, m in QUANTUM_CANDIDATES]
+    assert t.quantum_work() == 2e8 and t.min_steps() == 16
 
 
 def test_failing_jobs_are_answered_not_fatal():
@@ -172,7 +186,7 @@ def test_failing_jobs_are_answered_not_fatal():
 def test_work_based_quanta():
     clock = Clock()
     be = SimBackend(clock, bytes_per_walker=1, walker_steps_per_s=1e6, sleep_until=clock.until)
-    srv = Server(be, memory_budget=10 ** 9, quantum_steps=1000, quantum_work=10_000, clock=clock)
+    srv = Server(be, memory_budget=10 ** 9, quantum_steps=1000, quantum_work=10_000, clock=clock, min_steps=1)
     srv.submit(spec("small", 100, 300))     # 100 steps per round: done in 3 rounds
     srv.submit(spec("large", 10_000, 20))   # 1 step per round
     drive(srv, clock)
@@ -183,3 +197,21 @@ def test_work_based_quanta():
     assert steps["small"] == [100, 100, 100] and steps["large"] == [1] * 20
     res = {r.name: r for r in srv.results}
     assert res["small"].finished < res["large"].finished
+
+
+def test_work_based_quanta_step_floor():
+    """A job whose share of a round is fewer than min_steps steps still
+    advances min_steps (its state round trip is amortised), and never past
+    its end or the per-round cap."""
+    clock = Clock()
+    be = SimBackend(clock, bytes_per_walker=1, walker_steps_per_s=1e6, sleep_until=clock.until)
+    srv = Server(be, memory_budget=10 ** 9, quantum_steps=12, quantum_work=10_000, clock=clock, min_steps=8)
+    srv.submit(spec("small", 100, 30))      # 100 steps by work, capped at 12: 12, 12, 6
+    srv.submit(spec("large", 10_000, 20))   # 1 step by work, floored at 8: 8, 8, 4
+    drive(srv, clock)
+    steps = {}
+    for rnd in be.log:
+        for name, n in rnd:
+            steps.setdefault(name, []).append(n)
+    assert steps["small"] == [12, 12, 6] and steps["large"] == [8, 8, 4]
+    assert all(not r.error for r in srv.results) and srv.used == 0
