@@ -93,7 +93,7 @@ inline int64_t persistent_grid(int64_t total_tiles, int cus, int per_cu, int wpc
 
 inline int padded_modes(int m)
 {
-    return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 128;
+    return m <= 4 ? 4 : m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 128;
 }
 
 // rank bucket: 1, N or T = N(N+1)/2 (for more than 4 states only 1 or T)

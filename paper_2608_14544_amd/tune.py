@@ -60,7 +60,7 @@ def budget_variant(mp: int, n_states: int = 3) -> int:
 
 def padded_modes(m: int) -> int:
     """Mode count the general kernels are specialised on."""
-    for mp in (8, 16, 32, 64):
+    for mp in (4, 8, 16, 32, 64):
         if m <= mp:
             return mp
     return 128

@@ -123,7 +123,8 @@ def test_latency_stats():
 
 def test_tuning_classes_and_table_roundtrip(tmp_path):
     from paper_2608_14544_amd.tune import TuningTable, kernel_class, padded_modes, rank_bucket
-    assert padded_modes(1) == 8 and padded_modes(9) == 16 and padded_modes(33) == 64 and padded_modes(100) == 128
+    assert padded_modes(1) == 4 and padded_modes(5) == 8 and padded_modes(9) == 16 and padded_modes(33) == 64
+    assert padded_modes(100) == 128
     assert rank_bucket(0, 3) == 1 and rank_bucket(2, 3) == 3 and rank_bucket(4, 3) == 6
     assert kernel_class(2, 8, 3, "fp32") is None           # closed-form two-state kernels
     assert kernel_class(3, 40, 1, "fp32") == (3, 64, 1, "fp32")  # two-wave budget at 64 modes
