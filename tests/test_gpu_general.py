@@ -72,6 +72,37 @@ def test_general_determinism_and_slicing(P):
         assert np.array_equal(out1, out2), prec
 
 
+def _with_spectators(wl, n_extra):
+    """The same model with ``n_extra`` uncoupled harmonic modes appended
+    (K_j = 0, at rest at the origin on average)."""
+    m = wl.model
+    N = m.v0.shape[0]
+    lvc = W.LVCModel(name=m.name + "_spectators", mass=np.concatenate([m.mass, np.ones(n_extra)]),
+                     omega=np.concatenate([m.omega, np.full(n_extra, float(m.omega.min()))]), v0=m.v0,
+                     k=np.concatenate([m.k, np.zeros((n_extra, N, N))]))
+    init = W.InitSpec(kT=wl.init.kT, q0=np.concatenate([wl.init.q0, np.zeros(n_extra)]), state=wl.init.state)
+    return W.Workload(lvc, init, wl.run)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n_states", [3, 4])
+def test_four_mode_build_equals_eight_mode_build(P, prec, n_states):
+    """A 3-mode model runs the four-mode build; the same model with two
+    uncoupled spectator modes runs the eight-mode build.  The spectators
+    add exact zeros to every coupling coordinate and draw their own random
+    numbers, so both builds give the same bits for the elements, weights,
+    phases, frames and flags, the three coupled modes and every bin."""
+    wl = W.random_lvc(40 + n_states, n_states=n_states, n_modes=3, n_traj=3000, n_steps=80, cadence=10)
+    ws = _with_spectators(wl, 2)
+    assert P.Model(wl.model).n_modes == 3 and P.Model(ws.model).n_modes == 5
+    out_a, st_a, _, _ = gpu_run(P, wl, prec=prec)
+    out_b, st_b, _, _ = gpu_run(P, ws, prec=prec)
+    for k in ("a", "b", "w", "phase", "U", "flags"):
+        assert np.array_equal(st_a[k], st_b[k]), (prec, k)
+    assert np.array_equal(st_a["q"], st_b["q"][:, :3]) and np.array_equal(st_a["p"], st_b["p"][:, :3]), prec
+    assert np.array_equal(out_a, out_b), prec
+
+
 def _crossing_model(coupling=5e-5):
     """Three states whose diagonal energies cross as mode 0 moves, with a
     weak coupling between states 0 and 1: the adiabatic gap of that pair
