@@ -243,14 +243,20 @@ def cpu_baseline(wl, target_s: float):
 
 
 def _oracle_other_legs():
-    """The oracle beside two further legs, on bounded samples (a few seconds
-    each): the bilinear model's propagation (65536 walkers x 200 steps) and
-    fixed-budget resampling (pure Python, 1e6 walkers with heavy-tailed
-    signed weights)."""
+    """The oracle on the other configurations and beside two further legs,
+    each bounded to a few seconds: the one-mode spin-boson run at its full
+    size (1e4 walkers x 200 steps), the 3-mode Ohmic spin-boson run at kT
+    0.2 on 65536 of its 1e6 walkers (all 2000 steps), the bilinear model's
+    propagation (65536 walkers x 200 steps) and fixed-budget resampling
+    (pure Python, 1e6 walkers with heavy-tailed signed weights)."""
     import numpy as np
     import oracle.core as oc
     import oracle.resample as orr
     import workloads as W
+    s1 = W.spin_boson_1mode()
+    r1, dt1 = _oracle_rate(s1, s1.run.n_traj)
+    so = W.spin_boson_ohmic(kT=0.2)
+    ro, dto = _oracle_rate(so, 65536)
     bw = W.pyrazine_bilinear(n_traj=0, n_steps=200, cadence=10)
     rb, dtb = _oracle_rate(bw, 65536)
     T = 1_000_000
@@ -263,7 +269,13 @@ def _oracle_other_legs():
     t0 = time.perf_counter()
     orr.resample(st, 21)
     dtr = time.perf_counter() - t0
-    return {"pyrazine_bilinear": {"value": rb, "unit": "trajectory-steps/s", "cores": oc.num_threads(),
+    return {"spin_boson_1mode_full": {"value": r1, "unit": "trajectory-steps/s", "cores": oc.num_threads(),
+                                      "sample": f"{s1.run.n_traj} walkers x {s1.run.n_steps} steps (the whole "
+                                                f"run), {dt1:.3f} s"},
+            "spin_boson_ohmic_kT0.2": {"value": ro, "unit": "trajectory-steps/s", "cores": oc.num_threads(),
+                                       "sample": f"65536 of {so.run.n_traj} walkers x {so.run.n_steps} steps, "
+                                                 f"{dto:.2f} s"},
+            "pyrazine_bilinear": {"value": rb, "unit": "trajectory-steps/s", "cores": oc.num_threads(),
                                   "sample": f"65536 walkers x 200 steps, {dtb:.2f} s"},
             "resample": {"value": T / dtr, "unit": "walkers/s", "cores": 1,
                          "sample": f"{T} walkers (2 states, 3 modes), {dtr:.2f} s, Python integers"}}

@@ -38,7 +38,7 @@ def test_committed_counters_match_the_current_kernel_sources():
 def test_oracle_beside_the_other_legs():
     import bench
     legs = bench._oracle_other_legs()
-    assert set(legs) == {"pyrazine_bilinear", "resample"}
+    assert set(legs) == {"spin_boson_1mode_full", "spin_boson_ohmic_kT0.2", "pyrazine_bilinear", "resample"}
     for v in legs.values():
         assert v["value"] > 0 and v["cores"] >= 1 and v["sample"]
 
