@@ -77,22 +77,27 @@ def _with_spectators(wl, n_extra):
     (K_j = 0, at rest at the origin on average)."""
     m = wl.model
     N = m.v0.shape[0]
+    poly = None if m.poly is None else np.concatenate([m.poly, np.zeros((n_extra,) + m.poly.shape[1:])])
     lvc = W.LVCModel(name=m.name + "_spectators", mass=np.concatenate([m.mass, np.ones(n_extra)]),
                      omega=np.concatenate([m.omega, np.full(n_extra, float(m.omega.min()))]), v0=m.v0,
-                     k=np.concatenate([m.k, np.zeros((n_extra, N, N))]))
+                     k=np.concatenate([m.k, np.zeros((n_extra, N, N))]), hbar=m.hbar, poly=poly)
     init = W.InitSpec(kT=wl.init.kT, q0=np.concatenate([wl.init.q0, np.zeros(n_extra)]), state=wl.init.state)
     return W.Workload(lvc, init, wl.run)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("n_states", [3, 4])
-def test_four_mode_build_equals_eight_mode_build(P, prec, n_states):
+@pytest.mark.parametrize("kind", ["lvc3", "lvc4", "poly3"])
+def test_four_mode_build_equals_eight_mode_build(P, prec, kind):
     """A 3-mode model runs the four-mode build; the same model with two
     uncoupled spectator modes runs the eight-mode build.  The spectators
     add exact zeros to every coupling coordinate and draw their own random
     numbers, so both builds give the same bits for the elements, weights,
     phases, frames and flags, the three coupled modes and every bin."""
-    wl = W.random_lvc(40 + n_states, n_states=n_states, n_modes=3, n_traj=3000, n_steps=80, cadence=10)
+    if kind == "poly3":
+        wl = W.random_poly(44, n_states=3, n_modes=3, degree=3, n_traj=3000, n_steps=80, cadence=10)
+    else:
+        n_states = int(kind[-1])
+        wl = W.random_lvc(40 + n_states, n_states=n_states, n_modes=3, n_traj=3000, n_steps=80, cadence=10)
     ws = _with_spectators(wl, 2)
     assert P.Model(wl.model).n_modes == 3 and P.Model(ws.model).n_modes == 5
     out_a, st_a, _, _ = gpu_run(P, wl, prec=prec)
