@@ -40,15 +40,17 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
 
 // (2 floor(x / 2^9) + 1) / 2^24: a uniform in (0,1) that is exact in both
 // binary32 and binary64, so both precisions see the same threshold value.
-// Formed as floor(x / 2^9) 2^-23 + 2^-24 in one fused multiply-add, exact
-// because the result has at most 24 significant bits.
+// The top 23 bits of x become the mantissa of 1 + floor(x / 2^9) 2^-23 (one
+// funnel shift of the exponent bits 0x7F and x by 9, v_alignbit_b32);
+// subtracting 1 - 2^-24 leaves (2 floor(x / 2^9) + 1) 2^-24, which has at
+// most 24 significant bits, so the subtraction is exact.
 __device__ __forceinline__ float u24f(uint32_t x)
 {
-    return __builtin_fmaf((float)(x >> 9), 0x1p-23f, 0x1p-24f);
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x, 9u)) - 0x1.fffffep-1f;
 }
 __device__ __forceinline__ double u24d(uint32_t x)
 {
-    return __builtin_fma((double)(x >> 9), 0x1p-23, 0x1p-24);
+    return (double)u24f(x);  // exact: the value has 24 significant bits
 }
 
 // 52-bit uniform in (0,1): k = hi * 2^20 + floor(lo / 2^12), (2k + 1) / 2^53.
