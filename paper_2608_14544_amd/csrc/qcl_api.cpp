@@ -249,8 +249,11 @@ struct BatchPlan {
 // the call stays ordered on the caller's stream.  Created on a device's
 // first multi-class call (default priority) and kept until the process
 // ends; the mutex keeps the fork/join sequences of concurrent host threads
-// apart.
-constexpr int kSideStreams = 4;
+// apart.  HIP spreads a process's streams over a few hardware queues (four
+// by default) in turn, and the caller's stream holds one of them: with
+// three side streams each has a queue of its own (a fourth shared one with
+// the third, and the classes on those two ran one after the other).
+constexpr int kSideStreams = 3;
 struct Fan {
     bool ready = false;
     hipStream_t s[kSideStreams];
@@ -321,9 +324,17 @@ qcl_status plan_batch(const qcl_batch_item *items, int32_t n_items, BatchPlan &p
                 return fail(QCL_ERR_UNSUPPORTED, "item %d: no batched kernel for this model", i);
         }
         c->order.push_back(i);
-        // per-step work grows with the mode count and (for the Jacobi
-        // solver) with N^3; the weight only orders tiles, so it is rough
-        const double per_step = m.fast2 ? 40.0 + 30.0 * m.m : 60.0 * m.n * m.n * m.n + 12.0 * m.n * m.n * m.m;
+        // per-step work in vector instructions, from the compiled kernels:
+        // about 10 per padded mode (3 times that with higher powers) plus
+        // the electronic part (solve, transition, forces), about 300, 700
+        // and 1250 for 2, 3 and 4 states and growing as N^3 beyond; the
+        // closed-form two-state kernels about 100 plus 25 per mode.  It
+        // orders tiles and spreads classes over the side streams, so it
+        // only needs to be roughly proportional to the time
+        const double per_step =
+            m.fast2 ? 100.0 + 25.0 * m.m * (m.degree > 1 ? 2 : 1)
+                    : 10.0 * qcl::padded_modes(m.m) * (m.degree > 1 ? 3 : 1) +
+                          (m.n <= 2 ? 300.0 : m.n == 3 ? 700.0 : 1250.0 * (m.n * m.n * m.n) / 64.0);
         weight[i] = per_step * it.prop.n_steps;
         const int64_t t = qcl::n_tiles(it.ens->n_traj);
         c->total_tiles += t;
@@ -900,8 +911,10 @@ qcl_status propagate_batch_in(const qcl_batch_item *items, int32_t n_items, void
             if (e == hipSuccess)
                 e = launch_class(c, s);
     } else if (plan.classes.size() > 1) {
-        // heaviest class first, one side stream per class in turn; a class
-        // whose last tiles leave CUs idle is overlapped by the next class
+        // heaviest class first, each on the side stream with the least
+        // estimated work so far (longest-processing-time order), so the
+        // streams finish close together; a class whose last tiles leave
+        // CUs idle is overlapped by the classes on the other streams
         std::lock_guard<std::mutex> lock(g_fan_mutex);
         Fan *f = nullptr;
         if ((e = device_fan(f)) != hipSuccess)
@@ -912,8 +925,14 @@ qcl_status propagate_batch_in(const qcl_batch_item *items, int32_t n_items, void
         for (int k = 0; k < used; ++k)
             if ((e = hipStreamWaitEvent(f->s[k], f->fork, 0)) != hipSuccess)
                 return device_fail(e, "hipStreamWaitEvent");
-        for (size_t i = 0; i < plan.classes.size() && e == hipSuccess; ++i)
-            e = launch_class(plan.classes[i], f->s[i % used]);
+        double load[kSideStreams] = {};
+        for (size_t i = 0; i < plan.classes.size() && e == hipSuccess; ++i) {
+            int k = 0;
+            for (int j = 1; j < used; ++j)
+                k = load[j] < load[k] ? j : k;
+            load[k] += plan.classes[i].cost;
+            e = launch_class(plan.classes[i], f->s[k]);
+        }
         // join whatever was launched back into the caller's stream
         for (int k = 0; k < used; ++k) {
             hipError_t ej = hipEventRecord(f->join[k], f->s[k]);
